@@ -1,0 +1,1172 @@
+/*
+ * CPU oracle for the enhanced Kogbetliantz SVD of order two
+ * (V. Novakovic, "Arithmetical enhancements of the Kogbetliantz method for
+ * the SVD of order two", arXiv 2407.13116), and for the batched two-sided
+ * Kogbetliantz sweep that calls it.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU path is checked against.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header or table with the GPU library, and the GPU library
+ * never loads it.
+ *
+ * Build: g++ -O2 -std=c++17 -ffp-contract=off -fno-fast-math -fopenmp -fPIC
+ *        -shared (no contraction: every fused multiply-add below is an
+ *        explicit std::fma call, every other operation is one IEEE rounding).
+ *
+ * Organisation (each part cites the passage of the paper it follows):
+ *   1. exact, integer-based, correctly rounded hypot            (Sect. 2)
+ *   2. (e,f) exponent-"mantissa" pairs and their operations      (Sect. 2)
+ *   3. double-word arithmetic for the wider datatype T of eq. (EXT), f64 only
+ *   4. the 2x2 SVD: classification + prescaling (Sect. 3.1), the simple
+ *      classes (Sect. 3.1), the URV factorisation (Sect. 3.2), the SVD of
+ *      the triangular factor (Sect. 3.3.1, Algorithms tf/tp) and the
+ *      assembly with the left-vector heuristic (Sect. 3.3.2)
+ *   5. the Kogbetliantz sweep over an n x n matrix (Sect. 1, eq. (SVD))
+ *   6. extern "C" batch drivers (OpenMP) for the test-suite
+ */
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+/* ------------------------------------------------------------------------ */
+/* Floating-point format constants (Sect. 2: p, eps = 2^-p, e_mu, e_nu).      */
+/* ------------------------------------------------------------------------ */
+template <class R> struct Fmt;
+template <> struct Fmt<double> {
+  static constexpr int p = 53;
+  static constexpr int e_mu = -1022;
+  static constexpr int e_nu = 1023;
+  static double mu() { return DBL_MIN; }
+  static double nu() { return DBL_MAX; }
+  static double eps() { return 0x1p-53; }
+};
+template <> struct Fmt<float> {
+  static constexpr int p = 24;
+  static constexpr int e_mu = -126;
+  static constexpr int e_nu = 127;
+  static float mu() { return FLT_MIN; }
+  static float nu() { return FLT_MAX; }
+  static float eps() { return 0x1p-24f; }
+};
+
+/* ------------------------------------------------------------------------ */
+/* 1. Correctly rounded hypot (Sect. 2: hypot(a,b) = fl(sqrt(a^2+b^2)),      */
+/*    assumed correctly rounded).  Construction: a candidate from long       */
+/*    double, then exact integer comparisons of a^2+b^2 against the squares  */
+/*    of the rounding midpoints around the candidate, moving the candidate   */
+/*    until it is the round-to-nearest-even value.  Obviously correct; slow.  */
+/* ------------------------------------------------------------------------ */
+struct U256 {
+  uint64_t w[4];
+};
+
+static U256 u_from128(unsigned __int128 v) {
+  U256 r;
+  r.w[0] = (uint64_t)v;
+  r.w[1] = (uint64_t)(v >> 64);
+  r.w[2] = 0;
+  r.w[3] = 0;
+  return r;
+}
+
+static U256 u_shl(U256 a, int s) {
+  U256 r = {{0, 0, 0, 0}};
+  int limbs = s / 64, bits = s % 64;
+  for (int i = 3; i >= 0; --i) {
+    int src = i - limbs;
+    if (src < 0) continue;
+    uint64_t v = a.w[src] << bits;
+    if (bits && src - 1 >= 0) v |= a.w[src - 1] >> (64 - bits);
+    r.w[i] = v;
+  }
+  return r;
+}
+
+static U256 u_add(U256 a, U256 b) {
+  U256 r;
+  unsigned __int128 c = 0;
+  for (int i = 0; i < 4; ++i) {
+    c += (unsigned __int128)a.w[i] + b.w[i];
+    r.w[i] = (uint64_t)c;
+    c >>= 64;
+  }
+  return r;
+}
+
+static int u_cmp(U256 a, U256 b) {
+  for (int i = 3; i >= 0; --i) {
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+  }
+  return 0;
+}
+
+/* Exact dyadic m * 2^k of a non-negative double (floats convert exactly). */
+struct Dy {
+  uint64_t m;
+  int k;
+};
+
+static Dy dy_of(double x) {
+  Dy d;
+  if (x == 0) {
+    d.m = 0;
+    d.k = 0;
+    return d;
+  }
+  int e;
+  double f = std::frexp(x, &e); /* x = f 2^e, f in [1/2, 1) */
+  d.m = (uint64_t)std::ldexp(f, 53);
+  d.k = e - 53;
+  return d;
+}
+
+/* sign(a^2 + b^2 - ((lo + hi)/2)^2), exactly.  `hi` may stand for 2^(e_nu+1)
+   (the value "just above the largest finite", used for the overflow
+   midpoint), passed as hi_pow2 >= 0 with hi ignored. */
+static int cmp_sumsq_mid(double a, double b, double lo, double hi, int hi_pow2) {
+  Dy A = dy_of(a), B = dy_of(b), L = dy_of(lo), H;
+  if (hi_pow2 >= 0) {
+    H.m = 1;
+    H.k = hi_pow2;
+  } else {
+    H = dy_of(hi);
+  }
+  /* midpoint = (L + H)/2 = M 2^(kq-1) */
+  int kq = std::min(L.m ? L.k : H.k, H.k);
+  unsigned __int128 M = 0;
+  if (L.m) M += (unsigned __int128)L.m << (L.k - kq);
+  M += (unsigned __int128)H.m << (H.k - kq);
+  /* exponents of the three squares */
+  int ea = 2 * A.k, eb = 2 * B.k, em = 2 * (kq - 1);
+  int E = em;
+  if (A.m) E = std::min(E, ea);
+  if (B.m) E = std::min(E, eb);
+  U256 lhs = {{0, 0, 0, 0}};
+  if (A.m) lhs = u_add(lhs, u_shl(u_from128((unsigned __int128)A.m * A.m), ea - E));
+  if (B.m) lhs = u_add(lhs, u_shl(u_from128((unsigned __int128)B.m * B.m), eb - E));
+  /* M < 2^56, M^2 < 2^112: square in two 128-bit halves */
+  uint64_t Mlo = (uint64_t)M, Mhi = (uint64_t)(M >> 64);
+  U256 m2 = u_from128((unsigned __int128)Mlo * Mlo);
+  if (Mhi) {
+    U256 cross = u_shl(u_from128((unsigned __int128)Mlo * Mhi), 65);
+    U256 top = u_shl(u_from128((unsigned __int128)Mhi * Mhi), 128);
+    m2 = u_add(u_add(m2, cross), top);
+  }
+  U256 rhs = u_shl(m2, em - E);
+  return u_cmp(lhs, rhs);
+}
+
+template <class R> static bool is_even(R x);
+template <> bool is_even<double>(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, 8);
+  return (u & 1) == 0;
+}
+template <> bool is_even<float>(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  return (u & 1) == 0;
+}
+
+template <class R>
+static R cr_hypot(R x, R y) {
+  R a = std::fabs(x), b = std::fabs(y);
+  if (a < b) std::swap(a, b);
+  if (std::isinf(a)) return a;
+  if (std::isnan(a) || std::isnan(b)) return a + b;
+  if (b == 0) return a;
+  int ea, eb;
+  std::frexp((double)a, &ea);
+  std::frexp((double)b, &eb);
+  /* b/a < 2^(eb-ea+1), so sqrt(a^2+b^2) - a < a 2^(2(eb-ea)+1) < half an
+     ulp of a once ea - eb > 30: the result is a. */
+  if (ea - eb > 30) return a;
+  long double la = a, lb = b;
+  R r = (R)std::sqrt(la * la + lb * lb);
+  const R inf = (R)INFINITY;
+  const int top = Fmt<R>::e_nu + 1; /* 2^top is the overflow "neighbour" */
+  for (;;) {
+    if (std::isinf(r)) r = Fmt<R>::nu();
+    R up = std::nextafter(r, inf);
+    int c = std::isinf(up) ? cmp_sumsq_mid(a, b, r, 0, top) : cmp_sumsq_mid(a, b, r, up, -1);
+    if (c > 0) {
+      if (std::isinf(up)) return up;
+      r = up;
+      continue;
+    }
+    if (c == 0) {
+      if (std::isinf(up)) return up; /* the largest finite is odd */
+      return is_even(r) ? r : up;
+    }
+    R dn = std::nextafter(r, (R)0);
+    c = cmp_sumsq_mid(a, b, dn, r, -1);
+    if (c < 0) {
+      r = dn;
+      continue;
+    }
+    if (c == 0) return is_even(dn) ? dn : r;
+    return r;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2. (e,f) pairs (Sect. 2): w = 2^e f with 1 <= |f| < 2, zero is (0,0).     */
+/* ------------------------------------------------------------------------ */
+template <class R> struct EF {
+  int e;
+  R f;
+};
+
+/* N(x) = (e_x, f_x), e_x = floor(lg|x|) (also for subnormal x). */
+template <class R> static EF<R> ef_of(R x) {
+  EF<R> r;
+  if (x == 0) {
+    r.e = 0;
+    r.f = 0;
+    return r;
+  }
+  r.e = std::ilogb(x);
+  r.f = std::scalbn(x, -r.e);
+  return r;
+}
+
+/* fl(w) = scalbn(f_w, e_w): a single rounding, may under- or overflow. */
+template <class R> static R ef_fl(EF<R> x) { return std::scalbn(x.f, x.e); }
+
+/* 2^s (.) x   (eq. unary) */
+template <class R> static EF<R> ef_pow2(int s, EF<R> x) {
+  if (x.f != 0) x.e += s;
+  return x;
+}
+
+/* x (.) y = (e_x + e_y + e_z, f_z), z = fl(f_x f_y)   (eq. binary) */
+template <class R> static EF<R> ef_mul(EF<R> x, EF<R> y) {
+  R z = x.f * y.f;
+  EF<R> n = ef_of(z);
+  if (n.f != 0) n.e += x.e + y.e;
+  return n;
+}
+
+/* x (/) y = (e_x - e_y + e_z, f_z), z = fl(f_x / f_y)   (eq. binary) */
+template <class R> static EF<R> ef_div(EF<R> x, EF<R> y) {
+  R z = x.f / y.f;
+  EF<R> n = ef_of(z);
+  if (n.f != 0) n.e += x.e - y.e;
+  return n;
+}
+
+/* x (+) y for positive finite x, y (eq. plus): overflow-avoiding addition. */
+template <class R> static EF<R> ef_plus(R x, R y) {
+  R z = x + y;
+  if (z <= Fmt<R>::nu()) return ef_of(z);
+  z = (x * (R)0.5) + (y * (R)0.5);
+  EF<R> n = ef_of(z);
+  n.e += 1;
+  return n;
+}
+
+/* x (-) y for positive finite x, y (eq. minus, Lemma minus):
+   underflow-avoiding subtraction; x = y gives (0,0). */
+template <class R> static EF<R> ef_minus(R x, R y) {
+  EF<R> zero = {0, (R)0};
+  if (x == y) return zero;
+  R z = x - y;
+  if (std::fabs(z) >= Fmt<R>::mu()) return ef_of(z);
+  int c = Fmt<R>::e_mu + Fmt<R>::p - 1 - std::min(std::ilogb(x), std::ilogb(y));
+  z = std::scalbn(x, c) - std::scalbn(y, c);
+  EF<R> n = ef_of(z);
+  n.e -= c;
+  return n;
+}
+
+template <class R> static int sgn3(R f) { return (f > 0) - (f < 0); }
+
+/* x < y in the sense of the represented values (eq. prec). */
+template <class R> static bool ef_prec(EF<R> x, EF<R> y) {
+  int sx = sgn3(x.f), sy = sgn3(y.f);
+  if (sx < sy) return true;
+  if (sx != sy) return false;
+  return (x.e < y.e) || ((x.e == y.e) && (x.f < y.f));
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3. Double-word arithmetic (Joldes, Muller, Popescu, "Tight and rigorous   */
+/*    error bounds for basic building blocks of double-word arithmetic",     */
+/*    ACM TOMS 44(2), 2017): the wider datatype T of eq. (EXT) for binary64.  */
+/* ------------------------------------------------------------------------ */
+static void two_sum(double a, double b, double &s, double &t) {
+  s = a + b;
+  double ap = s - b;
+  double bp = s - ap;
+  double da = a - ap;
+  double db = b - bp;
+  t = da + db;
+}
+
+static void fast_two_sum(double a, double b, double &s, double &t) {
+  s = a + b;
+  double z = s - a;
+  t = b - z;
+}
+
+static void two_prod(double a, double b, double &p, double &e) {
+  p = a * b;
+  e = std::fma(a, b, -p);
+}
+
+/* AccurateDWPlusDW (Algorithm 6 of the cited paper). */
+static void dw_plus_dw(double xh, double xl, double yh, double yl, double &zh, double &zl) {
+  double sh, sl, th, tl, vh, vl;
+  two_sum(xh, yh, sh, sl);
+  two_sum(xl, yl, th, tl);
+  double c = sl + th;
+  fast_two_sum(sh, c, vh, vl);
+  double w = tl + vl;
+  fast_two_sum(vh, w, zh, zl);
+}
+
+/* DWDivFP3 (Algorithm 15 of the cited paper). */
+static void dw_div_fp(double xh, double xl, double y, double &zh, double &zl) {
+  double th = xh / y;
+  double ph, pl;
+  two_prod(th, y, ph, pl);
+  double dh = xh - ph; /* exact */
+  double dl = xl - pl;
+  double d = dh + dl;
+  double tl = d / y;
+  fast_two_sum(th, tl, zh, zl);
+}
+
+/* fl(FL(FL(x1 y1 +- x2 y2) / d)) of eq. (EXT), with T = double-word for
+   binary64.  Each product is formed exactly from the factors' normalised
+   mantissas, both are scaled by the larger product's exponent (so the sum
+   cannot overflow and the smaller addend only loses bits far below 2^-106
+   of the larger), summed, divided by d's mantissa, and the leading word
+   scaled back by one rounding. */
+static double ext_f64(double x1, double y1, double x2, double y2, bool minus, double d) {
+  int a1 = std::ilogb(x1), b1 = std::ilogb(y1), a2 = std::ilogb(x2), b2 = std::ilogb(y2);
+  int k1 = a1 + b1, k2 = a2 + b2, K = std::max(k1, k2);
+  double p1h, p1l, p2h, p2l;
+  two_prod(std::scalbn(x1, -a1), std::scalbn(y1, -b1), p1h, p1l);
+  two_prod(std::scalbn(x2, -a2), std::scalbn(y2, -b2), p2h, p2l);
+  p1h = std::scalbn(p1h, k1 - K);
+  p1l = std::scalbn(p1l, k1 - K);
+  p2h = std::scalbn(p2h, k2 - K);
+  p2l = std::scalbn(p2l, k2 - K);
+  if (minus) {
+    p2h = -p2h;
+    p2l = -p2l;
+  }
+  double xh, xl;
+  dw_plus_dw(p1h, p1l, p2h, p2l, xh, xl);
+  if (xh == 0) return 0.0;
+  int ed = std::ilogb(d);
+  double qh, ql;
+  dw_div_fp(xh, xl, std::scalbn(d, -ed), qh, ql);
+  return std::scalbn(qh, K - ed);
+}
+
+/* Same for binary32, with T = binary64 exactly as in the paper: both
+   products are exact in binary64, the sum and the quotient are rounded in
+   binary64 (FL), and the quotient is rounded to binary32 (fl). */
+static float ext_f32(float x1, float y1, float x2, float y2, bool minus, float d) {
+  double p1 = (double)x1 * (double)y1;
+  double p2 = (double)x2 * (double)y2;
+  double s = minus ? (p1 - p2) : (p1 + p2);
+  double q = s / (double)d;
+  return (float)q;
+}
+
+template <class R> static R ext(R x1, R y1, R x2, R y2, bool minus, R d);
+template <> double ext<double>(double x1, double y1, double x2, double y2, bool minus, double d) {
+  return ext_f64(x1, y1, x2, y2, minus, d);
+}
+template <> float ext<float>(float x1, float y1, float x2, float y2, bool minus, float d) {
+  return ext_f32(x1, y1, x2, y2, minus, d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 4. The SVD of order two.                                                 */
+/* ------------------------------------------------------------------------ */
+template <class R> struct M2 {
+  R a[2][2]; /* a[row][col] */
+};
+
+template <class R> static M2<R> m_id() { return M2<R>{{{1, 0}, {0, 1}}}; }
+template <class R> static M2<R> m_x() { return M2<R>{{{0, 1}, {1, 0}}}; }
+template <class R> static M2<R> m_diag(R d1, R d2) { return M2<R>{{{d1, 0}, {0, d2}}}; }
+/* plane rotation [c -s; s c] (eq. tfp) */
+template <class R> static M2<R> m_rot(R c, R s) { return M2<R>{{{c, -s}, {s, c}}}; }
+template <class R> static M2<R> m_t(const M2<R> &A) {
+  return M2<R>{{{A.a[0][0], A.a[1][0]}, {A.a[0][1], A.a[1][1]}}};
+}
+/* Plain matrix product.  Every product formed below has a signed
+   permutation as one factor, so every entry is a single non-zero term and
+   the product is exact. */
+template <class R> static M2<R> m_mul(const M2<R> &A, const M2<R> &B) {
+  M2<R> C;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) C.a[i][j] = A.a[i][0] * B.a[0][j] + A.a[i][1] * B.a[1][j];
+  return C;
+}
+
+/* sign as used for the sign matrices: sgn(x) = -1 if x < 0, else +1 (zeros
+   of either sign give +1). */
+template <class R> static R sgn(R x) { return x < 0 ? (R)-1 : (R)1; }
+
+/* type t = [g11!=0] + 2[g21!=0] + 4[g12!=0] + 8[g22!=0], read off the
+   pictures of eq. (ts). */
+template <class R> static int type_of(const M2<R> &G) {
+  return (G.a[0][0] != 0) | ((G.a[1][0] != 0) << 1) | ((G.a[0][1] != 0) << 2) |
+         ((G.a[1][1] != 0) << 3);
+}
+
+enum Cls { Z9 = 0, Z3 = 1, Z5 = 2, Z13 = 3, Z15 = 4 };
+
+/* permutational classes of eq. (ts) */
+static Cls cls_of(int t) {
+  switch (t) {
+    case 3:
+    case 12:
+      return Z3;
+    case 5:
+    case 10:
+      return Z5;
+    case 7:
+    case 11:
+    case 13:
+    case 14:
+      return Z13;
+    case 15:
+      return Z15;
+    default:
+      return Z9; /* 0, 1, 2, 4, 6, 8, 9 */
+  }
+}
+
+/* scale type of eq. (ts) */
+static int scale_type(Cls c) {
+  switch (c) {
+    case Z9:
+      return 0;
+    case Z15:
+      return 2;
+    default:
+      return 1;
+  }
+}
+
+/* Result of the SVD of a (prescaled) matrix: G' = U diag(s1, s2) V^T. */
+template <class R> struct Part {
+  M2<R> U, V;
+  EF<R> s1, s2;
+};
+
+/* Class t ~ 9 (Sect. 3.1): permute into the 0 / 1 / 9 form with
+   |d11| >= |d22| using at most one permutation per side, then take the
+   signs of the diagonal out of the rows: U = P_U S, V = P_V. */
+template <class R> static Part<R> svd_z9(const M2<R> &G, int t) {
+  M2<R> PU = m_id<R>(), PV = m_id<R>();
+  switch (t) {
+    case 2:
+      PU = m_x<R>();
+      break;
+    case 4:
+      PV = m_x<R>();
+      break;
+    case 8:
+      PU = m_x<R>();
+      PV = m_x<R>();
+      break;
+    case 6:
+      if (std::fabs(G.a[1][0]) >= std::fabs(G.a[0][1]))
+        PU = m_x<R>();
+      else
+        PV = m_x<R>();
+      break;
+    case 9:
+      if (std::fabs(G.a[0][0]) < std::fabs(G.a[1][1])) {
+        PU = m_x<R>();
+        PV = m_x<R>();
+      }
+      break;
+    default:
+      break; /* 0, 1 */
+  }
+  M2<R> D = m_mul(m_t(PU), m_mul(G, PV));
+  M2<R> S = m_diag(sgn(D.a[0][0]), sgn(D.a[1][1]));
+  Part<R> r;
+  r.U = m_mul(PU, S);
+  r.V = PV;
+  r.s1 = ef_of(std::fabs(D.a[0][0]));
+  r.s2 = ef_of(std::fabs(D.a[1][1]));
+  return r;
+}
+
+/* Givens rotation by theta from tan(theta) (eq. Givens, Lemma sincostheta):
+   sec = hypot(tan, 1), cos = fl(1/sec), sin = fl(tan/sec). */
+template <class R> static M2<R> givens(R tan_t) {
+  R sec = cr_hypot(tan_t, (R)1);
+  return m_rot((R)1 / sec, tan_t / sec);
+}
+
+/* Class t ~ 3 (Sect. 3.1): one non-zero column.  Swap the columns of a
+   t = 12 matrix (P_V), make the column positive by row signs (S_U), put the
+   larger element on top (P_U), one QR rotation with tan = g21''/g11''
+   (eq. theta); sigma1 = hypot, sigma2 = 0; U = S_U P_U U_theta, V = P_V. */
+template <class R> static Part<R> svd_z3(const M2<R> &G, int t) {
+  M2<R> PV = (t == 12) ? m_x<R>() : m_id<R>();
+  M2<R> H = m_mul(G, PV);
+  R a = H.a[0][0], b = H.a[1][0];
+  M2<R> SU = m_diag(sgn(a), sgn(b));
+  a = std::fabs(a);
+  b = std::fabs(b);
+  M2<R> PU = m_id<R>();
+  if (a < b) {
+    PU = m_x<R>();
+    std::swap(a, b);
+  }
+  Part<R> r;
+  r.U = m_mul(m_mul(SU, PU), givens(b / a));
+  r.V = PV;
+  r.s1 = ef_of(cr_hypot(a, b));
+  r.s2 = ef_of((R)0);
+  return r;
+}
+
+/* Class t ~ 5 (Sect. 3.1): one non-zero row; the transposed analogue:
+   P_U for t = 10, column signs S_V, column order P_V, one RQ rotation with
+   tan = g12''/g11''; U = P_U, V = S_V P_V V_theta. */
+template <class R> static Part<R> svd_z5(const M2<R> &G, int t) {
+  M2<R> PU = (t == 10) ? m_x<R>() : m_id<R>();
+  M2<R> H = m_mul(m_t(PU), G);
+  R a = H.a[0][0], b = H.a[0][1];
+  M2<R> SV = m_diag(sgn(a), sgn(b));
+  a = std::fabs(a);
+  b = std::fabs(b);
+  M2<R> PV = m_id<R>();
+  if (a < b) {
+    PV = m_x<R>();
+    std::swap(a, b);
+  }
+  Part<R> r;
+  r.U = PU;
+  r.V = m_mul(m_mul(SV, PV), givens(b / a));
+  r.s1 = ef_of(cr_hypot(a, b));
+  r.s2 = ef_of((R)0);
+  return r;
+}
+
+/* The SVD of R~ = [a b; 0 d] with a >= d > 0, b > 0 (Sect. 3.3.1). */
+template <class R> struct Tri {
+  R cphi, sphi, tphi, sec_phi; /* functions of phi (Algorithm tf) */
+  R cpsi, spsi, tpsi;          /* functions of psi (Algorithm tp) */
+  EF<R> s1, s2;                /* sigma~' after the ordering */
+  bool psig;                   /* P_sigma = X */
+  bool ovf;                    /* tan(psi) overflowed */
+};
+
+template <class R> static Tri<R> tri_svd(R a, R b, R d) {
+  const R eps = Fmt<R>::eps();
+  const R inf = (R)INFINITY;
+  Tri<R> o;
+  /* Algorithm tf: tan(2 phi), in the listed order of cases */
+  R t2;
+  if (a == d) {
+    t2 = ((R)2 * d) / b; /* eq. t2f'' */
+  } else if (b == d) {   /* eq. t2f''' */
+    t2 = ef_fl(ef_div(ef_mul(ef_pow2(1, ef_of(b)), ef_of(d)), ef_mul(ef_of(a), ef_of(a))));
+  } else if (a / b < eps) {
+    t2 = ((R)2 * d) / b; /* eq. t2f'' */
+  } else {
+    R h = cr_hypot(a, b);
+    if (h == d) {
+      t2 = inf; /* eq. t2f' */
+    } else {
+      EF<R> s = ef_plus(h, d), df = ef_minus(h, d);
+      t2 = ef_fl(ef_div(ef_mul(ef_pow2(1, ef_of(b)), ef_of(d)), ef_mul(df, s)));
+    }
+  }
+  /* tan(phi) by eq. tf, then sec, cos, sin */
+  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + cr_hypot(t2, (R)1));
+  R sec_phi = cr_hypot(tphi, (R)1);
+  o.tphi = tphi;
+  o.sec_phi = sec_phi;
+  o.cphi = (R)1 / sec_phi;
+  o.sphi = tphi / sec_phi;
+  /* Algorithm tp: tan(psi) by eq. tp, the singular values by eq. s' or,
+     when tan(psi) overflows, by eq. tp' and the sigma assignments of
+     Algorithm tp */
+  R t = std::fma(d, tphi, b);
+  R tpsi = t / a;
+  o.tpsi = tpsi;
+  EF<R> s1, s2;
+  if (tpsi == inf) {
+    o.ovf = true;
+    EF<R> tt = ef_of(t);
+    EF<R> cpsi = ef_div(ef_of(a), tt);
+    o.cpsi = ef_fl(cpsi);
+    o.spsi = (R)1;
+    s1 = tt;
+    s2 = ef_mul(ef_of(d), cpsi);
+  } else {
+    o.ovf = false;
+    R sec_psi = cr_hypot(tpsi, (R)1);
+    o.cpsi = (R)1 / sec_psi;
+    o.spsi = tpsi / sec_psi;
+    EF<R> sp = ef_div(ef_of(sec_phi), ef_of(sec_psi));
+    s1 = ef_div(ef_of(a), sp);
+    s2 = ef_mul(ef_of(d), sp);
+  }
+  o.psig = ef_prec(s1, s2);
+  if (o.psig) std::swap(s1, s2);
+  o.s1 = s1;
+  o.s2 = s2;
+  return o;
+}
+
+/* Sect. 3.2.2: the fully pivoted URV of a prescaled type-15 matrix.
+   Column pivoting by the column norms w1, w2 (P_V), row signs from the new
+   first column (S_1), row pivoting (P_U), then the QR rotation of eq. QR15
+   with tan(theta) = g21/g11 of the pivoted matrix and r11 = w1.  r12 and r22
+   are returned with their signs (before S_12 and S_22). */
+template <class R> struct Urv15 {
+  M2<R> S1, PU, PV;
+  R tan_t, sec_t, r11, r12, r22;
+  bool ext, exact;
+};
+
+template <class R> static Urv15<R> urv15(const M2<R> &Gp) {
+  Urv15<R> q;
+  R w1 = cr_hypot(Gp.a[0][0], Gp.a[1][0]);
+  R w2 = cr_hypot(Gp.a[0][1], Gp.a[1][1]);
+  q.PV = m_id<R>();
+  if (w1 < w2) {
+    q.PV = m_x<R>();
+    std::swap(w1, w2);
+  }
+  M2<R> Gt = m_mul(Gp, q.PV);
+  q.S1 = m_diag(sgn(Gt.a[0][0]), sgn(Gt.a[1][0]));
+  M2<R> G2 = m_mul(q.S1, Gt);
+  q.PU = (G2.a[0][0] < G2.a[1][0]) ? m_x<R>() : m_id<R>();
+  M2<R> G3 = m_mul(m_t(q.PU), G2);
+  R g11 = G3.a[0][0], g21 = G3.a[1][0], g12 = G3.a[0][1], g22 = G3.a[1][1];
+  q.tan_t = g21 / g11;
+  q.sec_t = cr_hypot(q.tan_t, (R)1);
+  q.r11 = w1;
+  /* Theorem R: tan(theta) is exact iff g21 - tan g11 = 0; that residual of
+     a correctly rounded quotient is representable, so fma yields it exactly */
+  q.exact = std::fma(-q.tan_t, g11, g21) == 0;
+  R r12f = std::fma(g22, q.tan_t, g12) / q.sec_t;
+  R r22f = std::fma(-g12, q.tan_t, g22) / q.sec_t;
+  q.ext = false;
+  if (q.exact) {
+    q.r12 = r12f;
+    q.r22 = r22f;
+  } else if (sgn(g12) == sgn(g22)) {
+    /* same signs: r12 is accurate, r22 suffers cancellation: eq. EXT */
+    q.r12 = r12f;
+    q.r22 = ext(g22, g11, g12, g21, true, g11) / q.sec_t;
+    q.ext = true;
+  } else {
+    /* opposite signs: r22 is accurate, r12 by eq. EXT */
+    q.r22 = r22f;
+    q.r12 = ext(g12, g11, g22, g21, false, g11) / q.sec_t;
+    q.ext = true;
+  }
+  return q;
+}
+
+/* info word layout (also documented in the GPU library's header) */
+enum : uint32_t {
+  INFO_DET_U = 1u << 8,
+  INFO_DET_V = 1u << 9,
+  INFO_EXT = 1u << 10,
+  INFO_RSWAP = 1u << 11,
+  INFO_TPSI_OVF = 1u << 12,
+  INFO_PSIG = 1u << 13,
+  INFO_DEGEN = 1u << 14,
+  INFO_NONFINITE = 1u << 15,
+};
+
+template <class R> struct Res {
+  M2<R> U, V;
+  EF<R> s1, s2; /* backscaled sigma_1 >= sigma_2 */
+  uint32_t info;
+};
+
+template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
+  Res<R> res;
+  M2<R> G = {{{g11, g12}, {g21, g22}}};
+  int t = type_of(G);
+  if (!std::isfinite(g11) || !std::isfinite(g21) || !std::isfinite(g12) || !std::isfinite(g22)) {
+    R nan = (R)NAN;
+    res.U = M2<R>{{{nan, nan}, {nan, nan}}};
+    res.V = res.U;
+    res.s1.e = res.s2.e = 0;
+    res.s1.f = res.s2.f = nan;
+    res.info = (uint32_t)t | INFO_NONFINITE;
+    return res;
+  }
+  /* Phase 1: prescaling (eqs. eG and s); matrices of class 9 are not
+     scaled (Sect. 3.1) */
+  Cls c = cls_of(t);
+  int s = 0;
+  if (c != Z9) {
+    int eG = INT_MIN;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        if (G.a[i][j] != 0) eG = std::max(eG, std::ilogb(G.a[i][j]));
+    s = Fmt<R>::e_nu - eG - scale_type(c);
+  }
+  M2<R> Gp;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) Gp.a[i][j] = std::scalbn(G.a[i][j], s);
+  /* the zero pattern is re-examined after the scaling */
+  int t1 = type_of(Gp);
+  Cls c1 = cls_of(t1);
+  uint32_t info = (uint32_t)t | ((uint32_t)t1 << 4);
+
+  Part<R> part;
+  bool done = false;
+  if (c1 == Z9) {
+    part = svd_z9(Gp, t1);
+    done = true;
+  } else if (c1 == Z3) {
+    part = svd_z3(Gp, t1);
+    done = true;
+  } else if (c1 == Z5) {
+    part = svd_z5(Gp, t1);
+    done = true;
+  }
+
+  /* Phase 2: the (pivoted) URV factorisation */
+  R r11 = 0, r12 = 0, r22 = 0;
+  M2<R> Uplus = m_id<R>(), Vplus = m_id<R>();
+  /* Z15 keeps the factors of U_+ apart for the heuristic */
+  M2<R> S1 = m_id<R>(), PU15 = m_id<R>();
+  R tan_t = 0;
+  bool s22neg = false;
+  if (!done && c1 == Z13) {
+    /* Sect. 3.2.1: permute into the upper triangular form, then three sign
+       changes make the upper triangle positive; all error-free */
+    M2<R> PU = m_id<R>(), PV = m_id<R>();
+    if (t1 == 7) PV = m_x<R>();
+    if (t1 == 14) PU = m_x<R>();
+    if (t1 == 11) {
+      PU = m_x<R>();
+      PV = m_x<R>();
+    }
+    M2<R> H = m_mul(m_t(PU), m_mul(Gp, PV)); /* [x y; 0 z] */
+    R x = H.a[0][0], y = H.a[0][1], z = H.a[1][1];
+    M2<R> S11 = m_diag(sgn(x), (R)1);
+    y = y * sgn(x);
+    M2<R> S12 = m_diag((R)1, sgn(y));
+    z = z * sgn(y);
+    M2<R> S22 = m_diag((R)1, sgn(z));
+    r11 = std::fabs(x);
+    r12 = std::fabs(y);
+    r22 = std::fabs(z);
+    Uplus = m_mul(m_mul(PU, S11), S22);
+    Vplus = m_mul(PV, S12);
+  } else if (!done && c1 == Z15) {
+    Urv15<R> q = urv15(Gp);
+    if (q.ext) info |= INFO_EXT;
+    M2<R> PV = q.PV;
+    S1 = q.S1;
+    PU15 = q.PU;
+    tan_t = q.tan_t;
+    r11 = q.r11;
+    r12 = q.r12;
+    r22 = q.r22;
+    if (r12 == 0 || r22 == 0) {
+      /* a zero appeared: R'' is of type 9 (or 1), or 5; it is processed as
+         in Sect. 3.1, accounting for the transformations already applied */
+      info |= INFO_DEGEN;
+      M2<R> Rpp = {{{r11, r12}, {(R)0, r22}}};
+      int t2 = type_of(Rpp);
+      Part<R> sub = (cls_of(t2) == Z5) ? svd_z5(Rpp, t2) : svd_z9(Rpp, t2);
+      part.U = m_mul(m_mul(m_mul(S1, PU15), givens(tan_t)), sub.U);
+      part.V = m_mul(PV, sub.V);
+      part.s1 = sub.s1;
+      part.s2 = sub.s2;
+      done = true;
+    } else {
+      M2<R> S12 = m_diag((R)1, sgn(r12));
+      r22 = r22 * sgn(r12);
+      r12 = std::fabs(r12);
+      s22neg = r22 < 0;
+      r22 = std::fabs(r22);
+      Vplus = m_mul(PV, S12);
+    }
+  }
+
+  if (!done) {
+    /* Phase 3 (Sect. 3.3): swap the diagonal if r11 < r22 by permuting
+       R^T symmetrically with X (eq. RT), compute the SVD of R~ and assemble */
+    bool swapped = r11 < r22;
+    if (swapped) info |= INFO_RSWAP;
+    Tri<R> tr = swapped ? tri_svd(r22, r12, r11) : tri_svd(r11, r12, r22);
+    if (tr.ovf) info |= INFO_TPSI_OVF;
+    if (tr.psig) info |= INFO_PSIG;
+    M2<R> S2 = swapped ? m_diag((R)1, (R)-1) : m_id<R>();
+    /* eq. RT: U_bphi = rot(sin psi, cos psi) S2, V_bpsi = rot(sin phi,
+       cos phi) S2, tan(bphi) = 1/tan(psi) when swapped */
+    M2<R> Ubphi = swapped ? m_mul(m_rot(tr.spsi, tr.cpsi), S2) : m_rot(tr.cphi, tr.sphi);
+    M2<R> Vbpsi = swapped ? m_mul(m_rot(tr.sphi, tr.cphi), S2) : m_rot(tr.cpsi, tr.spsi);
+    R tbphi = swapped ? (R)1 / tr.tpsi : tr.tphi;
+    M2<R> Psig = tr.psig ? m_x<R>() : m_id<R>();
+    if (c1 == Z13) {
+      part.U = m_mul(m_mul(Uplus, Ubphi), Psig);
+    } else {
+      /* Z15: the left-vector heuristic (eqs. p+t, p-t, tan+-, UV): the two
+         rotations by theta and bphi are merged into one by the tangent of
+         the sum (S22 = I) or of the difference (S22 = diag(1,-1)); the
+         quadrant follows from the sign of the denominator */
+      R num, den;
+      if (!s22neg) {
+        num = tbphi + tan_t;
+        den = std::fma(-tbphi, tan_t, (R)1);
+      } else {
+        num = tbphi - tan_t;
+        den = std::fma(tbphi, tan_t, (R)1);
+      }
+      R ca, sa;
+      if (den == 0) {
+        ca = 0;
+        sa = sgn(num);
+      } else {
+        R ta = num / den;
+        R sec_a = cr_hypot(ta, (R)1);
+        R sd = sgn(den);
+        ca = sd * ((R)1 / sec_a);
+        sa = sd * (ta / sec_a);
+      }
+      M2<R> Mrot = m_mul(m_rot(ca, sa), S2);
+      if (s22neg) Mrot = m_mul(m_diag((R)1, (R)-1), Mrot);
+      part.U = m_mul(m_mul(m_mul(S1, PU15), Mrot), Psig);
+    }
+    part.V = m_mul(m_mul(Vplus, Vbpsi), Psig);
+    part.s1 = tr.s1;
+    part.s2 = tr.s2;
+  }
+
+  /* Sect. 3.3.2: backscale, sigma_i = 2^-s (.) sigma~_i' */
+  res.U = part.U;
+  res.V = part.V;
+  res.s1 = ef_pow2(-s, part.s1);
+  res.s2 = ef_pow2(-s, part.s2);
+  res.info = info | ((uint32_t)(uint16_t)(int16_t)s << 16);
+  return res;
+}
+
+/* U (or V) is a signed permutation times a plane rotation, hence of the
+   form [c -d s; s d c] with d = det = +-1.  Returns false if not. */
+template <class R> static bool compact(const M2<R> &U, R &c, R &s, bool &neg) {
+  R d = U.a[0][0] * U.a[1][1] - U.a[0][1] * U.a[1][0];
+  neg = d < 0;
+  R dd = neg ? (R)-1 : (R)1;
+  c = U.a[0][0];
+  s = U.a[1][0];
+  bool ok = (U.a[0][1] == -dd * s) && (U.a[1][1] == dd * c);
+  /* canonical zeros: -0 becomes +0 */
+  c = c + (R)0;
+  s = s + (R)0;
+  return ok;
+}
+
+template <class R>
+static int batch_fwd(int64_t n, const R *g11, const R *g21, const R *g12, const R *g22, R *cu,
+                     R *su, R *cv, R *sv, R *f1, R *f2, int32_t *e1, int32_t *e2, int32_t *info,
+                     R *s1, R *s2, int nthreads) {
+  int bad = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    Res<R> r = ksvd2<R>(g11[i], g21[i], g12[i], g22[i]);
+    bool nu, nv;
+    R c, s;
+    bool okU = compact(r.U, c, s, nu);
+    cu[i] = c;
+    su[i] = s;
+    bool okV = compact(r.V, c, s, nv);
+    cv[i] = c;
+    sv[i] = s;
+    uint32_t inf = r.info;
+    if (!(inf & INFO_NONFINITE)) {
+      if (nu) inf |= INFO_DET_U;
+      if (nv) inf |= INFO_DET_V;
+      if (!okU || !okV) bad += 1;
+    }
+    f1[i] = r.s1.f;
+    f2[i] = r.s2.f;
+    e1[i] = r.s1.e;
+    e2[i] = r.s2.e;
+    info[i] = (int32_t)inf;
+    if (s1) s1[i] = ef_fl(r.s1);
+    if (s2) s2[i] = ef_fl(r.s2);
+  }
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 5. Two-sided Kogbetliantz iteration over one n x n matrix (Sect. 1, eq.  */
+/*    (SVD)): in each parallel step the n/2 disjoint pivot submatrices of a  */
+/*    round-robin ordering are diagonalised by the 2x2 SVD above; the        */
+/*    embedded U_k^T is applied to the pivot rows, then V_k to the pivot     */
+/*    columns; the pivot off-diagonals become 0 and its diagonal sigma; U_k  */
+/*    and V_k accumulate into U and V.  Matrices are column-major.           */
+/* ------------------------------------------------------------------------ */
+
+/* Round-robin (circle) ordering: position 0 is fixed, positions 1..n-1
+   rotate by one each step; in step k the slot pairs (q, n-1-q) meet. */
+static int rr_player(int n, int k, int q) {
+  if (q == 0) return 0;
+  return 1 + (q - 1 + k) % (n - 1);
+}
+
+/* one element pair of a rotation: x' = a x + b y as fma(a, x, b*y) */
+template <class R> static R rot_lin(R a, R x, R b, R y) { return std::fma(a, x, b * y); }
+
+template <class R>
+static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor, int accumulate,
+                     int *sweeps_done) {
+  if (!accumulate) {
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        U[i + (int64_t)j * n] = (i == j) ? (R)1 : (R)0;
+        V[i + (int64_t)j * n] = (i == j) ? (R)1 : (R)0;
+      }
+  }
+  /* ||G_0||_F in binary64 (the threshold of the stopping criterion) */
+  double fro2 = 0;
+  for (int64_t k = 0; k < (int64_t)n * n; ++k) fro2 += (double)G[k] * (double)G[k];
+  double tol = tol_factor * n * (double)Fmt<R>::eps() * std::sqrt(fro2);
+  int np = n / 2;
+  R *pc = new R[4 * np]; /* per pivot: u11 u21 u12 u22 */
+  R *pv = new R[4 * np];
+  int *pi = new int[np], *pj = new int[np];
+  R *ps1 = new R[np], *ps2 = new R[np];
+  int status = 1;
+  int sw = 0;
+  for (sw = 0; sw < max_sweeps; ++sw) {
+    for (int k = 0; k < n - 1; ++k) {
+      for (int q = 0; q < np; ++q) {
+        int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
+        int i = std::min(a, b), j = std::max(a, b);
+        pi[q] = i;
+        pj[q] = j;
+        R gii = G[i + (int64_t)i * n], gji = G[j + (int64_t)i * n];
+        R gij = G[i + (int64_t)j * n], gjj = G[j + (int64_t)j * n];
+        Res<R> r = ksvd2<R>(gii, gji, gij, gjj);
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y) {
+            pc[4 * q + x + 2 * y] = r.U.a[x][y];
+            pv[4 * q + x + 2 * y] = r.V.a[x][y];
+          }
+        ps1[q] = ef_fl(r.s1);
+        ps2[q] = ef_fl(r.s2);
+      }
+      /* rows: G <- U_k^T G; row i' = u11 row_i + u21 row_j, row j' = u12 row_i + u22 row_j */
+      for (int q = 0; q < np; ++q) {
+        int i = pi[q], j = pj[q];
+        R u11 = pc[4 * q], u21 = pc[4 * q + 1], u12 = pc[4 * q + 2], u22 = pc[4 * q + 3];
+        for (int c = 0; c < n; ++c) {
+          R x = G[i + (int64_t)c * n], y = G[j + (int64_t)c * n];
+          G[i + (int64_t)c * n] = rot_lin(u11, x, u21, y);
+          G[j + (int64_t)c * n] = rot_lin(u12, x, u22, y);
+        }
+      }
+      /* columns: G <- G V_k; col i' = col_i v11 + col_j v21, col j' = col_i v12 + col_j v22 */
+      for (int q = 0; q < np; ++q) {
+        int i = pi[q], j = pj[q];
+        R v11 = pv[4 * q], v21 = pv[4 * q + 1], v12 = pv[4 * q + 2], v22 = pv[4 * q + 3];
+        for (int r = 0; r < n; ++r) {
+          R x = G[r + (int64_t)i * n], y = G[r + (int64_t)j * n];
+          G[r + (int64_t)i * n] = rot_lin(v11, x, v21, y);
+          G[r + (int64_t)j * n] = rot_lin(v12, x, v22, y);
+        }
+        /* the pivot block becomes diag(sigma1, sigma2) */
+        G[i + (int64_t)i * n] = ps1[q];
+        G[j + (int64_t)j * n] = ps2[q];
+        G[i + (int64_t)j * n] = 0;
+        G[j + (int64_t)i * n] = 0;
+      }
+      /* U <- U U_k, V <- V V_k (columns) */
+      for (int q = 0; q < np; ++q) {
+        int i = pi[q], j = pj[q];
+        R u11 = pc[4 * q], u21 = pc[4 * q + 1], u12 = pc[4 * q + 2], u22 = pc[4 * q + 3];
+        R v11 = pv[4 * q], v21 = pv[4 * q + 1], v12 = pv[4 * q + 2], v22 = pv[4 * q + 3];
+        for (int r = 0; r < n; ++r) {
+          R x = U[r + (int64_t)i * n], y = U[r + (int64_t)j * n];
+          U[r + (int64_t)i * n] = rot_lin(u11, x, u21, y);
+          U[r + (int64_t)j * n] = rot_lin(u12, x, u22, y);
+          x = V[r + (int64_t)i * n];
+          y = V[r + (int64_t)j * n];
+          V[r + (int64_t)i * n] = rot_lin(v11, x, v21, y);
+          V[r + (int64_t)j * n] = rot_lin(v12, x, v22, y);
+        }
+      }
+    }
+    /* off-diagonal Frobenius norm after the sweep, in binary64 */
+    double off2 = 0;
+    for (int c = 0; c < n; ++c)
+      for (int r = 0; r < n; ++r)
+        if (r != c) off2 += (double)G[r + (int64_t)c * n] * (double)G[r + (int64_t)c * n];
+    if (std::sqrt(off2) <= tol) {
+      status = 0;
+      ++sw;
+      break;
+    }
+  }
+  *sweeps_done = sw;
+  delete[] pc;
+  delete[] pv;
+  delete[] pi;
+  delete[] pj;
+  delete[] ps1;
+  delete[] ps2;
+  return status;
+}
+
+}  // namespace
+
+/* ------------------------------------------------------------------------ */
+/* 6. extern "C" entry points used by the test-suite (via ctypes).           */
+/* ------------------------------------------------------------------------ */
+extern "C" {
+
+int orc_version(void) { return 1; }
+
+double orc_hypot_f64(double x, double y) { return cr_hypot(x, y); }
+float orc_hypot_f32(float x, float y) { return cr_hypot(x, y); }
+
+void orc_hypot_batch_f64(int64_t n, const double *x, const double *y, double *out) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t i = 0; i < n; ++i) out[i] = cr_hypot(x[i], y[i]);
+}
+
+void orc_hypot_batch_f32(int64_t n, const float *x, const float *y, float *out) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t i = 0; i < n; ++i) out[i] = cr_hypot(x[i], y[i]);
+}
+
+/* (e,f) operations, exposed for their pins: op 0 = plus, 1 = minus,
+   2 = mul, 3 = div (the last two on N(x), N(y)) */
+void orc_ef_op_f64(int op, double x, double y, int *e, double *f) {
+  EF<double> r;
+  switch (op) {
+    case 0:
+      r = ef_plus(x, y);
+      break;
+    case 1:
+      r = ef_minus(x, y);
+      break;
+    case 2:
+      r = ef_mul(ef_of(x), ef_of(y));
+      break;
+    default:
+      r = ef_div(ef_of(x), ef_of(y));
+      break;
+  }
+  *e = r.e;
+  *f = r.f;
+}
+
+void orc_ef_op_f32(int op, float x, float y, int *e, float *f) {
+  EF<float> r;
+  switch (op) {
+    case 0:
+      r = ef_plus(x, y);
+      break;
+    case 1:
+      r = ef_minus(x, y);
+      break;
+    case 2:
+      r = ef_mul(ef_of(x), ef_of(y));
+      break;
+    default:
+      r = ef_div(ef_of(x), ef_of(y));
+      break;
+  }
+  *e = r.e;
+  *f = r.f;
+}
+
+double orc_ext_f64(double x1, double y1, double x2, double y2, int minus, double d) {
+  return ext_f64(x1, y1, x2, y2, minus != 0, d);
+}
+
+float orc_ext_f32(float x1, float y1, float x2, float y2, int minus, float d) {
+  return ext_f32(x1, y1, x2, y2, minus != 0, d);
+}
+
+/* The URV factorisation of a prescaled type-15 matrix (for the Theorem R
+   checks): out = {r11, r12, r22, tan(theta)}, flags bit0 exact tan, bit1 EXT. */
+void orc_urv15_f64(double g11, double g21, double g12, double g22, double *out, int *flags) {
+  M2<double> G = {{{g11, g12}, {g21, g22}}};
+  Urv15<double> q = urv15(G);
+  out[0] = q.r11;
+  out[1] = q.r12;
+  out[2] = q.r22;
+  out[3] = q.tan_t;
+  *flags = (q.exact ? 1 : 0) | (q.ext ? 2 : 0);
+}
+
+void orc_urv15_f32(float g11, float g21, float g12, float g22, float *out, int *flags) {
+  M2<float> G = {{{g11, g12}, {g21, g22}}};
+  Urv15<float> q = urv15(G);
+  out[0] = q.r11;
+  out[1] = q.r12;
+  out[2] = q.r22;
+  out[3] = q.tan_t;
+  *flags = (q.exact ? 1 : 0) | (q.ext ? 2 : 0);
+}
+
+/* returns the number of results whose U or V is not of the compact form
+   (an internal consistency check; 0 expected) */
+int orc_ksvd2_f64(int64_t n, const double *g11, const double *g21, const double *g12,
+                  const double *g22, double *cu, double *su, double *cv, double *sv, double *f1,
+                  double *f2, int32_t *e1, int32_t *e2, int32_t *info, double *s1, double *s2,
+                  int nthreads) {
+  return batch_fwd<double>(n, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1, s2,
+                           nthreads);
+}
+
+int orc_ksvd2_f32(int64_t n, const float *g11, const float *g21, const float *g12,
+                  const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
+                  float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1, float *s2,
+                  int nthreads) {
+  return batch_fwd<float>(n, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1, s2,
+                          nthreads);
+}
+
+/* One n x n matrix (column-major, in place): returns 0 when converged,
+   1 when max_sweeps ran out; tol_factor < 0 disables the stopping test. */
+int orc_kog_sweep_f64(int n, double *G, double *U, double *V, int max_sweeps, double tol_factor,
+                      int accumulate, int *sweeps_done) {
+  return sweep_one<double>(n, G, U, V, max_sweeps, tol_factor, accumulate, sweeps_done);
+}
+
+int orc_kog_sweep_f32(int n, float *G, float *U, float *V, int max_sweeps, double tol_factor,
+                      int accumulate, int *sweeps_done) {
+  return sweep_one<float>(n, G, U, V, max_sweeps, tol_factor, accumulate, sweeps_done);
+}
+
+}  // extern "C"

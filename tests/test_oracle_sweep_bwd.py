@@ -1,0 +1,186 @@
+"""Pins of the oracle's Kogbetliantz sweep (Sect. 1, eq. SVD) and of the SVD adjoint.
+
+Sweep: converged results are checked against LAPACK's singular values (numpy.linalg.svd,
+run as a library), the stopping test (off-diagonal norm <= n eps ||G||_F), orthogonality of
+U and V and the reconstruction G = U Sigma V^T.
+
+Adjoint: central finite differences of the oracle's own forward map (an independent
+numerical derivative) on general, near-degenerate (gauge-invariant polar-factor loss) and
+rank-deficient (first singular triple only) matrices, and the textbook special case
+d sigma_i / dG = u_i v_i^T.
+"""
+import numpy as np
+import pytest
+
+from paper_2407_13116_amd import inputs
+
+DTYPES = [np.float64, np.float32]
+
+
+def _eps(dtype):
+    return 2.0 ** (-53 if np.dtype(dtype) == np.float64 else -24)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [2, 4, 6, 10, 16, 32])
+def test_sweep_converges_to_svd(orc, dtype, n):
+    rng = np.random.default_rng(100 + n)
+    G0 = (rng.standard_normal((n, n)) * np.exp2(rng.integers(-3, 4, (n, n)))).astype(dtype)
+    G, U, V, st, sw = orc.kog_sweep(np.asfortranarray(G0), max_sweeps=30, tol_factor=1.0)
+    assert st == 0 and 1 <= sw <= 15, (st, sw)
+    eps = _eps(dtype)
+    G0d = G0.astype(np.float64)
+    fro = np.linalg.norm(G0d)
+    off = np.linalg.norm(G - np.diag(np.diag(G)))
+    assert off <= n * eps * fro * (1 + 1e-6)
+    sig = np.sort(np.abs(np.diag(G).astype(np.float64)))[::-1]
+    ref = np.linalg.svd(G0d, compute_uv=False)
+    assert np.max(np.abs(sig - ref)) <= 20 * n * eps * ref[0]
+    Ud, Vd = U.astype(np.float64), V.astype(np.float64)
+    assert np.linalg.norm(Ud.T @ Ud - np.eye(n)) <= 20 * n * eps
+    assert np.linalg.norm(Vd.T @ Vd - np.eye(n)) <= 20 * n * eps
+    R = Ud @ np.diag(np.diag(G).astype(np.float64)) @ Vd.T
+    assert np.linalg.norm(R - G0d) <= 20 * n * eps * fro
+
+
+def test_sweep_fixed_count_and_diagonal(orc):
+    rng = np.random.default_rng(3)
+    G0 = np.asfortranarray(rng.standard_normal((8, 8)))
+    _, _, _, st, sw = orc.kog_sweep(G0, max_sweeps=3, tol_factor=-1.0)
+    assert (st, sw) == (1, 3)
+    D = np.asfortranarray(np.diag([3.0, -1.0, 2.0, 0.5]))
+    G, U, V, st, sw = orc.kog_sweep(D, max_sweeps=5, tol_factor=1.0)
+    assert st == 0 and sw == 1
+    assert sorted(np.abs(np.diag(G))) == [0.5, 1.0, 2.0, 3.0]
+
+
+def test_sweep_graded_columns(orc):
+    """The uniform-size workload's column grading (column j scaled by 2^(-j/8))."""
+    G0 = inputs.sweep_uniform(seed=6, nmat=1, n=32)[0]
+    G, U, V, st, sw = orc.kog_sweep(G0, max_sweeps=30, tol_factor=1.0)
+    assert st == 0
+    ref = np.linalg.svd(G0, compute_uv=False)
+    sig = np.sort(np.abs(np.diag(G)))[::-1]
+    assert np.max(np.abs(sig - ref) / ref) <= 1e-12
+
+
+# ------------------------------------------------------------------ adjoint
+
+def _fwd(orc, G):
+    """Oracle forward on [B,2,2] float64: (U, S, V) full, S plain."""
+    g = inputs.soa_from_mats(G)
+    o = orc.ksvd2(*g)
+    U, V = orc.full_uv(o)
+    S = np.stack([o["s1"], o["s2"]], 1)
+    return U, S, V
+
+
+def _fd(orc, G, loss, h_rel=1e-6):
+    B = G.shape[0]
+    grad = np.zeros_like(G)
+    gmax = np.abs(G).reshape(B, -1).max(axis=1)
+    for r in range(2):
+        for c in range(2):
+            # a step relative to the entry itself (tiny entries need tiny steps)
+            h = h_rel * np.maximum(np.abs(G[:, r, c]), 1e-3 * gmax)
+            Gp = G.copy()
+            Gm = G.copy()
+            Gp[:, r, c] += h
+            Gm[:, r, c] -= h
+            grad[:, r, c] = (loss(*_fwd(orc, Gp)) - loss(*_fwd(orc, Gm))) / (2 * h)
+    return grad
+
+
+def _rel(a, b):
+    scale = np.maximum(np.abs(b).reshape(len(b), -1).max(axis=1), 1e-300)
+    return (np.abs(a - b).reshape(len(b), -1).max(axis=1) / scale).max()
+
+
+def test_backward_fd_general(orc):
+    G, dS, dU, dV, lab = inputs.diff_batch(np.float64, B=4096)
+    sel = lab == 0
+    G, dS, dU, dV = G[sel][:600], dS[sel][:600], dU[sel][:600], dV[sel][:600]
+    U, S, V = _fwd(orc, G)
+
+    def loss(U_, S_, V_):
+        return (dS * S_).sum(1) + (dU * U_).sum((1, 2)) + (dV * V_).sum((1, 2))
+
+    got = orc.svd2_backward(U, S, V, dS, dU, dV)
+    fd = _fd(orc, G, loss)
+    assert _rel(got, fd) <= 1e-6
+
+
+def _mp_polar_loss_grad(G, dS, W, h=None):
+    """Central differences of L = dS . sigma + <W, U V^T> through an independent
+    300-bit SVD (mpmath.svd_r): exact to far below the float64 noise floor."""
+    import mpmath
+    with mpmath.workprec(300):
+        h = mpmath.mpf(2) ** -120 if h is None else h
+
+        def L(M):
+            U, S, V = mpmath.svd_r(M)          # M = U diag(S) V
+            Q = U * V                           # the polar factor (gauge-invariant)
+            val = sum(mpmath.mpf(float(dS[k])) * S[k] for k in range(2))
+            for r in range(2):
+                for c in range(2):
+                    val += mpmath.mpf(float(W[r, c])) * Q[r, c]
+            return val
+
+        out = np.zeros((2, 2))
+        for r in range(2):
+            for c in range(2):
+                Mp = mpmath.matrix([[float(x) for x in row] for row in G])
+                Mm = Mp.copy()
+                Mp[r, c] += h
+                Mm[r, c] -= h
+                out[r, c] = float((L(Mp) - L(Mm)) / (2 * h))
+        return out
+
+
+def test_backward_fd_near_degenerate(orc):
+    """sigma1/sigma2 - 1 < 1e-6: the gauge-invariant polar-factor loss <W, U V^T> plus
+    Sigma terms (its 1/(s1-s2) coefficient p vanishes).  U and V alone are ill-conditioned
+    there, so the differences are taken through a 300-bit SVD instead of the float64 map."""
+    G, dS, dU, dV, lab = inputs.diff_batch(np.float64, B=4096)
+    sel = lab == 1
+    G, dS, W = G[sel][:120], dS[sel][:120], dU[sel][:120]
+    U, S, V = _fwd(orc, G)
+    assert np.all(S[:, 0] / S[:, 1] - 1 < 2e-6)
+    dUa = np.einsum("bij,bjk->bik", W, V)              # dL/dU = W V
+    dVa = np.einsum("bji,bjk->bik", W, U)              # dL/dV = W^T U
+    got = orc.svd2_backward(U, S, V, dS, dUa, dVa)
+    fd = np.stack([_mp_polar_loss_grad(G[i], dS[i], W[i]) for i in range(len(G))])
+    assert _rel(got, fd) <= 1e-6
+
+
+def test_backward_fd_rank_deficient(orc):
+    """sigma2 = 0: the loss of the first singular triple only (sigma1, u1 v1^T), smooth at
+    det G = 0; the adjoint stays finite."""
+    G, dS, dU, dV, lab = inputs.diff_batch(np.float64, B=4096)
+    sel = lab == 2
+    G, dS, W = G[sel][:300], dS[sel][:300], dU[sel][:300]
+    U, S, V = _fwd(orc, G)
+    assert np.all(S[:, 1] <= 1e-15 * S[:, 0])
+
+    def loss(U_, S_, V_):
+        return dS[:, 0] * S_[:, 0] + np.einsum("bij,bi,bj->b", W, U_[:, :, 0], V_[:, :, 0])
+
+    dUa = np.zeros_like(U)
+    dVa = np.zeros_like(V)
+    dUa[:, :, 0] = np.einsum("bij,bj->bi", W, V[:, :, 0])
+    dVa[:, :, 0] = np.einsum("bij,bi->bj", W, U[:, :, 0])
+    dSa = dS.copy()
+    dSa[:, 1] = 0
+    got = orc.svd2_backward(U, S, V, dSa, dUa, dVa)
+    assert np.all(np.isfinite(got))
+    fd = _fd(orc, G, loss)
+    assert _rel(got, fd) <= 1e-6
+
+
+def test_backward_sigma_only_closed_form(orc):
+    G, dS, _, _, _ = inputs.diff_batch(np.float64, B=2048)
+    U, S, V = _fwd(orc, G)
+    got = orc.svd2_backward(U, S, V, dS)
+    want = U[:, :, 0, None] * V[:, None, :, 0] * dS[:, 0, None, None] + \
+        U[:, :, 1, None] * V[:, None, :, 1] * dS[:, 1, None, None]
+    assert np.max(np.abs(got - want)) <= 1e-15 * np.max(np.abs(want))
