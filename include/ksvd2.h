@@ -1,0 +1,202 @@
+/*
+ * ksvd2.h -- C ABI of libksvd2.so: the enhanced Kogbetliantz SVD of real 2x2
+ * matrices (V. Novakovic, "Arithmetical enhancements of the Kogbetliantz
+ * method for the SVD of order two", arXiv 2407.13116), batched on an AMD
+ * Instinct MI355X (gfx950), its adjoint, and a batched two-sided Kogbetliantz
+ * sweep built on it.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - G = U Sigma V^T with U, V orthogonal and sigma_1 >= sigma_2 >= 0
+ *    (Sect. 1, the definition of the SVD).
+ *  - Every pointer argument is device memory owned by the caller (for example
+ *    the storage of a torch tensor), aligned to its element size, and the
+ *    arrays must not overlap unless stated.  The library allocates nothing
+ *    per call and keeps no reference to the arrays after the call returns.
+ *  - `stream` is a hipStream_t (NULL selects the null stream).  Calls only
+ *    enqueue work: they are asynchronous and ordered on that stream; results
+ *    are valid once the stream has been synchronised.
+ *  - dtype codes: 0 = binary32 (float), 1 = binary64 (double).
+ *  - Return value: 0 on success, or a negative status; the matching message
+ *    is available from ksvd2_last_error() (per host thread):
+ *      KSVD2_EINVAL (-1)  invalid argument (negative size, null or misaligned
+ *                         required pointer, tau < 0, ...), nothing enqueued
+ *      KSVD2_EDTYPE (-2)  unsupported dtype code, nothing enqueued
+ *      KSVD2_EHIP   (-3)  the HIP runtime reported an error at launch
+ *      KSVD2_EWORKSPACE (-4) a workspace is smaller than required
+ *    A batch of size 0 is a no-op that returns 0.
+ *  - Inputs must be finite (Sect. 2).  A non-finite matrix is not an error:
+ *    its info word gets bit 15 and its outputs are NaN.
+ *  - Results are bitwise reproducible (Sect. 3.3.2, the reproducibility
+ *    remark): they depend only on the input bits, not on the launch.
+ */
+#ifndef KSVD2_H
+#define KSVD2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KSVD2_OK 0
+#define KSVD2_EINVAL (-1)
+#define KSVD2_EDTYPE (-2)
+#define KSVD2_EHIP (-3)
+#define KSVD2_EWORKSPACE (-4)
+
+/* Bits of the per-matrix info word written by the forward entry points. */
+#define KSVD2_INFO_TYPE_MASK 0x0000000Fu      /* t: zero pattern before scaling (eq. ts)  */
+#define KSVD2_INFO_TYPE1_SHIFT 4              /* t': zero pattern after scaling (Sect. 3.1) */
+#define KSVD2_INFO_DET_U (1u << 8)            /* det U = -1                               */
+#define KSVD2_INFO_DET_V (1u << 9)            /* det V = -1                               */
+#define KSVD2_INFO_EXT (1u << 10)             /* an element of R by eq. (EXT)             */
+#define KSVD2_INFO_RSWAP (1u << 11)           /* r11 < r22: R^T permuted (eq. RT)         */
+#define KSVD2_INFO_TPSI_OVF (1u << 12)        /* tan(psi) overflowed (eq. tp')            */
+#define KSVD2_INFO_PSIGMA (1u << 13)          /* sigma~'' reordered, P_sigma = X (Alg. tp) */
+#define KSVD2_INFO_DEGENERATE (1u << 14)      /* r12 or r22 became 0 in the URV (Sect. 3.2.2) */
+#define KSVD2_INFO_NONFINITE (1u << 15)       /* non-finite input; outputs are NaN         */
+#define KSVD2_INFO_SCALE_SHIFT 16             /* bits 16..31: s of eq. (s) as int16        */
+
+/* Library version (incremented on ABI changes). */
+int ksvd2_version(void);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *ksvd2_last_error(void);
+
+/*
+ * ksvd2_batch_f64 / ksvd2_batch_f32 -- the enhanced Kogbetliantz SVD of `batch`
+ * independent real 2x2 matrices (Sect. 3: prescaling and the simple classes,
+ * Sect. 3.1; the URV factorisation, Sect. 3.2 and eq. EXT; the SVD of the
+ * triangular factor, Algorithms tf and tp; assembly with the left-vector
+ * heuristic and backscaling, Sect. 3.3.2).
+ *
+ * Layout: structure of arrays.  Each argument is a plane of `batch` elements;
+ * matrix k is G_k = [g11[k] g12[k]; g21[k] g22[k]].
+ * Outputs (all required except the two plain-sigma planes):
+ *   cu, su   U_k = [cu -d su; su d cu] with d = -1 if info bit 8 else +1
+ *   cv, sv   V_k = [cv -d sv; sv d cv] with d = -1 if info bit 9 else +1
+ *   f1, e1   sigma_1 = f1 * 2^e1 with 1 <= f1 < 2, or f1 = 0 and e1 = 0
+ *   f2, e2   sigma_2 likewise, sigma_1 >= sigma_2 >= 0.  The (e,f) form of
+ *            Sect. 2 cannot overflow or underflow (Sect. 3.3.2).
+ *   info     the bits above
+ *   s1_plain, s2_plain (nullable): sigma_i rounded once to the working
+ *            precision (may overflow to +inf or underflow).
+ * Zeros in cu, su, cv, sv are +0.
+ * Outputs must not alias inputs.
+ */
+int ksvd2_batch_f64(int64_t batch, const double *g11, const double *g21, const double *g12,
+                    const double *g22, double *cu, double *su, double *cv, double *sv,
+                    double *f1, double *f2, int32_t *e1, int32_t *e2, int32_t *info,
+                    double *s1_plain, double *s2_plain, void *stream);
+int ksvd2_batch_f32(int64_t batch, const float *g11, const float *g21, const float *g12,
+                    const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
+                    float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1_plain,
+                    float *s2_plain, void *stream);
+
+/*
+ * ksvd2_svd2x2 -- the same SVD in the layout of an autograd graph: G, U, V are
+ * [batch,2,2] row-major arrays (element (i,j) of matrix k at 4k + 2i + j), S is
+ * [batch,2] with the plain singular values (rounded once to the working
+ * precision).  `info` (nullable) receives the info words.  U and V are the full
+ * matrices of ksvd2_batch_*, bit for bit.  dtype: 0 = float, 1 = double.
+ */
+int ksvd2_svd2x2(int dtype, int64_t batch, const void *G, void *U, void *S, void *V,
+                 int32_t *info, void *stream);
+
+/*
+ * ksvd2_batch_backward -- the adjoint of G = U diag(S) V^T for square 2x2
+ * matrices with full U and V (the standard SVD adjoint,
+ *   dG = U [diag(dS) + (F o (J - J^T)) S + S (F o (K - K^T))] V^T,
+ *   J = U^T dU, K = V^T dV, F_ij = 1/(s_j^2 - s_i^2) (i != j),
+ * written out for order two with a = J12 - J21, b = K12 - K21, p = (a+b)/2,
+ * q = (a-b)/2:  M12 = -p/(s1-s2) + q/(s1+s2), M21 = -p/(s1-s2) - q/(s1+s2),
+ * dG = U [[dS1, M12], [M21, dS2]] V^T).  The paper defines the forward map only;
+ * the adjoint is textbook calculus on it.
+ * Layout: U, V, dU, dV, dG are [batch,2,2] row-major; S, dS are [batch,2].
+ * dS, dU, dV are nullable (a null pointer means a zero upstream gradient).
+ * Degenerate singular values: with tau > 0, 1/(s1-s2) is replaced by
+ * (s1-s2)/((s1-s2)^2 + (tau s1)^2) (Lorentzian broadening); with tau = 0 the
+ * exact formula is used and the p-term is dropped only when s1 - s2 == 0.  The
+ * q-term needs 1/(s1+s2) only, so s2 = 0 < s1 is finite; s1 = s2 = 0 gives
+ * M = diag(dS).  tau < 0 is KSVD2_EINVAL.  dtype: 0 = float, 1 = double.
+ */
+int ksvd2_batch_backward(int dtype, int64_t batch, const void *U, const void *S, const void *V,
+                         const void *dS, const void *dU, const void *dV, void *dG, double tau,
+                         void *stream);
+
+/*
+ * ksvd2_hypot_batch -- the correctly rounded hypot(x, y) = fl(sqrt(x^2 + y^2))
+ * of Sect. 2 (never overflows spuriously, zero iff both arguments are zero),
+ * elementwise over n elements, as used inside the SVD.  Exposed so that the
+ * primitive itself can be checked on the device.  dtype: 0 = float, 1 = double.
+ */
+int ksvd2_hypot_batch(int dtype, int64_t n, const void *x, const void *y, void *out,
+                      void *stream);
+
+/*
+ * kog_sweep_batch -- the two-sided Kogbetliantz iteration (Sect. 1, eq. SVD) on
+ * `nmat` independent square matrices of even orders n_k (2 <= n_k <= 8192, at
+ * most 65535 matrices): in each parallel step the n_k/2 disjoint pivots of a
+ * round-robin ordering are diagonalised by the 2x2 SVD above (U_p, sigma,
+ * V_p; sigma rounded once to W), U_p^T is applied to the pivot rows of G, then
+ * V_p to the pivot columns (each element pair as fma(a, x, b*y)), the pivot
+ * block is set to diag(sigma_1, sigma_2), and U <- U U_p, V <- V V_p on the
+ * pivot columns.  A sweep is n_k - 1 steps (every pair meets once); after each
+ * sweep the iteration stops once ||offdiag(G)||_F <= tol_factor n_k eps ||G_0||_F
+ * (eps = 2^-53 or 2^-24; tol_factor < 0 disables the test), or after
+ * max_sweeps sweeps.
+ *
+ * Layout: matrix k is column-major at element offset off_host[k] of G, U and
+ * V (the caller packs them; the matrices must not overlap).  n_host and
+ * off_host are host arrays of nmat entries.
+ *   G        in: the matrices; out: the final iteration matrices (their
+ *            diagonals are the singular values, unsorted, non-negative)
+ *   U, V     out: the accumulated transformations (in/out when accumulate != 0:
+ *            the iteration then continues from the given U, V, e.g. to resume)
+ *   sigma    (nullable) out: diag(G) of matrix k at offset n_0 + ... + n_{k-1}
+ *   sweeps_out (nullable, device int32[nmat]): sweeps performed, negated when
+ *            the stopping test was not met within max_sweeps
+ * mode: 0 = plain per-step launches (the host polls convergence once per sweep,
+ *           so the call returns after the work is done);
+ *       1 = persistent kernels (one workgroup per matrix, one launch per order
+ *           bucket), asynchronous;
+ *       2 = mode 1 captured into a hipGraph on first use and replayed on later
+ *           calls with identical arguments (needs a non-null stream).
+ * All modes perform the same arithmetic in the same order: bitwise identical.
+ * workspace: device memory of at least kog_sweep_workspace_size() bytes,
+ * 256-byte aligned, owned by the caller, used only during the call's work.
+ * Inputs must keep ||G||_F well below the overflow threshold (the iteration
+ * itself does not rescale G).
+ */
+int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                    void *G, void *U, void *V, void *sigma, int32_t *sweeps_out,
+                    int32_t max_sweeps, double tol_factor, int accumulate, int mode,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of workspace kog_sweep_batch and kog_sigma_grad need for this batch
+   (0 for invalid arguments). */
+size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);
+
+/* Tuning table of the persistent sweep kernels: workgroup size (256, 512 or
+   1024) for order bucket 0: n <= 64, 1: n <= 128, 2: n <= 256, 3: n <= 512,
+   4: larger.  Process-wide; set by the autotuner. */
+int kog_sweep_tune(int dtype, int bucket, int block);
+
+/*
+ * kog_sigma_grad -- the gradient of sum_i dsigma_i sigma_i with respect to G
+ * for the SVD G = U diag(sigma) V^T delivered by kog_sweep_batch:
+ * dG = U diag(dsigma) V^T (d sigma_i / dG = u_i v_i^T).  Layouts as in
+ * kog_sweep_batch (U, V, dG column-major at off_host[k]; dsigma packed like
+ * sigma); workspace as for kog_sweep_batch.
+ */
+int kog_sigma_grad(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                   const void *U, const void *V, const void *dsigma, void *dG, void *workspace,
+                   size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSVD2_H */

@@ -1,0 +1,698 @@
+// Batched two-sided Kogbetliantz iteration (Sect. 1, eq. SVD) over many square
+// matrices of possibly different even orders, built on the 2x2 SVD of
+// ksvd2_device.hpp.
+//
+// One parallel step k of a sweep (round-robin ordering, n/2 disjoint pivots):
+//   1. every pivot (i, j) of step k is diagonalised by the 2x2 SVD of
+//      [g_ii g_ij; g_ji g_jj] (U_p, sigma, V_p; sigma rounded to W);
+//   2. rows i, j of G are rotated by U_p^T, then columns i, j by V_p:
+//      x' = fma(a, x, b*y) for every element pair;
+//   3. the pivot block becomes diag(sigma_1, sigma_2) exactly;
+//   4. columns i, j of U and V are rotated by U_p and V_p.
+// A sweep is n - 1 steps; after each sweep the off-diagonal Frobenius norm
+// is compared with tol_factor * n * eps * ||G_0||_F.
+//
+// Executions of exactly the same arithmetic:
+//   mode 0  plain per-step launches: a pivot kernel and an update kernel per
+//           step, a check kernel per sweep, the host polls convergence;
+//   mode 1  persistent: one workgroup per matrix runs all its sweeps (pivot
+//           parameters in LDS, workgroup barriers between phases), one launch
+//           per size bucket, no host round trips;
+//   mode 2  mode 1 captured once into a hipGraph and replayed.
+// Every element's sequence of operations is identical in all modes, and the
+// reductions use a fixed order, so the results are bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "abi_common.hpp"
+#include "ksvd2_device.hpp"
+
+namespace ksvd2 {
+
+constexpr int kRed = 256;       // lanes of the fixed-order reductions
+constexpr int kMaxOrder = 8192; // pair indices are stored as int16
+
+struct SweepDesc {
+  const int32_t *n;      // order of matrix m
+  const int64_t *off;    // element offset of matrix m in G, U, V
+  const int64_t *soff;   // offset of matrix m in sigma
+  const int64_t *poff;   // offset of matrix m's pivots in the parameter table
+  double *fro2;          // ||G_0||_F^2
+  int32_t *sweeps;       // sweeps done so far
+  int32_t *done;         // converged flag
+};
+
+// slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
+// slots 1..n-1 rotate by one position per step; slots s and n-1-s meet
+__device__ inline int rr_player(int n, int k, int s) {
+  return s == 0 ? 0 : 1 + (s - 1 + k) % (n - 1);
+}
+
+__device__ inline void rr_pair(int n, int k, int q, int &i, int &j) {
+  int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
+  i = a < b ? a : b;
+  j = a < b ? b : a;
+}
+
+template <class R> struct Piv {
+  R u11, u21, u12, u22, v11, v21, v12, v22, s1, s2;
+};
+
+template <class R> __device__ inline Piv<R> pivot_svd(const R *G, int n, int i, int j) {
+  R gii = G[i + (int64_t)i * n], gji = G[j + (int64_t)i * n];
+  R gij = G[i + (int64_t)j * n], gjj = G[j + (int64_t)j * n];
+  Svd2<R> r = svd2<R>(gii, gji, gij, gjj);
+  R du = (r.info & I_DETU) ? (R)-1 : (R)1, dv = (r.info & I_DETV) ? (R)-1 : (R)1;
+  Piv<R> p;
+  p.u11 = r.cu;
+  p.u21 = r.su;
+  p.u12 = -du * r.su;
+  p.u22 = du * r.cu;
+  p.v11 = r.cv;
+  p.v21 = r.sv;
+  p.v12 = -dv * r.sv;
+  p.v22 = dv * r.cv;
+  p.s1 = scale2(r.f1, r.e1);
+  p.s2 = scale2(r.f2, r.e2);
+  return p;
+}
+
+template <class R> __device__ inline R lin(R a, R x, R b, R y) { return fma(a, x, b * y); }
+
+// One update item of step k, for a matrix of order n.  Items [0, np^2) are
+// the 2x2 blocks (p, q) of G (rows of pivot p, columns of pivot q); items
+// [np^2, np^2 + n np) rotate U[r, i_q], U[r, j_q]; the next n np items do the
+// same for V.  `pair(q, i, j)` and `piv(q)` read the step's tables.
+template <class R, class PairF, class PivF>
+__device__ inline void update_item(int64_t w, int n, R *G, R *U, R *V, PairF pair, PivF piv) {
+  int np = n >> 1;
+  int64_t nb = (int64_t)np * np;
+  if (w < nb) {
+    int p = (int)(w % np), q = (int)(w / np);
+    int ip, jp, iq, jq;
+    pair(p, ip, jp);
+    if (p == q) {
+      Piv<R> P = piv(p);
+      G[ip + (int64_t)ip * n] = P.s1;
+      G[jp + (int64_t)jp * n] = P.s2;
+      G[ip + (int64_t)jp * n] = (R)0;
+      G[jp + (int64_t)ip * n] = (R)0;
+      return;
+    }
+    pair(q, iq, jq);
+    Piv<R> Pp = piv(p), Pq = piv(q);
+    R *ci = G + (int64_t)iq * n, *cj = G + (int64_t)jq * n;
+    R a = ci[ip], b = ci[jp], c = cj[ip], d = cj[jp];  // rows (ip, jp) x cols (iq, jq)
+    // rows: row_i' = u11 row_i + u21 row_j, row_j' = u12 row_i + u22 row_j
+    R a1 = lin(Pp.u11, a, Pp.u21, b), b1 = lin(Pp.u12, a, Pp.u22, b);
+    R c1 = lin(Pp.u11, c, Pp.u21, d), d1 = lin(Pp.u12, c, Pp.u22, d);
+    // columns: col_i' = col_i v11 + col_j v21, col_j' = col_i v12 + col_j v22
+    ci[ip] = lin(Pq.v11, a1, Pq.v21, c1);
+    cj[ip] = lin(Pq.v12, a1, Pq.v22, c1);
+    ci[jp] = lin(Pq.v11, b1, Pq.v21, d1);
+    cj[jp] = lin(Pq.v12, b1, Pq.v22, d1);
+    return;
+  }
+  w -= nb;
+  int64_t nu = (int64_t)n * np;
+  bool isv = w >= nu;
+  if (isv) w -= nu;
+  int r = (int)(w % n), q = (int)(w / n);
+  int iq, jq;
+  pair(q, iq, jq);
+  Piv<R> P = piv(q);
+  R *M = isv ? V : U;
+  R e1 = isv ? P.v11 : P.u11, e2 = isv ? P.v21 : P.u21;
+  R e3 = isv ? P.v12 : P.u12, e4 = isv ? P.v22 : P.u22;
+  R *ci = M + (int64_t)iq * n, *cj = M + (int64_t)jq * n;
+  R x = ci[r], y = cj[r];
+  ci[r] = lin(e1, x, e2, y);
+  cj[r] = lin(e3, x, e4, y);
+}
+
+// Fixed-order sum of squares (in binary64) of G's entries (or of its off-
+// diagonal ones): lane t < 256 sums rows t, t+256, ... of every column in
+// column order; then a fixed halving tree.  Every thread of the block calls it.
+template <class R>
+__device__ double block_sumsq(const R *G, int n, bool offdiag, double *red) {
+  int t = threadIdx.x;
+  if (t < kRed) {
+    double acc = 0.0;
+    for (int c = 0; c < n; ++c) {
+      const R *col = G + (int64_t)c * n;
+      for (int r = t; r < n; r += kRed) {
+        if (offdiag && r == c) continue;
+        double x = (double)col[r];
+        acc = fma(x, x, acc);
+      }
+    }
+    red[t] = acc;
+  }
+  __syncthreads();
+  for (int s = kRed / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double v = red[0];
+  __syncthreads();
+  return v;
+}
+
+template <class R>
+__device__ double init_matrix(const R *G, R *U, R *V, int n, bool accumulate, double *red) {
+  if (!accumulate) {
+    int64_t tot = (int64_t)n * n;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+      int r = (int)(e % n), c = (int)(e / n);
+      R v = (r == c) ? (R)1 : (R)0;
+      U[e] = v;
+      V[e] = v;
+    }
+  }
+  return block_sumsq(G, n, false, red);
+}
+
+__device__ inline bool converged(double off2, double fro2, int n, double tolf, double eps) {
+  if (tolf < 0.0) return false;
+  double tol = tolf * (double)n * eps;
+  return off2 <= tol * tol * fro2;
+}
+
+template <class R>
+__device__ void finish_matrix(const R *G, int n, R *sig, int32_t *sweeps_out, int sweeps,
+                              bool conv) {
+  if (sig)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sig[i] = G[i + (int64_t)i * n];
+  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = conv ? sweeps : -sweeps;
+}
+
+// ----------------------------------------------------------- mode 0 kernels
+
+template <class R>
+__global__ __launch_bounds__(kRed) void k_sw_init(SweepDesc d, const R *G, R *U, R *V,
+                                                  int accumulate) {
+  __shared__ double red[kRed];
+  int m = blockIdx.x;
+  int64_t o = d.off[m];
+  double f2 = init_matrix(G + o, U + o, V + o, d.n[m], accumulate != 0, red);
+  if (threadIdx.x == 0) {
+    d.fro2[m] = f2;
+    d.sweeps[m] = 0;
+    d.done[m] = 0;
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, Piv<R> *par,
+                                                      int16_t *pairs, int k) {
+  int m = blockIdx.y;
+  int n = d.n[m];
+  int np = n >> 1;
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np || k >= n - 1 || d.done[m]) return;
+  int i, j;
+  rr_pair(n, k, q, i, j);
+  int64_t po = d.poff[m];
+  pairs[2 * (po + q)] = (int16_t)i;
+  pairs[2 * (po + q) + 1] = (int16_t)j;
+  par[po + q] = pivot_svd(G + d.off[m], n, i, j);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, R *U, R *V,
+                                                      const Piv<R> *par, const int16_t *pairs,
+                                                      int k) {
+  int m = blockIdx.y;
+  int n = d.n[m];
+  if (k >= n - 1 || d.done[m]) return;
+  int np = n >> 1;
+  int64_t items = (int64_t)np * np + 2 * (int64_t)n * np;
+  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= items) return;
+  int64_t po = d.poff[m], o = d.off[m];
+  const int16_t *pt = pairs + 2 * po;
+  const Piv<R> *pp = par + po;
+  update_item<R>(
+      w, n, G + o, U + o, V + o,
+      [pt](int q, int &i, int &j) {
+        i = pt[2 * q];
+        j = pt[2 * q + 1];
+      },
+      [pp](int q) { return pp[q]; });
+}
+
+template <class R>
+__global__ __launch_bounds__(kRed) void k_sw_check(SweepDesc d, const R *G, double tolf) {
+  __shared__ double red[kRed];
+  int m = blockIdx.x;
+  if (d.done[m]) return;  // uniform over the block
+  int n = d.n[m];
+  double off2 = block_sumsq(G + d.off[m], n, true, red);
+  if (threadIdx.x == 0) {
+    d.sweeps[m] += 1;
+    if (converged(off2, d.fro2[m], n, tolf, (double)Lim<R>::eps())) d.done[m] = 1;
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, const R *G, R *sigma,
+                                                    int32_t *sweeps_out) {
+  int m = blockIdx.x;
+  finish_matrix(G + d.off[m], d.n[m], sigma ? sigma + d.soff[m] : nullptr,
+                sweeps_out ? sweeps_out + m : nullptr, d.sweeps[m], d.done[m] != 0);
+}
+
+// ------------------------------------------------------- mode 1: persistent
+//
+// One workgroup per matrix (the launch covers the matrices listed in `mats`,
+// longest first).  LDS holds the step's pivot parameters and pair table; the
+// matrix itself stays in global memory (L2/MALL resident while it is hot).
+
+template <class R, int BS>
+__global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t *mats, R *G, R *U,
+                                                      R *V, R *sigma, int32_t *sweeps_out,
+                                                      int max_sweeps, double tolf,
+                                                      int accumulate) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *red = reinterpret_cast<double *>(smem);
+  int m = mats[blockIdx.x];
+  int n = d.n[m];
+  int np = n >> 1;
+  Piv<R> *spar = reinterpret_cast<Piv<R> *>(smem + kRed * sizeof(double));
+  int16_t *spair = reinterpret_cast<int16_t *>(smem + kRed * sizeof(double) + np * sizeof(Piv<R>));
+  int64_t o = d.off[m];
+  R *Gm = G + o, *Um = U + o, *Vm = V + o;
+  double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red);
+  __syncthreads();
+  int64_t items = (int64_t)np * np + 2 * (int64_t)n * np;
+  int sw = 0;
+  bool conv = false;
+  for (; sw < max_sweeps && !conv; ++sw) {
+    for (int k = 0; k < n - 1; ++k) {
+      for (int q = threadIdx.x; q < np; q += BS) {
+        int i, j;
+        rr_pair(n, k, q, i, j);
+        spair[2 * q] = (int16_t)i;
+        spair[2 * q + 1] = (int16_t)j;
+        spar[q] = pivot_svd(Gm, n, i, j);
+      }
+      __syncthreads();
+      for (int64_t w = threadIdx.x; w < items; w += BS) {
+        update_item<R>(
+            w, n, Gm, Um, Vm,
+            [spair](int q, int &i, int &j) {
+              i = spair[2 * q];
+              j = spair[2 * q + 1];
+            },
+            [spar](int q) { return spar[q]; });
+      }
+      __syncthreads();
+    }
+    double off2 = block_sumsq(Gm, n, true, red);
+    conv = converged(off2, fro2, n, tolf, (double)Lim<R>::eps());
+  }
+  finish_matrix(Gm, n, sigma ? sigma + d.soff[m] : nullptr, sweeps_out ? sweeps_out + m : nullptr,
+                sw, conv);
+}
+
+// ------------------------------------------------------------ sigma gradient
+//
+// dG = U diag(dsigma) V^T per matrix (d sigma_i / dG = u_i v_i^T, summed with
+// weights dsigma_i): a 32x32 output tile per 256-lane workgroup, k-panels of
+// 32 staged through LDS, each lane accumulating 4 outputs of one column.
+
+template <class R>
+__global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, const R *U, const R *V,
+                                                    const R *ds, R *dG) {
+  __shared__ R su[32][33];  // U tile: rows r0.., columns k0..
+  __shared__ R sv[32][33];  // V tile scaled by ds: rows c0.., columns k0..
+  int m = blockIdx.z;
+  int n = d.n[m];
+  int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  if (r0 >= n || c0 >= n) return;
+  int64_t o = d.off[m];
+  const R *Um = U + o, *Vm = V + o, *dsm = ds + d.soff[m];
+  int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty in 0..7
+  R acc[4] = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < n; k0 += 32) {
+    for (int t = threadIdx.x; t < 32 * 32; t += 256) {
+      int rr = t & 31, kk = t >> 5;
+      int r = r0 + rr, c = c0 + rr, k = k0 + kk;
+      su[rr][kk] = (r < n && k < n) ? Um[r + (int64_t)k * n] : (R)0;
+      sv[rr][kk] = (c < n && k < n) ? Vm[c + (int64_t)k * n] * dsm[k] : (R)0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      R u = su[tx][kk];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a] = fma(u, sv[ty + 8 * a][kk], acc[a]);
+    }
+    __syncthreads();
+  }
+  R *out = dG + o;
+  for (int a = 0; a < 4; ++a) {
+    int r = r0 + tx, c = c0 + ty + 8 * a;
+    if (r < n && c < n) out[r + (int64_t)c * n] = acc[a];
+  }
+}
+
+// ----------------------------------------------------------------- host side
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+  size_t n, off, soff, poff, order, fro2, sweeps, done, par, pairs, total;
+};
+
+static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
+  WsLayout L;
+  size_t p = 0;
+  L.n = p;      p = align256(p + nmat * 4);
+  L.off = p;    p = align256(p + nmat * 8);
+  L.soff = p;   p = align256(p + nmat * 8);
+  L.poff = p;   p = align256(p + nmat * 8);
+  L.order = p;  p = align256(p + nmat * 4);
+  L.fro2 = p;   p = align256(p + nmat * 8);
+  L.sweeps = p; p = align256(p + nmat * 4);
+  L.done = p;   p = align256(p + nmat * 4);
+  L.par = p;    p = align256(p + npiv * 10 * w);
+  L.pairs = p;  p = align256(p + npiv * 4);
+  L.total = p;
+  return L;
+}
+
+// persistent-kernel tuning table: block size per (dtype, order bucket)
+struct Tune {
+  int block[2][5];
+};
+static Tune g_tune = {{{256, 256, 512, 1024, 1024}, {256, 256, 512, 1024, 1024}}};
+static std::mutex g_mu;
+
+static int bucket_of(int n) {
+  if (n <= 64) return 0;
+  if (n <= 128) return 1;
+  if (n <= 256) return 2;
+  if (n <= 512) return 3;
+  return 4;
+}
+
+template <class R> static size_t persistent_lds(int n) {
+  return kRed * sizeof(double) + (size_t)(n / 2) * sizeof(Piv<R>) + (size_t)(n / 2) * 4 + 16;
+}
+
+template <class R>
+static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int count, int maxn,
+                             int block, R *G, R *U, R *V, R *sigma, int32_t *sweeps_out,
+                             int max_sweeps, double tolf, int accumulate, hipStream_t st) {
+  size_t lds = persistent_lds<R>(maxn);
+  switch (block) {
+    case 256:
+      hipLaunchKernelGGL((k_sw_persistent<R, 256>), dim3(count), dim3(256), lds, st, d, mats_dev,
+                         G, U, V, sigma, sweeps_out, max_sweeps, tolf, accumulate);
+      break;
+    case 512:
+      hipLaunchKernelGGL((k_sw_persistent<R, 512>), dim3(count), dim3(512), lds, st, d, mats_dev,
+                         G, U, V, sigma, sweeps_out, max_sweeps, tolf, accumulate);
+      break;
+    case 1024:
+      hipLaunchKernelGGL((k_sw_persistent<R, 1024>), dim3(count), dim3(1024), lds, st, d,
+                         mats_dev, G, U, V, sigma, sweeps_out, max_sweeps, tolf, accumulate);
+      break;
+    default:
+      return fail(KSVD2_EINVAL, "unsupported block size %d", block);
+  }
+  return launch_status("kog_sweep persistent launch");
+}
+
+struct GraphKey {
+  int dtype, mode;
+  int64_t nmat;
+  const void *G, *U, *V, *sigma, *sweeps, *ws;
+  int max_sweeps, accumulate;
+  double tolf;
+  hipStream_t st;
+  std::vector<int32_t> n;
+  std::vector<int64_t> off;
+  int tune_hash;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(dtype, mode, nmat, G, U, V, sigma, sweeps, ws, max_sweeps, accumulate, tolf,
+                    st, n, off, tune_hash) <
+           std::tie(o.dtype, o.mode, o.nmat, o.G, o.U, o.V, o.sigma, o.sweeps, o.ws, o.max_sweeps,
+                    o.accumulate, o.tolf, o.st, o.n, o.off, o.tune_hash);
+  }
+};
+static std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+template <class R>
+static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                      R *G, R *U, R *V, R *sigma, int32_t *sweeps_out, int max_sweeps,
+                      double tolf, int accumulate, int mode, void *ws, size_t ws_bytes,
+                      hipStream_t st) {
+  if (nmat < 0) return fail(KSVD2_EINVAL, "nmat < 0");
+  if (nmat == 0) return KSVD2_OK;
+  if (!n_host || !off_host) return fail(KSVD2_EINVAL, "n_host and off_host are required");
+  if (max_sweeps < 0) return fail(KSVD2_EINVAL, "max_sweeps < 0");
+  if (mode < 0 || mode > 2) return fail(KSVD2_EINVAL, "mode must be 0, 1 or 2");
+  if (nmat > 65535) return fail(KSVD2_EINVAL, "at most 65535 matrices per call");
+  if (mode == 2 && st == nullptr)
+    return fail(KSVD2_EINVAL, "mode 2 (hipGraph) needs a non-null stream");
+  const size_t w = sizeof(R);
+  KSVD2_REQ(G, w); KSVD2_REQ(U, w); KSVD2_REQ(V, w); KSVD2_REQ(ws, 256);
+  KSVD2_OPT(sigma, w); KSVD2_OPT(sweeps_out, 4);
+  int64_t npiv = 0, stot = 0;
+  int maxn = 0;
+  std::vector<int64_t> soff(nmat), poff(nmat);
+  for (int64_t m = 0; m < nmat; ++m) {
+    int n = n_host[m];
+    if (n < 2 || (n & 1) || n > kMaxOrder)
+      return fail(KSVD2_EINVAL, "matrix %lld: order %d must be even, in [2, %d]", (long long)m,
+                  n, kMaxOrder);
+    if (off_host[m] < 0) return fail(KSVD2_EINVAL, "matrix %lld: negative offset", (long long)m);
+    soff[m] = stot;
+    poff[m] = npiv;
+    stot += n;
+    npiv += n / 2;
+    maxn = std::max(maxn, n);
+  }
+  WsLayout L = ws_layout(nmat, npiv, w);
+  if (ws_bytes < L.total)
+    return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  // longest matrices first (they have the most steps)
+  std::vector<int32_t> order(nmat);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return n_host[a] > n_host[b]; });
+  // stage the descriptor into the workspace (one host buffer, one copy)
+  std::vector<unsigned char> host(L.par, 0);
+  std::memcpy(host.data() + L.n, n_host, nmat * 4);
+  std::memcpy(host.data() + L.off, off_host, nmat * 8);
+  std::memcpy(host.data() + L.soff, soff.data(), nmat * 8);
+  std::memcpy(host.data() + L.poff, poff.data(), nmat * 8);
+  std::memcpy(host.data() + L.order, order.data(), nmat * 4);
+  unsigned char *wsb = static_cast<unsigned char *>(ws);
+  hipError_t e = hipMemcpyAsync(wsb, host.data(), L.par, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(KSVD2_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  SweepDesc d;
+  d.n = reinterpret_cast<const int32_t *>(wsb + L.n);
+  d.off = reinterpret_cast<const int64_t *>(wsb + L.off);
+  d.soff = reinterpret_cast<const int64_t *>(wsb + L.soff);
+  d.poff = reinterpret_cast<const int64_t *>(wsb + L.poff);
+  d.fro2 = reinterpret_cast<double *>(wsb + L.fro2);
+  d.sweeps = reinterpret_cast<int32_t *>(wsb + L.sweeps);
+  d.done = reinterpret_cast<int32_t *>(wsb + L.done);
+  const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
+
+  if (mode == 0) {
+    Piv<R> *par = reinterpret_cast<Piv<R> *>(wsb + L.par);
+    int16_t *pairs = reinterpret_cast<int16_t *>(wsb + L.pairs);
+    hipLaunchKernelGGL(k_sw_init<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, U, V,
+                       accumulate);
+    int rc = launch_status("kog_sweep init");
+    if (rc) return rc;
+    int maxnp = maxn / 2;
+    int64_t maxitems = (int64_t)maxnp * maxnp + 2 * (int64_t)maxn * maxnp;
+    std::vector<int32_t> done(nmat);
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      for (int k = 0; k < maxn - 1; ++k) {
+        hipLaunchKernelGGL(k_sw_pivots<R>, dim3(grid_for(maxnp), (unsigned)nmat), dim3(kBlock), 0,
+                           st, d, G, par, pairs, k);
+        hipLaunchKernelGGL(k_sw_update<R>, dim3(grid_for(maxitems), (unsigned)nmat),
+                           dim3(kBlock), 0, st, d, G, U, V, par, pairs, k);
+      }
+      hipLaunchKernelGGL(k_sw_check<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, tolf);
+      rc = launch_status("kog_sweep step");
+      if (rc) return rc;
+      e = hipMemcpyAsync(done.data(), d.done, nmat * 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return fail(KSVD2_EHIP, "convergence poll: %s", hipGetErrorString(e));
+      if (std::all_of(done.begin(), done.end(), [](int32_t v) { return v != 0; })) break;
+    }
+    hipLaunchKernelGGL(k_sw_finish<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, sigma,
+                       sweeps_out);
+    return launch_status("kog_sweep finish");
+  }
+
+  // modes 1 and 2: one persistent launch per order bucket, longest first
+  Tune tune;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    tune = g_tune;
+  }
+  int di = (w == 8) ? 1 : 0;
+  struct Seg {
+    int begin, count, maxn, block;
+  };
+  std::vector<Seg> segs;
+  for (int64_t a = 0; a < nmat;) {
+    int b0 = bucket_of(n_host[order[a]]);
+    int64_t bb = a;
+    while (bb < nmat && bucket_of(n_host[order[bb]]) == b0) ++bb;
+    segs.push_back(Seg{(int)a, (int)(bb - a), n_host[order[a]], tune.block[di][b0]});
+    a = bb;
+  }
+  auto launch_all = [&]() -> int {
+    for (const Seg &s : segs) {
+      int rc = launch_persistent<R>(d, order_dev + s.begin, s.count, s.maxn, s.block, G, U, V,
+                                    sigma, sweeps_out, max_sweeps, tolf, accumulate, st);
+      if (rc) return rc;
+    }
+    return KSVD2_OK;
+  };
+  if (mode == 1) return launch_all();
+
+  // mode 2: capture the launches once per argument set, then replay
+  GraphKey key{dtype, mode, nmat, G, U, V, sigma, sweeps_out, ws, max_sweeps, accumulate,
+               tolf, st, std::vector<int32_t>(n_host, n_host + nmat),
+               std::vector<int64_t>(off_host, off_host + nmat), 0};
+  for (int b = 0; b < 5; ++b) key.tune_hash = key.tune_hash * 31 + tune.block[di][b];
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+  }
+  if (!exec) {
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(KSVD2_EHIP, "graph capture: %s", hipGetErrorString(e));
+    int rc = launch_all();
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(KSVD2_EHIP, "graph capture end: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(KSVD2_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_graphs[key] = exec;
+  }
+  e = hipGraphLaunch(exec, st);
+  if (e != hipSuccess) return fail(KSVD2_EHIP, "graph launch: %s", hipGetErrorString(e));
+  return KSVD2_OK;
+}
+
+template <class R>
+static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                           const R *U, const R *V, const R *ds, R *dG, void *ws, size_t ws_bytes,
+                           hipStream_t st) {
+  if (nmat < 0) return fail(KSVD2_EINVAL, "nmat < 0");
+  if (nmat == 0) return KSVD2_OK;
+  if (!n_host || !off_host) return fail(KSVD2_EINVAL, "n_host and off_host are required");
+  if (nmat > 65535) return fail(KSVD2_EINVAL, "at most 65535 matrices per call");
+  const size_t w = sizeof(R);
+  KSVD2_REQ(U, w); KSVD2_REQ(V, w); KSVD2_REQ(ds, w); KSVD2_REQ(dG, w); KSVD2_REQ(ws, 256);
+  int maxn = 0;
+  int64_t stot = 0;
+  std::vector<int64_t> soff(nmat);
+  for (int64_t m = 0; m < nmat; ++m) {
+    int n = n_host[m];
+    if (n < 1 || n > kMaxOrder) return fail(KSVD2_EINVAL, "bad order %d", n);
+    soff[m] = stot;
+    stot += n;
+    maxn = std::max(maxn, n);
+  }
+  size_t need = align256(nmat * 4) + align256(nmat * 8) * 2;
+  if (ws_bytes < need) return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  std::vector<unsigned char> host(need, 0);
+  size_t o_n = 0, o_off = align256(nmat * 4), o_soff = o_off + align256(nmat * 8);
+  std::memcpy(host.data() + o_n, n_host, nmat * 4);
+  std::memcpy(host.data() + o_off, off_host, nmat * 8);
+  std::memcpy(host.data() + o_soff, soff.data(), nmat * 8);
+  unsigned char *wsb = static_cast<unsigned char *>(ws);
+  hipError_t e = hipMemcpyAsync(wsb, host.data(), need, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(KSVD2_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  SweepDesc d{};
+  d.n = reinterpret_cast<const int32_t *>(wsb + o_n);
+  d.off = reinterpret_cast<const int64_t *>(wsb + o_off);
+  d.soff = reinterpret_cast<const int64_t *>(wsb + o_soff);
+  unsigned t = (unsigned)((maxn + 31) / 32);
+  hipLaunchKernelGGL(k_sigma_grad<R>, dim3(t, t, (unsigned)nmat), dim3(256), 0, st, d, U, V, ds,
+                     dG);
+  return launch_status("kog_sigma_grad launch");
+}
+
+}  // namespace ksvd2
+
+using namespace ksvd2;
+
+extern "C" {
+
+size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host) {
+  if (nmat <= 0 || !n_host || (dtype != 0 && dtype != 1)) return 0;
+  int64_t npiv = 0;
+  for (int64_t m = 0; m < nmat; ++m) npiv += std::max(n_host[m], 0) / 2;
+  size_t a = ws_layout(nmat, npiv, dtype ? 8 : 4).total;
+  size_t b = align256(nmat * 4) + align256(nmat * 8) * 2;
+  return std::max(a, b);
+}
+
+int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                    void *G, void *U, void *V, void *sigma, int32_t *sweeps_out,
+                    int32_t max_sweeps, double tol_factor, int accumulate, int mode,
+                    void *workspace, size_t ws_bytes, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == 1)
+    return sweep_impl<double>(1, nmat, n_host, off_host, (double *)G, (double *)U, (double *)V,
+                              (double *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate,
+                              mode, workspace, ws_bytes, st);
+  if (dtype == 0)
+    return sweep_impl<float>(0, nmat, n_host, off_host, (float *)G, (float *)U, (float *)V,
+                             (float *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate, mode,
+                             workspace, ws_bytes, st);
+  return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+int kog_sweep_tune(int dtype, int bucket, int block) {
+  if (dtype != 0 && dtype != 1) return fail(KSVD2_EDTYPE, "dtype must be 0 or 1");
+  if (bucket < 0 || bucket > 4) return fail(KSVD2_EINVAL, "bucket must be in [0, 4]");
+  if (block != 256 && block != 512 && block != 1024)
+    return fail(KSVD2_EINVAL, "block must be 256, 512 or 1024");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tune.block[dtype][bucket] = block;
+  return KSVD2_OK;
+}
+
+int kog_sigma_grad(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                   const void *U, const void *V, const void *dsigma, void *dG, void *workspace,
+                   size_t ws_bytes, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == 1)
+    return sigma_grad_impl<double>(nmat, n_host, off_host, (const double *)U, (const double *)V,
+                                   (const double *)dsigma, (double *)dG, workspace, ws_bytes, st);
+  if (dtype == 0)
+    return sigma_grad_impl<float>(nmat, n_host, off_host, (const float *)U, (const float *)V,
+                                  (const float *)dsigma, (float *)dG, workspace, ws_bytes, st);
+  return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+}  // extern "C"

@@ -1,0 +1,748 @@
+// Device side of the enhanced Kogbetliantz SVD of order two (gfx950).
+//
+// One matrix per lane.  Everything here is straight-line scalar code in the
+// working precision W (double or float), with explicit fma and no contraction
+// (the library is built with -ffp-contract=off), IEEE division and square
+// root, and gradual underflow.  The paper's steps, in order (Sect. 3):
+//   phase 1  type/class of the zero pattern (eq. ts), prescaling by a power of
+//            two (eqs. eG, s), re-examination of the pattern, simple classes
+//            (Sect. 3.1);
+//   phase 2  error-free triangularisation of class 13 (Sect. 3.2.1) or the
+//            fully pivoted URV of class 15 with the wider-precision element
+//            (Sect. 3.2.2, eqs. QR15, EXT, Theorem R);
+//   phase 3  SVD of the triangular factor (Sect. 3.3.1, Algorithms tf, tp),
+//            assembly with the left-vector heuristic (Sect. 3.3.2, eqs. p+t,
+//            p-t, tan+-, UV) and backscaling in (e,f) form.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ksvd2 {
+
+// ---------------------------------------------------------------------------
+// Format constants (Sect. 2): p, eps = 2^-p, e_mu, e_nu.
+// ---------------------------------------------------------------------------
+template <class R> struct Lim;
+template <> struct Lim<double> {
+  static constexpr int p = 53, e_mu = -1022, e_nu = 1023;
+  __device__ static double mu() { return 0x1p-1022; }
+  __device__ static double nu() { return 0x1.fffffffffffffp+1023; }
+  __device__ static double eps() { return 0x1p-53; }
+};
+template <> struct Lim<float> {
+  static constexpr int p = 24, e_mu = -126, e_nu = 127;
+  __device__ static float mu() { return 0x1p-126f; }
+  __device__ static float nu() { return 0x1.fffffep+127f; }
+  __device__ static float eps() { return 0x1p-24f; }
+};
+
+// floor(lg|x|) for finite x != 0 (also for subnormal x).
+__device__ inline int ilog2(double x) {
+  int e;
+  (void)frexp(x, &e);
+  return e - 1;
+}
+__device__ inline int ilog2(float x) {
+  int e;
+  (void)frexpf(x, &e);
+  return e - 1;
+}
+
+// x 2^n rounded once to nearest-even, as IEEE scaleB: exact while the result
+// is normal, gradual underflow below that, +-inf on overflow.
+__device__ inline double scale2(double x, int n) {
+  if (x == 0.0) return x;
+  int r = ilog2(x) + n;
+  if (r >= -1022) return ldexp(x, n);
+  if (r < -1075) return copysign(0.0, x);
+  return ldexp(x, n + 128) * 0x1p-128;  // exact step, then one IEEE rounding
+}
+__device__ inline float scale2(float x, int n) {
+  if (x == 0.0f) return x;
+  int r = ilog2(x) + n;
+  if (r >= -126) return ldexpf(x, n);
+  if (r < -150) return copysignf(0.0f, x);
+  return ldexpf(x, n + 64) * 0x1p-64f;
+}
+
+__device__ inline double ldexp_w(double x, int n) { return ldexp(x, n); }
+__device__ inline double frexp_w(double x, int *e) { return frexp(x, e); }
+__device__ inline float frexp_w(float x, int *e) { return frexpf(x, e); }
+__device__ inline float ldexp_w(float x, int n) { return ldexpf(x, n); }
+
+// ---------------------------------------------------------------------------
+// Error-free transformations (Dekker/Knuth; Joldes-Muller-Popescu 2017).
+// ---------------------------------------------------------------------------
+__device__ inline void two_sum(double a, double b, double &s, double &t) {
+  s = a + b;
+  double bb = s - a;
+  double aa = s - bb;
+  t = (a - aa) + (b - bb);
+}
+__device__ inline void fast_two_sum(double a, double b, double &s, double &t) {
+  s = a + b;
+  t = b - (s - a);
+}
+__device__ inline void two_prod(double a, double b, double &p, double &e) {
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// Exact sign of the sum of n doubles (Shewchuk's grow-expansion: the
+// components stay non-overlapping, so the sign of the sum is the sign of the
+// most significant non-zero component).  Used only on rare rounding-boundary
+// paths.
+__device__ __attribute__((noinline)) int exact_sign(double t0, double t1, double t2, double t3,
+                                                    double t4, double t5, double t6, double t7) {
+  const double t[8] = {t0, t1, t2, t3, t4, t5, t6, t7};
+  double e[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double q = t[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      double s, r;
+      two_sum(q, e[j], s, r);
+      e[j] = r;
+      q = s;
+    }
+    e[i] = q;
+  }
+  int sg = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (e[j] != 0.0) sg = e[j] > 0.0 ? 1 : -1;
+  return sg;
+}
+
+__device__ inline bool even_sig(double y) { return (__double_as_longlong(y) & 1) == 0; }
+__device__ inline bool even_sig(float y) { return (__float_as_uint(y) & 1u) == 0; }
+
+// ---------------------------------------------------------------------------
+// Correctly rounded hypot, binary64.
+//   hi >= lo > 0; once the exponent gap exceeds 30 the result is hi.
+//   Both subnormal: the result lies on the 2^-1074 grid; integer rounding of
+//   sqrt(H^2 + L^2) with an exact sign test (no ties are possible there).
+//   Otherwise scale hi into [1,2) (exact), form S = A^2 + B^2 as a double-word,
+//   y = RN(sqrt(RN(S))) is within one ulp of the answer; the residual
+//   t = S - y^2 (error < 2^-99) is compared with the squared rounding midpoints
+//   around y; only when t is within 2^-98 of one does an exact expansion sign
+//   test decide (this includes exact ties, e.g. Pythagorean midpoints).
+// ---------------------------------------------------------------------------
+__device__ __attribute__((noinline)) double hypot_tiny(double hi, double lo) {
+  double H = ldexp(hi, 1074), L = ldexp(lo, 1074);  // integers < 2^52, exact
+  double p, pe, q, qe;
+  two_prod(H, H, p, pe);
+  two_prod(L, L, q, qe);
+  double k = rint(sqrt(p + q));
+  double kk, kke;
+  two_prod(k, k, kk, kke);
+  // S - k^2 - k > 0  <=>  sqrt(S) > k + 1/2 (S integer, so never a tie)
+  if (exact_sign(p, pe, q, qe, -kk, -kke, -k, 0.0) > 0) {
+    k += 1.0;
+  } else if (exact_sign(p, pe, q, qe, -kk, -kke, k, 0.0) <= 0) {
+    k -= 1.0;  // S <= k^2 - k  <=>  sqrt(S) < k - 1/2
+  }
+  return k * 0x1p-1074;
+}
+
+__device__ __attribute__((noinline)) double hypot_resolve(double p, double pe, double q,
+                                                          double qe, double y, double up_gap,
+                                                          double dn_gap) {
+  // sign(S - m^2) at the upper midpoint m = y + up_gap/2, then at the lower one
+  double yy, yye;
+  two_prod(y, y, yy, yye);
+  double h = 0.5 * up_gap;
+  int cu = exact_sign(p, pe, q, qe, -yy, -yye, -2.0 * y * h, -h * h);
+  if (cu > 0) return y + up_gap;
+  if (cu == 0) return even_sig(y) ? y : y + up_gap;
+  h = 0.5 * dn_gap;
+  int cd = exact_sign(p, pe, q, qe, -yy, -yye, 2.0 * y * h, -h * h);
+  if (cd < 0) return y - dn_gap;
+  if (cd == 0) return even_sig(y) ? y : y - dn_gap;
+  return y;
+}
+
+__device__ __attribute__((always_inline)) inline double hypot_cr(double x, double y) {
+  double a = fabs(x), b = fabs(y);
+  double hi = fmax(a, b), lo = fmin(a, b);
+  if (lo == 0.0 || isinf(hi)) return hi;
+  int eh = ilog2(hi), el = ilog2(lo);
+  if (eh - el > 30) return hi;
+  if (eh < -1022) return hypot_tiny(hi, lo);
+  double A = ldexp(hi, -eh), B = ldexp(lo, -eh);  // A in [1,2), B >= 2^-31: exact
+  double p, pe, q, qe;
+  two_prod(A, A, p, pe);
+  two_prod(B, B, q, qe);
+  double sh = p + q;                     // p >= q: Fast2Sum
+  double sl = (q - (sh - p)) + (pe + qe);
+  double r = sqrt(sh + sl);              // within one ulp of sqrt(S)
+  double rr, rre;
+  two_prod(r, r, rr, rre);
+  double t = ((sh - rr) - rre) + sl;     // S - r^2 (sh - rr is exact)
+  double u = (r >= 2.0) ? 0x1p-51 : 0x1p-52;               // ulp(r)
+  double gdn = (r == 1.0 || r == 2.0) ? 0.5 * u : u;        // r - pred(r)
+  double tup = fma(r, u, 0.25 * u * u);                     // (r+u/2)^2 - r^2
+  double tdn = fma(-r, gdn, 0.25 * gdn * gdn);              // (r-gdn/2)^2 - r^2
+  const double M = 0x1p-98;
+  double res;
+  if (t > tup + M) {
+    res = r + u;
+  } else if (t < tdn - M) {
+    res = r - gdn;
+  } else if (t >= tup - M || t <= tdn + M) {
+    res = hypot_resolve(p, pe, q, qe, r, u, gdn);
+  } else {
+    res = r;
+  }
+  return ldexp(res, eh);
+}
+
+// ---------------------------------------------------------------------------
+// Correctly rounded hypot, binary32: evaluate in binary64 (squares exact), round
+// to binary32, and settle the one float midpoint that can separate the binary64
+// value from the exact one by an exact sign test of S - m^2 (hi^2 - m^2 is
+// exact in binary64, so only the addition of lo^2 rounds, which keeps the sign).
+// ---------------------------------------------------------------------------
+__device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y) {
+  double a = fabs((double)x), b = fabs((double)y);
+  double hi = fmax(a, b), lo = fmin(a, b);
+  double S = fma(hi, hi, lo * lo);
+  double r = sqrt(S);
+  float f = (float)r;
+  double fd = isinf(f) ? 0x1p128 : (double)f;  // +inf stands for 2^128 here
+  if (fd == r) return f;
+  bool above = r > fd;
+  float g;
+  double gd;
+  if (above) {
+    if (f == 0x1.fffffep+127f) {
+      g = __int_as_float(0x7f800000);
+      gd = 0x1p128;
+    } else {
+      g = __uint_as_float(__float_as_uint(f) + 1u);
+      gd = (double)g;
+    }
+  } else {
+    g = __uint_as_float(__float_as_uint(f) - 1u);  // f > 0 here
+    gd = (double)g;
+  }
+  double m = (fd + gd) * 0.5;
+  double sgn = fma(-m, m, hi * hi) + lo * lo;  // sign of S - m^2, exactly
+  if (above) {
+    if (sgn > 0.0) return g;
+    if (sgn == 0.0) return even_sig(f) ? f : g;
+    return f;
+  }
+  if (sgn < 0.0) return g;
+  if (sgn == 0.0) return even_sig(f) ? f : g;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// (e,f) pairs (Sect. 2, eqs. unary, binary, plus, minus, prec).
+// ---------------------------------------------------------------------------
+template <class R> struct EF {
+  int e;
+  R f;
+};
+
+template <class R> __device__ inline EF<R> nrm(R x) {  // N(x)
+  EF<R> r;
+  if (x == (R)0) {
+    r.e = 0;
+    r.f = (R)0;
+  } else {
+    int e;
+    R m = frexp_w(x, &e);  // x = m 2^e, |m| in [1/2, 1)
+    r.e = e - 1;
+    r.f = m * (R)2;
+  }
+  return r;
+}
+
+template <class R> __device__ inline R flo(EF<R> x) { return scale2(x.f, x.e); }  // fl(w)
+
+template <class R> __device__ inline EF<R> ef_twice(EF<R> x) {  // 2 (.) x
+  if (x.f != (R)0) x.e += 1;
+  return x;
+}
+
+template <class R> __device__ inline EF<R> ef_mul(EF<R> x, EF<R> y) {
+  EF<R> z = nrm(x.f * y.f);
+  if (z.f != (R)0) z.e += x.e + y.e;
+  return z;
+}
+
+template <class R> __device__ inline EF<R> ef_div(EF<R> x, EF<R> y) {
+  EF<R> z = nrm(x.f / y.f);
+  if (z.f != (R)0) z.e += x.e - y.e;
+  return z;
+}
+
+template <class R> __device__ inline EF<R> ef_plus(R x, R y) {  // x, y > 0
+  R z = x + y;
+  if (z <= Lim<R>::nu()) return nrm(z);
+  EF<R> w = nrm(x * (R)0.5 + y * (R)0.5);
+  w.e += 1;
+  return w;
+}
+
+template <class R> __device__ inline EF<R> ef_minus(R x, R y) {  // x, y > 0
+  EF<R> w;
+  if (x == y) {
+    w.e = 0;
+    w.f = (R)0;
+    return w;
+  }
+  R z = x - y;
+  if (fabs(z) >= Lim<R>::mu()) return nrm(z);
+  int lx = ilog2(x), ly = ilog2(y);
+  int c = Lim<R>::e_mu + Lim<R>::p - 1 - (lx < ly ? lx : ly);
+  w = nrm(ldexp_w(x, c) - ldexp_w(y, c));  // upscaling: exact
+  w.e -= c;
+  return w;
+}
+
+template <class R> __device__ inline int sign3(R f) { return (f > (R)0) - (f < (R)0); }
+
+template <class R> __device__ inline bool ef_prec(EF<R> x, EF<R> y) {
+  int sx = sign3(x.f), sy = sign3(y.f);
+  if (sx != sy) return sx < sy;
+  return (x.e < y.e) || (x.e == y.e && x.f < y.f);
+}
+
+// ---------------------------------------------------------------------------
+// The wider-precision element of eq. (EXT):
+//   fl(FL(FL(x1 y1 + x2 y2) / d))    (subtraction: the caller negates x2).
+// binary32: T = binary64 (products exact, sum and quotient rounded in binary64,
+// then one rounding to binary32).
+// binary64: T = double-word.  Both products are formed exactly from the
+// factors' mantissas; both are scaled by the larger product's exponent;
+// AccurateDWPlusDW, then DWDivFP3 by d's mantissa (Joldes-Muller-Popescu 2017,
+// Algorithms 6 and 15); the leading word is scaled back with one rounding.
+// ---------------------------------------------------------------------------
+__device__ inline float ext_w(float x1, float y1, float x2, float y2, float d) {
+  double s = (double)x1 * (double)y1 + (double)x2 * (double)y2;
+  return (float)(s / (double)d);
+}
+
+__device__ __attribute__((always_inline)) inline double ext_w(double x1, double y1, double x2, double y2,
+                                                             double d) {
+  int a1 = ilog2(x1), b1 = ilog2(y1), a2 = ilog2(x2), b2 = ilog2(y2);
+  int k1 = a1 + b1, k2 = a2 + b2;
+  int K = k1 > k2 ? k1 : k2;
+  double p1h, p1l, p2h, p2l;
+  two_prod(ldexp(x1, -a1), ldexp(y1, -b1), p1h, p1l);
+  two_prod(ldexp(x2, -a2), ldexp(y2, -b2), p2h, p2l);
+  p1h = scale2(p1h, k1 - K);
+  p1l = scale2(p1l, k1 - K);
+  p2h = scale2(p2h, k2 - K);
+  p2l = scale2(p2l, k2 - K);
+  // AccurateDWPlusDW
+  double sh, sl, th, tl, vh, vl, xh, xl;
+  two_sum(p1h, p2h, sh, sl);
+  two_sum(p1l, p2l, th, tl);
+  fast_two_sum(sh, sl + th, vh, vl);
+  fast_two_sum(vh, tl + vl, xh, xl);
+  if (xh == 0.0) return 0.0;
+  // DWDivFP3 by the mantissa of d
+  int ed = ilog2(d);
+  double dm = ldexp(d, -ed);
+  double qh = xh / dm;
+  double ph, pl;
+  two_prod(qh, dm, ph, pl);
+  double dl = ((xh - ph) + (xl - pl)) / dm;
+  double zh, zl;
+  fast_two_sum(qh, dl, zh, zl);
+  return scale2(zh, K - ed);
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 matrices as four registers, [a b; c d] (row-major), with the exact
+// signed-permutation operations used to assemble U and V.
+// ---------------------------------------------------------------------------
+template <class R> struct M2 {
+  R a, b, c, d;
+};
+template <class R> __device__ inline M2<R> mrot(R c, R s) { return M2<R>{c, -s, s, c}; }
+template <class R> __device__ inline M2<R> mid() { return M2<R>{(R)1, (R)0, (R)0, (R)1}; }
+template <class R> __device__ inline void swap_rows(M2<R> &m) {
+  R t = m.a; m.a = m.c; m.c = t;
+  t = m.b; m.b = m.d; m.d = t;
+}
+template <class R> __device__ inline void swap_cols(M2<R> &m) {
+  R t = m.a; m.a = m.b; m.b = t;
+  t = m.c; m.c = m.d; m.d = t;
+}
+template <class R> __device__ inline void neg_row(M2<R> &m, int i) {
+  if (i == 0) { m.a = -m.a; m.b = -m.b; } else { m.c = -m.c; m.d = -m.d; }
+}
+template <class R> __device__ inline void neg_col(M2<R> &m, int j) {
+  if (j == 0) { m.a = -m.a; m.c = -m.c; } else { m.b = -m.b; m.d = -m.d; }
+}
+
+template <class R> __device__ inline bool negative(R x) { return x < (R)0; }
+
+// Result of one 2x2 SVD: U = [cu, -dU su; su, dU cu], V likewise, sigma_i =
+// f_i 2^e_i (sigma1 >= sigma2 >= 0), info bits as in the public header.
+template <class R> struct Svd2 {
+  R cu, su, cv, sv, f1, f2;
+  int e1, e2;
+  uint32_t info;
+};
+
+enum : uint32_t {
+  I_DETU = 1u << 8, I_DETV = 1u << 9, I_EXT = 1u << 10, I_RSWAP = 1u << 11,
+  I_TPSI_OVF = 1u << 12, I_PSIG = 1u << 13, I_DEGEN = 1u << 14, I_NONFINITE = 1u << 15,
+};
+
+// class masks over the 16 types of eq. (ts)
+constexpr uint32_t CL9 = (1u << 0) | (1u << 1) | (1u << 2) | (1u << 4) | (1u << 6) | (1u << 8) |
+                         (1u << 9);
+constexpr uint32_t CL3 = (1u << 3) | (1u << 12);
+constexpr uint32_t CL5 = (1u << 5) | (1u << 10);
+constexpr uint32_t CL13 = (1u << 7) | (1u << 11) | (1u << 13) | (1u << 14);
+
+template <class R> __device__ inline int ztype(R g11, R g21, R g12, R g22) {
+  return (g11 != (R)0) | ((g21 != (R)0) << 1) | ((g12 != (R)0) << 2) | ((g22 != (R)0) << 3);
+}
+
+// A partial SVD of a (prescaled) matrix: G' = U diag(s1, s2) V^T.
+template <class R> struct Part {
+  M2<R> U, V;
+  EF<R> s1, s2;
+};
+
+// Sect. 3.1, class 9: at most one permutation per side into the 0/1/9 form
+// with |d11| >= |d22|; row signs go into U (U = P_U S, V = P_V).
+template <class R> __device__ __attribute__((always_inline)) Part<R> part9(M2<R> G, int t) {
+  bool pu = false, pv = false;
+  if (t == 2) pu = true;
+  else if (t == 4) pv = true;
+  else if (t == 8) pu = pv = true;
+  else if (t == 6) {
+    if (fabs(G.c) >= fabs(G.b)) pu = true; else pv = true;
+  } else if (t == 9) {
+    if (fabs(G.a) < fabs(G.d)) pu = pv = true;
+  }
+  M2<R> D = G;
+  if (pu) swap_rows(D);
+  if (pv) swap_cols(D);
+  Part<R> r;
+  r.U = mid<R>();
+  if (negative(D.a)) neg_col(r.U, 0);
+  if (negative(D.d)) neg_col(r.U, 1);
+  if (pu) swap_rows(r.U);
+  r.V = mid<R>();
+  if (pv) swap_rows(r.V);
+  r.s1 = nrm(fabs(D.a));
+  r.s2 = nrm(fabs(D.d));
+  return r;
+}
+
+// cos and sin of the Givens angle from its tangent (eq. Givens, Lemma sincostheta)
+template <class R> __device__ inline M2<R> givens(R tn) {
+  R sec = hypot_cr(tn, (R)1);
+  return mrot((R)1 / sec, tn / sec);
+}
+
+// Sect. 3.1, classes 3 (one non-zero column) and 5 (one non-zero row).
+template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R> G, int t) {
+  bool col = (t == 3 || t == 12);
+  bool pfirst = (t == 12 || t == 10);  // P_V for t = 12, P_U for t = 10
+  R a, b;
+  if (col) { a = pfirst ? G.b : G.a; b = pfirst ? G.d : G.c; }
+  else { a = pfirst ? G.c : G.a; b = pfirst ? G.d : G.b; }
+  bool na = negative(a), nb = negative(b);
+  a = fabs(a);
+  b = fabs(b);
+  bool sw = a < b;
+  if (sw) { R t2 = a; a = b; b = t2; }
+  M2<R> W = givens(b / a);
+  if (sw) swap_rows(W);
+  if (na) neg_row(W, 0);
+  if (nb) neg_row(W, 1);
+  M2<R> P = mid<R>();
+  if (pfirst) swap_rows(P);
+  Part<R> r;
+  if (col) { r.U = W; r.V = P; } else { r.U = P; r.V = W; }
+  r.s1 = nrm(hypot_cr(a, b));
+  r.s2 = nrm((R)0);
+  return r;
+}
+
+// The SVD of R~ = [a b; 0 d], a >= d > 0, b > 0 (Sect. 3.3.1).
+template <class R> struct Tri {
+  R cphi, sphi, tphi, cpsi, spsi, tpsi;
+  EF<R> s1, s2;
+  bool psig, ovf;
+};
+
+template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a, R b, R d) {
+  const R inf = (R)INFINITY;
+  Tri<R> o;
+  // Algorithm tf: tan(2 phi), cases in their listed order
+  R t2;
+  if (a == d) {
+    t2 = ((R)2 * d) / b;  // eq. t2f''
+  } else if (b == d) {    // eq. t2f'''
+    t2 = flo(ef_div(ef_mul(ef_twice(nrm(b)), nrm(d)), ef_mul(nrm(a), nrm(a))));
+  } else if (a / b < Lim<R>::eps()) {
+    t2 = ((R)2 * d) / b;  // eq. t2f''
+  } else {
+    R h = hypot_cr(a, b);
+    if (h == d) {
+      t2 = inf;
+    } else {
+      EF<R> sm = ef_plus(h, d), df = ef_minus(h, d);
+      t2 = flo(ef_div(ef_mul(ef_twice(nrm(b)), nrm(d)), ef_mul(df, sm)));
+    }
+  }
+  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hypot_cr(t2, (R)1));  // eq. tf
+  R sphi_sec = hypot_cr(tphi, (R)1);
+  o.tphi = tphi;
+  o.cphi = (R)1 / sphi_sec;
+  o.sphi = tphi / sphi_sec;
+  // Algorithm tp
+  R tt = fma(d, tphi, b);
+  R tpsi = tt / a;
+  o.tpsi = tpsi;
+  EF<R> s1, s2;
+  if (tpsi == inf) {  // eq. tp' and the sigma assignment of Algorithm tp
+    o.ovf = true;
+    EF<R> et = nrm(tt);
+    EF<R> bcos = ef_div(nrm(a), et);
+    o.cpsi = flo(bcos);
+    o.spsi = (R)1;
+    s1 = et;
+    s2 = ef_mul(nrm(d), bcos);
+  } else {  // eq. s'
+    o.ovf = false;
+    R spsi_sec = hypot_cr(tpsi, (R)1);
+    o.cpsi = (R)1 / spsi_sec;
+    o.spsi = tpsi / spsi_sec;
+    EF<R> sp = ef_div(nrm(sphi_sec), nrm(spsi_sec));
+    s1 = ef_div(nrm(a), sp);
+    s2 = ef_mul(nrm(d), sp);
+  }
+  o.psig = ef_prec(s1, s2);
+  o.s1 = o.psig ? s2 : s1;
+  o.s2 = o.psig ? s1 : s2;
+  return o;
+}
+
+template <class R> __device__ inline void put_uv(const M2<R> &U, R &c, R &s, bool &neg) {
+  R det = U.a * U.d - U.b * U.c;
+  neg = det < (R)0;
+  c = U.a + (R)0;  // canonical zero: -0 -> +0
+  s = U.c + (R)0;
+}
+
+// The whole method for one matrix.
+template <class R> __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g22) {
+  Svd2<R> out;
+  int t = ztype(g11, g21, g12, g22);
+  if (!(isfinite(g11) && isfinite(g21) && isfinite(g12) && isfinite(g22))) {
+    R nan = (R)NAN;
+    out.cu = out.su = out.cv = out.sv = out.f1 = out.f2 = nan;
+    out.e1 = out.e2 = 0;
+    out.info = (uint32_t)t | I_NONFINITE;
+    return out;
+  }
+  // phase 1: prescaling (class 9 is not scaled)
+  int s = 0;
+  uint32_t tb = 1u << t;
+  if (!(tb & CL9)) {
+    int eg = -0x7fffffff;
+    if (g11 != (R)0) eg = max(eg, ilog2(g11));
+    if (g21 != (R)0) eg = max(eg, ilog2(g21));
+    if (g12 != (R)0) eg = max(eg, ilog2(g12));
+    if (g22 != (R)0) eg = max(eg, ilog2(g22));
+    int stype = (t == 15) ? 2 : 1;
+    s = Lim<R>::e_nu - eg - stype;
+  }
+  M2<R> G;
+  if (s >= 0) {
+    G = M2<R>{ldexp_w(g11, s), ldexp_w(g12, s), ldexp_w(g21, s), ldexp_w(g22, s)};
+  } else {  // s in {-1, -2}: one IEEE rounding each
+    R f = (s == -1) ? (R)0.5 : (R)0.25;
+    G = M2<R>{g11 * f, g12 * f, g21 * f, g22 * f};
+  }
+  int t1 = ztype(G.a, G.c, G.b, G.d);
+  uint32_t tb1 = 1u << t1;
+  uint32_t info = (uint32_t)t | ((uint32_t)t1 << 4);
+
+  Part<R> part;
+  bool tri = false;
+  R r11 = 0, r12 = 0, r22 = 0;
+  M2<R> Up = mid<R>(), Vp = mid<R>();  // U_+ (class 13) and V_+
+  // class 15 pieces kept for the heuristic
+  R tan_t = 0, sec_t = 1;
+  bool s1n0 = false, s1n1 = false, pu15 = false, s22neg = false;
+
+  if (tb1 & (CL9 | CL3 | CL5)) {
+    part = (tb1 & CL9) ? part9(G, t1) : part35(G, t1);
+  } else if (tb1 & CL13) {
+    // Sect. 3.2.1: permute into [x y; 0 z], then three sign changes
+    bool pu = (t1 == 14 || t1 == 11), pv = (t1 == 7 || t1 == 11);
+    M2<R> H = G;
+    if (pu) swap_rows(H);
+    if (pv) swap_cols(H);
+    bool nx = negative(H.a);
+    R y = nx ? -H.b : H.b;
+    bool ny = negative(y);
+    R z = ny ? -H.d : H.d;
+    bool nz = negative(z);
+    r11 = fabs(H.a);
+    r12 = fabs(y);
+    r22 = fabs(z);
+    // U_+ = P_U S11 S22 = P_U diag(sgn x, sgn z'), V_+ = P_V S12 = P_V diag(1, sgn y')
+    if (nx) neg_col(Up, 0);
+    if (nz) neg_col(Up, 1);
+    if (pu) swap_rows(Up);
+    if (ny) neg_col(Vp, 1);
+    if (pv) swap_rows(Vp);
+    tri = true;
+  } else {
+    // Sect. 3.2.2: class 15, the fully pivoted URV
+    R w1 = hypot_cr(G.a, G.c), w2 = hypot_cr(G.b, G.d);
+    bool pv = w1 < w2;
+    if (pv) {
+      R tw = w1; w1 = w2; w2 = tw;
+      swap_cols(G);
+    }
+    s1n0 = negative(G.a);
+    s1n1 = negative(G.c);
+    if (s1n0) { G.a = -G.a; G.b = -G.b; }
+    if (s1n1) { G.c = -G.c; G.d = -G.d; }
+    pu15 = G.a < G.c;
+    if (pu15) swap_rows(G);
+    // G''' = [G.a G.b; G.c G.d], G.a >= G.c > 0
+    tan_t = G.c / G.a;
+    sec_t = hypot_cr(tan_t, (R)1);
+    r11 = w1;
+    bool exact = fma(-tan_t, G.a, G.c) == (R)0;
+    bool same = negative(G.b) == negative(G.d);
+    // the element without cancellation: r12 (same signs) or r22 (opposite)
+    R P = same ? G.d : -G.b, Q = same ? G.b : G.d;
+    R rgood = fma(P, tan_t, Q) / sec_t;
+    R rother;
+    if (exact) {
+      R P2 = same ? -G.b : G.d, Q2 = same ? G.d : G.b;
+      rother = fma(P2, tan_t, Q2) / sec_t;
+    } else {
+      // eq. EXT: r22 = (g22 g11 - g12 g21)/g11/sec or r12 = (g12 g11 + g22 g21)/g11/sec
+      R x1 = same ? G.d : G.b, x2 = same ? -G.b : G.d;
+      rother = ext_w(x1, G.a, x2, G.c, G.a) / sec_t;
+      info |= I_EXT;
+    }
+    r12 = same ? rgood : rother;
+    r22 = same ? rother : rgood;
+    Vp = mid<R>();
+    if (pv) swap_rows(Vp);
+    if (r12 == (R)0 || r22 == (R)0) {
+      // a zero appeared: R'' = [r11 r12; 0 r22] is of type 9/1 or 5 and is
+      // finished as in Sect. 3.1; U = S_1 P_U U_theta U_R, V = P_V V_R
+      info |= I_DEGEN;
+      M2<R> Rpp = M2<R>{r11, r12, (R)0, r22};
+      int t2 = ztype(Rpp.a, Rpp.c, Rpp.b, Rpp.d);
+      part = (t2 == 5) ? part35(Rpp, t2) : part9(Rpp, t2);
+      M2<R> Ut = givens(tan_t);
+      // Ut * U_R: U_R is a signed permutation, apply its columns to Ut
+      M2<R> UR = part.U;
+      M2<R> U2 = M2<R>{Ut.a * UR.a + Ut.b * UR.c, Ut.a * UR.b + Ut.b * UR.d,
+                       Ut.c * UR.a + Ut.d * UR.c, Ut.c * UR.b + Ut.d * UR.d};
+      if (pu15) swap_rows(U2);
+      if (s1n0) neg_row(U2, 0);
+      if (s1n1) neg_row(U2, 1);
+      M2<R> VR = part.V;
+      if (pv) swap_rows(VR);
+      part.U = U2;
+      part.V = VR;
+    } else {
+      bool n12 = negative(r12);
+      if (n12) { r22 = -r22; neg_col(Vp, 1); }
+      r12 = fabs(r12);
+      s22neg = negative(r22);
+      r22 = fabs(r22);
+      tri = true;
+    }
+  }
+
+  if (tri) {
+    // phase 3: swap the diagonal through R^T (eq. RT) if r11 < r22
+    bool swp = r11 < r22;
+    if (swp) info |= I_RSWAP;
+    Tri<R> tr = swp ? tri_svd(r22, r12, r11) : tri_svd(r11, r12, r22);
+    if (tr.ovf) info |= I_TPSI_OVF;
+    if (tr.psig) info |= I_PSIG;
+    // U_bphi and V_bpsi of eq. RT (S2 = diag(1,-1) when swapped)
+    M2<R> Ub = swp ? mrot(tr.spsi, tr.cpsi) : mrot(tr.cphi, tr.sphi);
+    M2<R> Vb = swp ? mrot(tr.sphi, tr.cphi) : mrot(tr.cpsi, tr.spsi);
+    if (swp) {
+      neg_col(Ub, 1);
+      neg_col(Vb, 1);
+    }
+    M2<R> U;
+    if (tb1 & CL13) {
+      // U = U_+ U_bphi P_sigma: U_+ is a signed permutation
+      U = M2<R>{Up.a * Ub.a + Up.b * Ub.c, Up.a * Ub.b + Up.b * Ub.d,
+                Up.c * Ub.a + Up.d * Ub.c, Up.c * Ub.b + Up.d * Ub.d};
+    } else {
+      // class 15: merge U_theta and U_bphi into one rotation by tan(bphi +- theta)
+      R tbp = swp ? (R)1 / tr.tpsi : tr.tphi;
+      R ca, sa;
+      if (isinf(tbp)) {
+        R ct = (R)1 / sec_t, st = tan_t / sec_t;
+        ca = s22neg ? st : -st;
+        sa = ct;
+      } else {
+        R num = s22neg ? tbp - tan_t : tbp + tan_t;
+        R den = fma(s22neg ? tbp : -tbp, tan_t, (R)1);
+        if (den == (R)0) {
+          ca = (R)0;
+          sa = negative(num) ? (R)-1 : (R)1;
+        } else {
+          R ta = num / den;
+          R sa_sec = hypot_cr(ta, (R)1);
+          R sd = negative(den) ? (R)-1 : (R)1;
+          ca = sd * ((R)1 / sa_sec);
+          sa = sd * (ta / sa_sec);
+        }
+      }
+      U = mrot(ca, sa);
+      if (swp) neg_col(U, 1);     // S2
+      if (s22neg) neg_row(U, 1);  // S22 on the left
+      if (pu15) swap_rows(U);
+      if (s1n0) neg_row(U, 0);
+      if (s1n1) neg_row(U, 1);
+    }
+    M2<R> V = M2<R>{Vp.a * Vb.a + Vp.b * Vb.c, Vp.a * Vb.b + Vp.b * Vb.d,
+                    Vp.c * Vb.a + Vp.d * Vb.c, Vp.c * Vb.b + Vp.d * Vb.d};
+    if (tr.psig) {
+      swap_cols(U);
+      swap_cols(V);
+    }
+    part.U = U;
+    part.V = V;
+    part.s1 = tr.s1;
+    part.s2 = tr.s2;
+  }
+
+  // backscale: sigma_i = 2^-s (.) sigma~_i' (Sect. 3.3.2)
+  bool nu_, nv_;
+  put_uv(part.U, out.cu, out.su, nu_);
+  put_uv(part.V, out.cv, out.sv, nv_);
+  if (nu_) info |= I_DETU;
+  if (nv_) info |= I_DETV;
+  out.f1 = part.s1.f;
+  out.f2 = part.s2.f;
+  out.e1 = (part.s1.f != (R)0) ? part.s1.e - s : 0;
+  out.e2 = (part.s2.f != (R)0) ? part.s2.e - s : 0;
+  out.info = info | ((uint32_t)(uint16_t)(int16_t)s << 16);
+  return out;
+}
+
+}  // namespace ksvd2

@@ -1,0 +1,246 @@
+// Batched kernels of the 2x2 SVD and its adjoint, and their C ABI entry points
+// (declared and documented in include/ksvd2.h).
+//
+// Launch shape: one matrix per lane, 256-lane workgroups (4 waves of 64), a
+// 1-D grid of ceil(B/256) workgroups, so a 2^24 batch is 65,536 workgroups,
+// far more than the 256 compute units.  Loads and stores are per-plane
+// (structure of arrays) and therefore coalesced: lane i touches element i of
+// every plane.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "abi_common.hpp"
+#include "ksvd2_device.hpp"
+
+namespace ksvd2 {
+
+std::string &last_error_ref() {
+  static thread_local std::string s;
+  return s;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_fwd_soa(int64_t n, const R *__restrict__ g11,
+                                                    const R *__restrict__ g21,
+                                                    const R *__restrict__ g12,
+                                                    const R *__restrict__ g22, R *__restrict__ cu,
+                                                    R *__restrict__ su, R *__restrict__ cv,
+                                                    R *__restrict__ sv, R *__restrict__ f1,
+                                                    R *__restrict__ f2, int32_t *__restrict__ e1,
+                                                    int32_t *__restrict__ e2,
+                                                    int32_t *__restrict__ info,
+                                                    R *__restrict__ s1, R *__restrict__ s2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Svd2<R> r = svd2<R>(g11[i], g21[i], g12[i], g22[i]);
+  cu[i] = r.cu;
+  su[i] = r.su;
+  cv[i] = r.cv;
+  sv[i] = r.sv;
+  f1[i] = r.f1;
+  f2[i] = r.f2;
+  e1[i] = r.e1;
+  e2[i] = r.e2;
+  info[i] = (int32_t)r.info;
+  if (s1) s1[i] = scale2(r.f1, r.e1);
+  if (s2) s2[i] = scale2(r.f2, r.e2);
+}
+
+// Autograd layout: G, U, V are [B,2,2] row-major, S is [B,2] (plain sigma).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_fwd_full(int64_t n, const R *__restrict__ G,
+                                                     R *__restrict__ U, R *__restrict__ S,
+                                                     R *__restrict__ V,
+                                                     int32_t *__restrict__ info) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const R *g = G + 4 * i;
+  Svd2<R> r = svd2<R>(g[0], g[2], g[1], g[3]);
+  R du = (r.info & I_DETU) ? (R)-1 : (R)1;
+  R dv = (r.info & I_DETV) ? (R)-1 : (R)1;
+  R *u = U + 4 * i;
+  u[0] = r.cu;
+  u[1] = -du * r.su;
+  u[2] = r.su;
+  u[3] = du * r.cu;
+  R *v = V + 4 * i;
+  v[0] = r.cv;
+  v[1] = -dv * r.sv;
+  v[2] = r.sv;
+  v[3] = dv * r.cv;
+  S[2 * i] = scale2(r.f1, r.e1);
+  S[2 * i + 1] = scale2(r.f2, r.e2);
+  if (info) info[i] = (int32_t)r.info;
+}
+
+// Adjoint of G = U diag(S) V^T (2x2, square, full U and V):
+//   a = (U^T dU)_12 - (U^T dU)_21,  b = (V^T dV)_12 - (V^T dV)_21,
+//   p = (a + b)/2, q = (a - b)/2,
+//   M = [[dS1, -p/(s1-s2) + q/(s1+s2)], [-p/(s1-s2) - q/(s1+s2), dS2]],
+//   dG = U M V^T.
+// 1/(s1-s2): with tau > 0 replaced by (s1-s2)/((s1-s2)^2 + (tau s1)^2);
+// with tau = 0 taken as 0 when s1 == s2; 1/(s1+s2) taken as 0 when s1+s2 == 0.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__ U,
+                                                const R *__restrict__ S,
+                                                const R *__restrict__ V,
+                                                const R *__restrict__ dS,
+                                                const R *__restrict__ dU,
+                                                const R *__restrict__ dV, R *__restrict__ dG,
+                                                R tau) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const R *u = U + 4 * i;
+  const R *v = V + 4 * i;
+  R u11 = u[0], u12 = u[1], u21 = u[2], u22 = u[3];
+  R v11 = v[0], v12 = v[1], v21 = v[2], v22 = v[3];
+  R s1 = S[2 * i], s2 = S[2 * i + 1];
+  R a = 0, b = 0;
+  if (dU) {
+    const R *w = dU + 4 * i;
+    // (U^T dU)_12 = u11 w12 + u21 w22 ; (U^T dU)_21 = u12 w11 + u22 w21
+    a = fma(u11, w[1], u21 * w[3]) - fma(u12, w[0], u22 * w[2]);
+  }
+  if (dV) {
+    const R *w = dV + 4 * i;
+    b = fma(v11, w[1], v21 * w[3]) - fma(v12, w[0], v22 * w[2]);
+  }
+  R p = (R)0.5 * (a + b), q = (R)0.5 * (a - b);
+  R dm = s1 - s2, sm = s1 + s2;
+  R idm;
+  if (tau > (R)0) {
+    R eta = tau * s1;
+    R den = fma(dm, dm, eta * eta);
+    idm = (den > (R)0) ? dm / den : (R)0;
+  } else {
+    idm = (dm != (R)0) ? (R)1 / dm : (R)0;
+  }
+  R ism = (sm != (R)0) ? (R)1 / sm : (R)0;
+  R m11 = dS ? dS[2 * i] : (R)0, m22 = dS ? dS[2 * i + 1] : (R)0;
+  R pd = p * idm, qs = q * ism;
+  R m12 = qs - pd, m21 = -pd - qs;
+  // T = U M, then dG = T V^T
+  R t11 = fma(u11, m11, u12 * m21), t12 = fma(u11, m12, u12 * m22);
+  R t21 = fma(u21, m11, u22 * m21), t22 = fma(u21, m12, u22 * m22);
+  R *g = dG + 4 * i;
+  g[0] = fma(t11, v11, t12 * v12);
+  g[1] = fma(t11, v21, t12 * v22);
+  g[2] = fma(t21, v11, t22 * v12);
+  g[3] = fma(t21, v21, t22 * v22);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_hypot(int64_t n, const R *__restrict__ x,
+                                                  const R *__restrict__ y, R *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = hypot_cr(x[i], y[i]);
+}
+
+template <class R>
+static int fwd_soa(int64_t n, const R *g11, const R *g21, const R *g12, const R *g22, R *cu, R *su,
+                   R *cv, R *sv, R *f1, R *f2, int32_t *e1, int32_t *e2, int32_t *info, R *s1,
+                   R *s2, void *stream) {
+  if (n < 0) return fail(KSVD2_EINVAL, "batch < 0");
+  if (n == 0) return KSVD2_OK;
+  const size_t w = sizeof(R);
+  KSVD2_REQ(g11, w); KSVD2_REQ(g21, w); KSVD2_REQ(g12, w); KSVD2_REQ(g22, w);
+  KSVD2_REQ(cu, w); KSVD2_REQ(su, w); KSVD2_REQ(cv, w); KSVD2_REQ(sv, w);
+  KSVD2_REQ(f1, w); KSVD2_REQ(f2, w); KSVD2_REQ(e1, 4); KSVD2_REQ(e2, 4); KSVD2_REQ(info, 4);
+  KSVD2_OPT(s1, w); KSVD2_OPT(s2, w);
+  hipLaunchKernelGGL(k_fwd_soa<R>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
+                     g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1, s2);
+  return launch_status("ksvd2 forward launch");
+}
+
+template <class R>
+static int fwd_full(int64_t n, const R *G, R *U, R *S, R *V, int32_t *info, void *stream) {
+  if (n < 0) return fail(KSVD2_EINVAL, "batch < 0");
+  if (n == 0) return KSVD2_OK;
+  const size_t w = sizeof(R);
+  KSVD2_REQ(G, w); KSVD2_REQ(U, w); KSVD2_REQ(S, w); KSVD2_REQ(V, w);
+  KSVD2_OPT(info, 4);
+  hipLaunchKernelGGL(k_fwd_full<R>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
+                     G, U, S, V, info);
+  return launch_status("ksvd2 forward (full layout) launch");
+}
+
+template <class R>
+static int bwd(int64_t n, const void *U, const void *S, const void *V, const void *dS,
+               const void *dU, const void *dV, void *dG, double tau, void *stream) {
+  if (n < 0) return fail(KSVD2_EINVAL, "batch < 0");
+  if (!(tau >= 0.0)) return fail(KSVD2_EINVAL, "tau must be >= 0");
+  if (n == 0) return KSVD2_OK;
+  const size_t w = sizeof(R);
+  KSVD2_REQ(U, w); KSVD2_REQ(S, w); KSVD2_REQ(V, w); KSVD2_REQ(dG, w);
+  KSVD2_OPT(dS, w); KSVD2_OPT(dU, w); KSVD2_OPT(dV, w);
+  hipLaunchKernelGGL(k_bwd<R>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
+                     (const R *)U, (const R *)S, (const R *)V, (const R *)dS, (const R *)dU,
+                     (const R *)dV, (R *)dG, (R)tau);
+  return launch_status("ksvd2 backward launch");
+}
+
+}  // namespace ksvd2
+
+using namespace ksvd2;
+
+extern "C" {
+
+int ksvd2_version(void) { return 1; }
+
+const char *ksvd2_last_error(void) { return last_error_ref().c_str(); }
+
+int ksvd2_batch_f64(int64_t batch, const double *g11, const double *g21, const double *g12,
+                    const double *g22, double *cu, double *su, double *cv, double *sv, double *f1,
+                    double *f2, int32_t *e1, int32_t *e2, int32_t *info, double *s1_plain,
+                    double *s2_plain, void *stream) {
+  return fwd_soa<double>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
+                         s1_plain, s2_plain, stream);
+}
+
+int ksvd2_batch_f32(int64_t batch, const float *g11, const float *g21, const float *g12,
+                    const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
+                    float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1_plain,
+                    float *s2_plain, void *stream) {
+  return fwd_soa<float>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1_plain,
+                        s2_plain, stream);
+}
+
+int ksvd2_svd2x2(int dtype, int64_t batch, const void *G, void *U, void *S, void *V,
+                 int32_t *info, void *stream) {
+  if (dtype == 1)
+    return fwd_full<double>(batch, (const double *)G, (double *)U, (double *)S, (double *)V, info,
+                            stream);
+  if (dtype == 0)
+    return fwd_full<float>(batch, (const float *)G, (float *)U, (float *)S, (float *)V, info,
+                           stream);
+  return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+int ksvd2_batch_backward(int dtype, int64_t batch, const void *U, const void *S, const void *V,
+                         const void *dS, const void *dU, const void *dV, void *dG, double tau,
+                         void *stream) {
+  if (dtype == 1) return bwd<double>(batch, U, S, V, dS, dU, dV, dG, tau, stream);
+  if (dtype == 0) return bwd<float>(batch, U, S, V, dS, dU, dV, dG, tau, stream);
+  return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+int ksvd2_hypot_batch(int dtype, int64_t n, const void *x, const void *y, void *out,
+                      void *stream) {
+  if (n < 0) return fail(KSVD2_EINVAL, "n < 0");
+  if (dtype != 0 && dtype != 1)
+    return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+  if (n == 0) return KSVD2_OK;
+  size_t w = dtype ? 8 : 4;
+  KSVD2_REQ(x, w); KSVD2_REQ(y, w); KSVD2_REQ(out, w);
+  if (dtype)
+    hipLaunchKernelGGL(k_hypot<double>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream,
+                       n, (const double *)x, (const double *)y, (double *)out);
+  else
+    hipLaunchKernelGGL(k_hypot<float>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream,
+                       n, (const float *)x, (const float *)y, (float *)out);
+  return launch_status("ksvd2 hypot launch");
+}
+
+}  // extern "C"

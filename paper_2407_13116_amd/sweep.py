@@ -1,0 +1,122 @@
+"""Batched two-sided Kogbetliantz sweep over many square matrices (C ABI
+kog_sweep_batch / kog_sigma_grad in include/ksvd2.h).
+
+Marshalling only: packing a list of matrices into one column-major device
+buffer, the workspace, and the stream (the hipGraph mode needs a non-null
+stream, so it runs on a side stream ordered after the caller's).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DT = {torch.float32: 0, torch.float64: 1}
+MODES = {"plain": 0, "persistent": 1, "graph": 2}
+
+
+class Packed:
+    """Square matrices packed column-major into one flat device tensor."""
+
+    def __init__(self, mats, dtype=None, device="cuda"):
+        mats = [np.asarray(m) for m in mats]
+        dtype = dtype or mats[0].dtype
+        self.n = np.array([m.shape[0] for m in mats], dtype=np.int32)
+        sizes = self.n.astype(np.int64) ** 2
+        self.off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        self.soff = np.concatenate([[0], np.cumsum(self.n.astype(np.int64))[:-1]]).astype(np.int64)
+        flat = np.concatenate([np.asarray(m, dtype=dtype).ravel(order="F") for m in mats])
+        self.G = torch.from_numpy(flat).to(device)
+        self.dtype = self.G.dtype
+
+    def unpack(self, flat):
+        """Device flat tensor (G, U or V layout) -> list of numpy matrices."""
+        h = flat.detach().cpu().numpy()
+        return [h[o:o + n * n].reshape((n, n), order="F") for o, n in zip(self.off, self.n)]
+
+    def unpack_sigma(self, sig):
+        h = sig.detach().cpu().numpy()
+        return [h[o:o + n] for o, n in zip(self.soff, self.n)]
+
+
+def workspace_bytes(dtype, n):
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    return int(_lib.lib().kog_sweep_workspace_size(_DT[dtype], len(n),
+                                                   n.ctypes.data_as(ctypes.c_void_p)))
+
+
+def kog_sweep_batch(packed: Packed, max_sweeps: int = 30, tol_factor: float = 1.0,
+                    mode: str | int = "persistent", U=None, V=None, workspace=None):
+    """Run the sweep in place on packed.G.  Returns dict(G, U, V, sigma, sweeps).
+
+    ``U``/``V`` given => accumulate (continue from them)."""
+    L = _lib.lib()
+    mode = MODES.get(mode, mode)
+    G = packed.G
+    dt = _DT[G.dtype]
+    acc = U is not None
+    if U is None:
+        U = torch.empty_like(G)
+        V = torch.empty_like(G)
+    sigma = torch.empty(int(packed.n.sum()), dtype=G.dtype, device=G.device)
+    sweeps = torch.empty(len(packed.n), dtype=torch.int32, device=G.device)
+    need = workspace_bytes(G.dtype, packed.n)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=G.device)
+    wsp = workspace.data_ptr()
+    pad = (-wsp) % 256
+    n = np.ascontiguousarray(packed.n)
+    off = np.ascontiguousarray(packed.off)
+    cur = torch.cuda.current_stream()
+    side = None
+    stream = cur
+    if mode == 2:
+        side = _side_stream(G.device)
+        side.wait_stream(cur)
+        stream = side
+    with torch.cuda.stream(stream):
+        rc = L.kog_sweep_batch(dt, len(n), n.ctypes.data_as(ctypes.c_void_p),
+                               off.ctypes.data_as(ctypes.c_void_p), G.data_ptr(), U.data_ptr(),
+                               V.data_ptr(), sigma.data_ptr(), sweeps.data_ptr(), int(max_sweeps),
+                               float(tol_factor), int(acc), int(mode), wsp + pad,
+                               workspace.numel() - pad, stream.cuda_stream or None)
+    _lib.check(rc, "kog_sweep_batch")
+    if side is not None:
+        cur.wait_stream(side)
+        for t in (G, U, V, sigma, sweeps, workspace):
+            t.record_stream(side)
+    return {"G": G, "U": U, "V": V, "sigma": sigma, "sweeps": sweeps, "workspace": workspace}
+
+
+_SIDE = {}
+
+
+def _side_stream(device):
+    key = torch.device(device).index or 0
+    if key not in _SIDE:
+        _SIDE[key] = torch.cuda.Stream(device=device)   # default priority
+    return _SIDE[key]
+
+
+def sigma_grad(packed: Packed, U, V, dsigma):
+    """dG = U diag(dsigma) V^T per matrix (the gradient of sum dsigma_i sigma_i)."""
+    L = _lib.lib()
+    dG = torch.empty_like(U)
+    need = workspace_bytes(U.dtype, packed.n)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=U.device)
+    pad = (-ws.data_ptr()) % 256
+    n = np.ascontiguousarray(packed.n)
+    off = np.ascontiguousarray(packed.off)
+    rc = L.kog_sigma_grad(_DT[U.dtype], len(n), n.ctypes.data_as(ctypes.c_void_p),
+                          off.ctypes.data_as(ctypes.c_void_p), U.data_ptr(), V.data_ptr(),
+                          dsigma.data_ptr(), dG.data_ptr(), ws.data_ptr() + pad,
+                          ws.numel() - pad, torch.cuda.current_stream().cuda_stream or None)
+    _lib.check(rc, "kog_sigma_grad")
+    return dG
+
+
+def set_tuning(dtype, bucket: int, block: int):
+    _lib.check(_lib.lib().kog_sweep_tune(_DT[dtype], bucket, block), "kog_sweep_tune")

@@ -1,0 +1,90 @@
+"""The C ABI library (CPU-side checks, no GPU needed).
+
+* libksvd2.so loads and exports every function that include/*.h declares;
+* invalid arguments are rejected before anything is enqueued (status codes and the
+  last-error message), which needs no device.
+"""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", txt, re.M):
+            name = m.group(1)
+            if name not in ("if", "while", "for", "return", "sizeof"):
+                names.add(name)
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2407_13116_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2407_13116_amd import build
+
+        build.build()
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert {"ksvd2_batch_f64", "ksvd2_batch_f32", "ksvd2_batch_backward", "ksvd2_svd2x2"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+    assert L.ksvd2_version() >= 1
+
+
+def test_invalid_arguments_rejected(L):
+    p = ctypes.c_void_p(64)  # aligned, never dereferenced: validation fails first
+    rc = L.ksvd2_batch_f64(-1, *([p] * 13), None, None, None)
+    assert rc == -1 and b"batch" in L.ksvd2_last_error()
+    rc = L.ksvd2_batch_f64(4, None, *([p] * 12), None, None, None)
+    assert rc == -1 and b"g11" in L.ksvd2_last_error()
+    rc = L.ksvd2_batch_f64(4, ctypes.c_void_p(65), *([p] * 12), None, None, None)
+    assert rc == -1 and b"aligned" in L.ksvd2_last_error()
+    assert L.ksvd2_batch_f64(0, *([None] * 15), None) == 0          # empty batch: no-op
+    assert L.ksvd2_svd2x2(7, 4, p, p, p, p, None, None) == -2
+    assert L.ksvd2_batch_backward(1, 4, p, p, p, None, None, None, p, -1.0, None) == -1
+    assert L.ksvd2_batch_backward(5, 4, p, p, p, None, None, None, p, 0.0, None) == -2
+    assert L.ksvd2_hypot_batch(1, -3, p, p, p, None) == -1
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+
+    from paper_2407_13116_amd import KSVD2Error, api
+
+    x = torch.zeros(4, dtype=torch.float64)
+    with pytest.raises(KSVD2Error):
+        api.ksvd2_batch(x, x, x, x)
+
+
+def test_sweep_arguments_rejected(L):
+    import numpy as np
+
+    n = np.array([4, 5], dtype=np.int32)          # odd order
+    off = np.array([0, 16], dtype=np.int64)
+    p = ctypes.c_void_p(256)
+    args = lambda nn, mode, ws_bytes: (1, 2, nn.ctypes.data_as(ctypes.c_void_p),
+                                       off.ctypes.data_as(ctypes.c_void_p), p, p, p, None, None,
+                                       3, 1.0, 0, mode, p, ws_bytes, None)
+    assert L.kog_sweep_batch(*args(n, 1, 1 << 20)) == -1
+    assert b"even" in L.ksvd2_last_error()
+    n2 = np.array([4, 6], dtype=np.int32)
+    assert L.kog_sweep_batch(*args(n2, 1, 16)) == -4                 # workspace too small
+    need = L.kog_sweep_workspace_size(1, 2, n2.ctypes.data_as(ctypes.c_void_p))
+    assert need > 0
+    assert L.kog_sweep_batch(*args(n2, 2, need)) == -1                # graph mode, null stream
+    assert L.kog_sweep_batch(*args(n2, 7, need)) == -1                # bad mode
+    assert L.kog_sweep_tune(1, 9, 256) == -1 and L.kog_sweep_tune(1, 0, 300) == -1
