@@ -842,7 +842,14 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
         den = std::fma(tbphi, tan_t, (R)1);
       }
       R ca, sa;
-      if (den == 0) {
+      if (std::isinf(tbphi)) {
+        /* tan(psi) underflowed to 0 in the swapped case: bphi = pi/2, and the
+           merged angle is pi/2 + theta (S22 = I) or pi/2 - theta */
+        R sec_t = cr_hypot(tan_t, (R)1);
+        R ct = (R)1 / sec_t, st = tan_t / sec_t;
+        ca = s22neg ? st : -st;
+        sa = ct;
+      } else if (den == 0) {
         ca = 0;
         sa = sgn(num);
       } else {
@@ -971,11 +978,21 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
         R gii = G[i + (int64_t)i * n], gji = G[j + (int64_t)i * n];
         R gij = G[i + (int64_t)j * n], gjj = G[j + (int64_t)j * n];
         Res<R> r = ksvd2<R>(gii, gji, gij, gjj);
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y) {
-            pc[4 * q + x + 2 * y] = r.U.a[x][y];
-            pv[4 * q + x + 2 * y] = r.V.a[x][y];
-          }
+        /* the pivot's U and V as delivered by the 2x2 SVD: [c -d s; s d c] */
+        R c, sn;
+        bool neg;
+        compact(r.U, c, sn, neg);
+        R d = neg ? (R)-1 : (R)1;
+        pc[4 * q] = c;
+        pc[4 * q + 1] = sn;
+        pc[4 * q + 2] = -d * sn;
+        pc[4 * q + 3] = d * c;
+        compact(r.V, c, sn, neg);
+        d = neg ? (R)-1 : (R)1;
+        pv[4 * q] = c;
+        pv[4 * q + 1] = sn;
+        pv[4 * q + 2] = -d * sn;
+        pv[4 * q + 3] = d * c;
         ps1[q] = ef_fl(r.s1);
         ps2[q] = ef_fl(r.s2);
       }
