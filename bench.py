@@ -29,6 +29,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("2x2 SVDs/sec (fwd, fwd+bwd) FP64/FP32; %HBM roofline; max rel err σ2 (ulp)")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_VECTOR_TFLOPS = 78.6      # 256 CU x 64 lanes x 2.4 GHz x 2 (an FMA counts twice)
+# algorithmic FP work per matrix of the forward method (main class-15 path): about 8
+# correctly rounded hypot (~45 VALU slots each in FP64), 18 IEEE divisions (~13 slots),
+# ~45 add/mul/fma, the double-word EXT block and ~25 exponent operations -> ~700 VALU
+# slots per FP64 matrix (~400 for FP32, hypot evaluated in binary64); a slot is priced
+# as one FMA = 2 flops against the FP64 vector peak
+ALG_VALU_SLOTS = {np.float64: 700, np.float32: 400}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pmc_traffic_k_fwd_soa_f64.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_13116_amd", "csrc", f)
+                  for f in ("ksvd2_device.hpp", "ksvd2_kernels.hip", "abi_common.hpp")]
 BYTES_FWD = {np.float64: 92, np.float32: 52}      # algorithmic bytes per matrix (in + out)
 BYTES_FWDBWD = {np.float64: 112 + 192, np.float32: 56 + 96}
 
@@ -136,6 +146,78 @@ def sigma2_error_sample(g, host, dtype, n=1500):
     return worst
 
 
+def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=60, tune=True):
+    """Time one converged solve of a batch of square matrices per execution mode (the
+    matrices are re-uploaded untimed before every run).  Effective bytes: every step reads
+    and writes G, U and V once, 6 n^2 w per matrix per step."""
+    import torch
+
+    from paper_2407_13116_amd import autotune
+    from paper_2407_13116_amd import sweep as sw
+
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    chosen = autotune.tune(mats, tdt) if tune else {}
+    p = sw.Packed(mats, dtype=dtype)
+    G0 = p.G.clone()
+    w = np.dtype(dtype).itemsize
+    res = {"tuned_blocks": {str(k): v for k, v in chosen.items()}}
+    ws = None
+    for mode in modes:
+        times = []
+        for rep in range(2 if mode == "graph" else 1):   # graph: capture, then replay
+            p.G.copy_(G0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode=mode,
+                                     workspace=ws)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            ws = out["workspace"]
+        sweeps = np.abs(out["sweeps"].cpu().numpy()).astype(np.int64)
+        n = p.n.astype(np.int64)
+        bytes_ = float(np.sum(sweeps * (n - 1) * 6 * n * n * w))
+        res[mode] = {"seconds": times[-1], "sweeps_mean": float(sweeps.mean()),
+                     "sweeps_max": int(sweeps.max()),
+                     "converged": bool(np.all(out["sweeps"].cpu().numpy() > 0)),
+                     "eff_GBs": bytes_ / times[-1] / 1e9,
+                     "matrices_per_s": len(mats) / times[-1]}
+        log(f"[bench] sweep {mode}: {res[mode]}")
+    del p, G0
+    torch.cuda.empty_cache()
+    return res
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(batch):
+    """HBM bytes per launch of the FP64 forward kernel from the committed rocprofv3
+    --pmc summary (FETCH_SIZE scaled by the copy-kernel calibration factor, plus
+    WRITE_SIZE), or None when that summary was taken on other kernel sources or another
+    batch size."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    try:
+        if kv["kernel_source_sha256"] != kernel_source_hash() or int(kv["batch"]) != batch:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(seconds):
     import oracle
     from paper_2407_13116_amd import inputs
@@ -152,6 +234,21 @@ def cpu_baseline(seconds):
     return {"value": done / dt, "unit": "2x2 SVDs/s", "cores": nthreads, "kind": "oracle",
             "sample": f"first 2^22 matrices of the FP64 2^24 workload, repeated for ~{seconds:.0f} s "
                       f"({done} SVDs in {dt:.1f} s), OpenMP static schedule"}
+
+
+def roofline(f64):
+    """The FP64 forward kernel is bound by VALU issue (its algorithmic bytes need only a
+    quarter of HBM bandwidth at the measured rate): achieved = algorithmic FP work per
+    launch / the kernel's average duration (HIP events on its launch stream)."""
+    B, ms = f64["B"], f64["ms_kernel"]
+    achieved = 2.0 * ALG_VALU_SLOTS[np.float64] * B / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_TFLOPS, "traffic": measured_traffic(B),
+            "kernel": "k_fwd_soa<double>", "avg_kernel_ms": ms, "batch": B,
+            "alg_valu_slots_per_matrix": ALG_VALU_SLOTS[np.float64],
+            "hbm": {"achieved_GBs": f64["GBs"], "peak_GBs": HBM_PEAK_GBS,
+                    "frac": f64["GBs"] / HBM_PEAK_GBS,
+                    "alg_bytes_per_matrix": BYTES_FWD[np.float64]}}
 
 
 def main():
@@ -184,22 +281,28 @@ def main():
                                "entries +-m 2^e with e uniform in [-1000,1000], 10% upper "
                                "triangular, 1% near-singular, SoA planes resident in HBM",
                    "batch": f64["B"]},
-        "roofline": {"bound": "hbm", "achieved": f64["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": f64["GBs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fwd_soa<double>", "avg_kernel_ms": f64["ms_kernel"],
-                     "bytes_per_matrix": BYTES_FWD[np.float64]},
+        "roofline": roofline(f64),
     }
     extra = {}
     if not args.no_extra:
         log("[bench] FP32 forward, 2^24 matrices")
         f32, g32, h32 = fwd_case(np.float32, args.steps, args.warmup)
         extra["fwd_f32"] = {"rate": f32["rate"], "ms_per_launch": f32["ms_kernel"],
-                            "GBs": f32["GBs"], "hbm_frac": f32["GBs"] / HBM_PEAK_GBS}
+                            "GBs": f32["GBs"], "hbm_frac": f32["GBs"] / HBM_PEAK_GBS,
+                            "alg_TFLOPs": 2.0 * ALG_VALU_SLOTS[np.float32] * f32["B"]
+                            / (f32["ms_kernel"] * 1e-3) / 1e12}
         for dt, name in ((np.float64, "fwdbwd_f64"), (np.float32, "fwdbwd_f32")):
             log(f"[bench] {name}, 2^22 matrices")
             fb = fwdbwd_case(dt, args.steps, args.warmup)
             extra[name] = {"rate": fb["rate"], "ms_per_step": fb["ms_kernel"], "GBs": fb["GBs"],
                            "hbm_frac": fb["GBs"] / HBM_PEAK_GBS}
+        from paper_2407_13116_amd import inputs as _inp
+
+        log("[bench] sweep: 256 x (n=256) FP64")
+        extra["sweep_uniform_f64"] = sweep_case(_inp.sweep_uniform(), np.float64)
+        for dt, name in ((np.float64, "sweep_uneven_f64"), (np.float32, "sweep_uneven_f32")):
+            log(f"[bench] sweep: 1,000 uneven orders, {name}")
+            extra[name] = sweep_case(_inp.sweep_uneven(dtype=dt), dt)
         log("[bench] sigma_2 accuracy sample")
         extra["max_rel_err_sigma2_ulp"] = {"f64": sigma2_error_sample(g64, h64, np.float64),
                                            "f32": sigma2_error_sample(g32, h32, np.float32),

@@ -164,6 +164,39 @@ __device__ __attribute__((noinline)) double hypot_resolve(double p, double pe, d
   return y;
 }
 
+// sqrt(S), S = sh + sl a double-word in [1, 8), correctly rounded to binary64.
+// A reciprocal square root estimate and one Goldschmidt step give g ~ sqrt(S)
+// (within about an ulp) and h ~ 1/(2 sqrt S); the residual t = S - g^2 is formed
+// exactly to 2^-99 (sh - g^2 is exact by Sterbenz), the first-order correction
+// c = t h gives the candidate y = RN(g + c) and w ~ sqrt(S) - y with an error
+// below 2^-92.  y is the answer unless w lies within 2^-88 of a rounding
+// midpoint of y; then the exact expansion sign test settles it (p, pe, q, qe
+// are the exact parts of S).
+__device__ __attribute__((always_inline)) inline double sqrt_dw_cr(double sh, double sl,
+                                                                    double p, double pe,
+                                                                    double q, double qe) {
+  double s = sh + sl;
+  double r0 = __builtin_amdgcn_rsq(s);
+  double g = s * r0, h = 0.5 * r0;
+  double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, s);
+  g = fma(d, h, g);
+  double gg, gge;
+  two_prod(g, g, gg, gge);
+  double t = ((sh - gg) - gge) + sl;
+  double c = t * h;
+  double y = g + c;
+  double w = (g - y) + c;
+  double hg = (y >= 2.0) ? 0x1p-52 : 0x1p-53;  // half an ulp of y (y in [1, 4))
+  const double M = 0x1p-88;
+  bool pow2 = (y == 1.0) || (y == 2.0);         // the gap below y is half as wide
+  bool ok = (fabs(w) < hg - M) && !(pow2 && w < -(0.5 * hg - M));
+  if (ok) return y;
+  return hypot_resolve(p, pe, q, qe, y, 2.0 * hg, pow2 ? hg : 2.0 * hg);
+}
+
 __device__ __attribute__((always_inline)) inline double hypot_cr(double x, double y) {
   double a = fabs(x), b = fabs(y);
   double hi = fmax(a, b), lo = fmin(a, b);
@@ -175,28 +208,21 @@ __device__ __attribute__((always_inline)) inline double hypot_cr(double x, doubl
   double p, pe, q, qe;
   two_prod(A, A, p, pe);
   two_prod(B, B, q, qe);
-  double sh = p + q;                     // p >= q: Fast2Sum
+  double sh = p + q;                               // p >= q: Fast2Sum
   double sl = (q - (sh - p)) + (pe + qe);
-  double r = sqrt(sh + sl);              // within one ulp of sqrt(S)
-  double rr, rre;
-  two_prod(r, r, rr, rre);
-  double t = ((sh - rr) - rre) + sl;     // S - r^2 (sh - rr is exact)
-  double u = (r >= 2.0) ? 0x1p-51 : 0x1p-52;               // ulp(r)
-  double gdn = (r == 1.0 || r == 2.0) ? 0.5 * u : u;        // r - pred(r)
-  double tup = fma(r, u, 0.25 * u * u);                     // (r+u/2)^2 - r^2
-  double tdn = fma(-r, gdn, 0.25 * gdn * gdn);              // (r-gdn/2)^2 - r^2
-  const double M = 0x1p-98;
-  double res;
-  if (t > tup + M) {
-    res = r + u;
-  } else if (t < tdn - M) {
-    res = r - gdn;
-  } else if (t >= tup - M || t <= tdn + M) {
-    res = hypot_resolve(p, pe, q, qe, r, u, gdn);
-  } else {
-    res = r;
-  }
-  return ldexp(res, eh);
+  return ldexp(sqrt_dw_cr(sh, sl, p, pe, q, qe), eh);
+}
+
+// hypot(t, 1) for 0 <= t <= 1 (the secants of angles up to pi/4): the larger
+// argument is exactly 1, so no scaling is needed.
+__device__ __attribute__((always_inline)) inline double hypot1_le1(double t) {
+  int et = ilog2(t);
+  if (t == 0.0 || et < -30) return 1.0;
+  double q, qe;
+  two_prod(t, t, q, qe);
+  double sh = 1.0 + q;
+  double sl = (q - (sh - 1.0)) + qe;
+  return sqrt_dw_cr(sh, sl, 1.0, 0.0, q, qe);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,8 +234,16 @@ __device__ __attribute__((always_inline)) inline double hypot_cr(double x, doubl
 __device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y) {
   double a = fabs((double)x), b = fabs((double)y);
   double hi = fmax(a, b), lo = fmin(a, b);
+  if (isinf(hi)) return (float)hi;
   double S = fma(hi, hi, lo * lo);
-  double r = sqrt(S);
+  if (S == 0.0) return 0.0f;
+  // sqrt(S) to about 2^-40 relative: a reciprocal square root estimate and one
+  // Goldschmidt step (S is far inside binary64's normal range).  The exact
+  // midpoint test below needs r only within a small fraction of a binary32 ulp.
+  double r0 = __builtin_amdgcn_rsq(S);
+  double r = S * r0, h = 0.5 * r0;
+  double e = fma(-h, r, 0.5);
+  r = fma(r, e, r);
   float f = (float)r;
   double fd = isinf(f) ? 0x1p128 : (double)f;  // +inf stands for 2^128 here
   if (fd == r) return f;
@@ -238,6 +272,10 @@ __device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y
   if (sgn < 0.0) return g;
   if (sgn == 0.0) return even_sig(f) ? f : g;
   return f;
+}
+
+__device__ __attribute__((always_inline)) inline float hypot1_le1(float t) {
+  return hypot_cr(t, 1.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,27 +398,61 @@ __device__ __attribute__((always_inline)) inline double ext_w(double x1, double 
 }
 
 // ---------------------------------------------------------------------------
-// 2x2 matrices as four registers, [a b; c d] (row-major), with the exact
-// signed-permutation operations used to assemble U and V.
+// Factored orthogonal matrices.  Every U and V the method builds is a signed
+// permutation times a plane rotation times a signed permutation (the P and S
+// factors around U_theta, U_phi, V_psi in Sect. 3), so they are kept as
+// L rot(c, s) R with L, R coded in three bits and multiplied symbolically; the
+// entries are formed once, at the end (each is +-c or +-s, exactly).
 // ---------------------------------------------------------------------------
-template <class R> struct M2 {
-  R a, b, c, d;
+
+// Signed permutation Q: column j of Q is (-1)^{n_j} e_{pi(j)}, pi swaps iff x.
+struct SP {
+  uint32_t x, n0, n1;
 };
-template <class R> __device__ inline M2<R> mrot(R c, R s) { return M2<R>{c, -s, s, c}; }
-template <class R> __device__ inline M2<R> mid() { return M2<R>{(R)1, (R)0, (R)0, (R)1}; }
-template <class R> __device__ inline void swap_rows(M2<R> &m) {
-  R t = m.a; m.a = m.c; m.c = t;
-  t = m.b; m.b = m.d; m.d = t;
+__device__ inline SP sp_id() { return SP{0u, 0u, 0u}; }
+__device__ inline SP sp_x(bool on) { return SP{on ? 1u : 0u, 0u, 0u}; }
+__device__ inline SP sp_diag(bool neg0, bool neg1) {
+  return SP{0u, neg0 ? 1u : 0u, neg1 ? 1u : 0u};
 }
-template <class R> __device__ inline void swap_cols(M2<R> &m) {
-  R t = m.a; m.a = m.b; m.b = t;
-  t = m.c; m.c = m.d; m.d = t;
+// (A B) e_j = (-1)^{nB_j} A e_{piB(j)} = (-1)^{nB_j + nA_{piB(j)}} e_{piA(piB(j))}
+__device__ inline SP sp_mul(SP a, SP b) {
+  SP r;
+  r.x = a.x ^ b.x;
+  r.n0 = b.n0 ^ (b.x ? a.n1 : a.n0);
+  r.n1 = b.n1 ^ (b.x ? a.n0 : a.n1);
+  return r;
 }
-template <class R> __device__ inline void neg_row(M2<R> &m, int i) {
-  if (i == 0) { m.a = -m.a; m.b = -m.b; } else { m.c = -m.c; m.d = -m.d; }
+
+// L rot(c, s) Rt with rot(c, s) = [c -s; s c]
+template <class R> struct Fac {
+  SP L;
+  R c, s;
+  SP Rt;
+};
+
+template <class R> __device__ inline Fac<R> fac(SP L, R c, R s, SP Rt) {
+  Fac<R> f;
+  f.L = L;
+  f.c = c;
+  f.s = s;
+  f.Rt = Rt;
+  return f;
 }
-template <class R> __device__ inline void neg_col(M2<R> &m, int j) {
-  if (j == 0) { m.a = -m.a; m.c = -m.c; } else { m.b = -m.b; m.d = -m.d; }
+
+template <class R> __device__ inline R neg_if(R v, uint32_t n) { return n ? -v : v; }
+
+// The first column (c, s) of L rot(c, s) Rt, and whether its determinant is -1.
+template <class R> __device__ inline void fac_out(const Fac<R> &f, R &c1, R &s1, bool &detneg) {
+  // rot Rt e_0 = (-1)^{n0} rot e_{pi(0)}
+  R v0 = f.Rt.x ? -f.s : f.c, v1 = f.Rt.x ? f.c : f.s;
+  v0 = neg_if(v0, f.Rt.n0);
+  v1 = neg_if(v1, f.Rt.n0);
+  // L v: component k lands in row pi_L(k) with the sign (-1)^{nL_k}
+  R w0 = neg_if(v0, f.L.n0), w1 = neg_if(v1, f.L.n1);
+  R u0 = f.L.x ? w1 : w0, u1 = f.L.x ? w0 : w1;
+  c1 = u0 + (R)0;  // canonical zero: -0 -> +0
+  s1 = u1 + (R)0;
+  detneg = ((f.L.x ^ f.L.n0 ^ f.L.n1 ^ f.Rt.x ^ f.Rt.n0 ^ f.Rt.n1) & 1u) != 0;
 }
 
 template <class R> __device__ inline bool negative(R x) { return x < (R)0; }
@@ -409,14 +481,19 @@ template <class R> __device__ inline int ztype(R g11, R g21, R g12, R g22) {
   return (g11 != (R)0) | ((g21 != (R)0) << 1) | ((g12 != (R)0) << 2) | ((g22 != (R)0) << 3);
 }
 
+// A (prescaled) 2x2 matrix [a b; c d], row-major.
+template <class R> struct M2 {
+  R a, b, c, d;
+};
+
 // A partial SVD of a (prescaled) matrix: G' = U diag(s1, s2) V^T.
 template <class R> struct Part {
-  M2<R> U, V;
+  Fac<R> U, V;
   EF<R> s1, s2;
 };
 
 // Sect. 3.1, class 9: at most one permutation per side into the 0/1/9 form
-// with |d11| >= |d22|; row signs go into U (U = P_U S, V = P_V).
+// with |d11| >= |d22|; the row signs go into U (U = P_U S, V = P_V).
 template <class R> __device__ __attribute__((always_inline)) Part<R> part9(M2<R> G, int t) {
   bool pu = false, pv = false;
   if (t == 2) pu = true;
@@ -427,28 +504,20 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part9(M2<R>
   } else if (t == 9) {
     if (fabs(G.a) < fabs(G.d)) pu = pv = true;
   }
-  M2<R> D = G;
-  if (pu) swap_rows(D);
-  if (pv) swap_cols(D);
+  // the diagonal of D = P_U^T G P_V
+  R d11 = pu ? (pv ? G.d : G.c) : (pv ? G.b : G.a);
+  R d22 = pu ? (pv ? G.a : G.b) : (pv ? G.c : G.d);
   Part<R> r;
-  r.U = mid<R>();
-  if (negative(D.a)) neg_col(r.U, 0);
-  if (negative(D.d)) neg_col(r.U, 1);
-  if (pu) swap_rows(r.U);
-  r.V = mid<R>();
-  if (pv) swap_rows(r.V);
-  r.s1 = nrm(fabs(D.a));
-  r.s2 = nrm(fabs(D.d));
+  r.U = fac(sp_mul(sp_x(pu), sp_diag(negative(d11), negative(d22))), (R)1, (R)0, sp_id());
+  r.V = fac(sp_x(pv), (R)1, (R)0, sp_id());
+  r.s1 = nrm(fabs(d11));
+  r.s2 = nrm(fabs(d22));
   return r;
 }
 
-// cos and sin of the Givens angle from its tangent (eq. Givens, Lemma sincostheta)
-template <class R> __device__ inline M2<R> givens(R tn) {
-  R sec = hypot_cr(tn, (R)1);
-  return mrot((R)1 / sec, tn / sec);
-}
-
-// Sect. 3.1, classes 3 (one non-zero column) and 5 (one non-zero row).
+// Sect. 3.1, classes 3 (one non-zero column) and 5 (one non-zero row): the
+// non-zero pair made non-negative by signs, the larger one first, and one Givens
+// rotation with tangent smaller/larger (eq. Givens, Lemma sincostheta).
 template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R> G, int t) {
   bool col = (t == 3 || t == 12);
   bool pfirst = (t == 12 || t == 10);  // P_V for t = 12, P_U for t = 10
@@ -460,14 +529,13 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R
   b = fabs(b);
   bool sw = a < b;
   if (sw) { R t2 = a; a = b; b = t2; }
-  M2<R> W = givens(b / a);
-  if (sw) swap_rows(W);
-  if (na) neg_row(W, 0);
-  if (nb) neg_row(W, 1);
-  M2<R> P = mid<R>();
-  if (pfirst) swap_rows(P);
+  R tn = b / a;
+  R sec = hypot1_le1(tn);  // 0 <= tan <= 1
+  Fac<R> W = fac(sp_mul(sp_diag(na, nb), sp_x(sw)), (R)1 / sec, tn / sec, sp_id());
+  Fac<R> P = fac(sp_x(pfirst), (R)1, (R)0, sp_id());
   Part<R> r;
-  if (col) { r.U = W; r.V = P; } else { r.U = P; r.V = W; }
+  r.U = col ? W : P;
+  r.V = col ? P : W;
   r.s1 = nrm(hypot_cr(a, b));
   r.s2 = nrm((R)0);
   return r;
@@ -501,7 +569,7 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
     }
   }
   R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hypot_cr(t2, (R)1));  // eq. tf
-  R sphi_sec = hypot_cr(tphi, (R)1);
+  R sphi_sec = hypot1_le1(tphi);  // 0 <= tan(phi) <= 1
   o.tphi = tphi;
   o.cphi = (R)1 / sphi_sec;
   o.sphi = tphi / sphi_sec;
@@ -533,15 +601,9 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
   return o;
 }
 
-template <class R> __device__ inline void put_uv(const M2<R> &U, R &c, R &s, bool &neg) {
-  R det = U.a * U.d - U.b * U.c;
-  neg = det < (R)0;
-  c = U.a + (R)0;  // canonical zero: -0 -> +0
-  s = U.c + (R)0;
-}
-
 // The whole method for one matrix.
-template <class R> __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g22) {
+template <class R>
+__device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g22) {
   Svd2<R> out;
   int t = ztype(g11, g21, g12, g22);
   if (!(isfinite(g11) && isfinite(g21) && isfinite(g12) && isfinite(g22))) {
@@ -577,51 +639,53 @@ template <class R> __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11,
   Part<R> part;
   bool tri = false;
   R r11 = 0, r12 = 0, r22 = 0;
-  M2<R> Up = mid<R>(), Vp = mid<R>();  // U_+ (class 13) and V_+
+  // left factors of U and V in front of the triangular SVD (U_+, V_+)
+  SP UL = sp_id(), VL = sp_id();
   // class 15 pieces kept for the heuristic
   R tan_t = 0, sec_t = 1;
-  bool s1n0 = false, s1n1 = false, pu15 = false, s22neg = false;
+  bool is15 = false, s22neg = false;
 
   if (tb1 & (CL9 | CL3 | CL5)) {
     part = (tb1 & CL9) ? part9(G, t1) : part35(G, t1);
   } else if (tb1 & CL13) {
-    // Sect. 3.2.1: permute into [x y; 0 z], then three sign changes
+    // Sect. 3.2.1: permute into [x y; 0 z], then three sign changes:
+    // U_+ = P_U S11 S22 = P_U diag(sgn x, sgn z'), V_+ = P_V S12 = P_V diag(1, sgn y')
     bool pu = (t1 == 14 || t1 == 11), pv = (t1 == 7 || t1 == 11);
-    M2<R> H = G;
-    if (pu) swap_rows(H);
-    if (pv) swap_cols(H);
-    bool nx = negative(H.a);
-    R y = nx ? -H.b : H.b;
+    R x = pu ? (pv ? G.d : G.c) : (pv ? G.b : G.a);
+    R y = pu ? (pv ? G.c : G.d) : (pv ? G.a : G.b);
+    R z = pu ? (pv ? G.a : G.b) : (pv ? G.c : G.d);
+    bool nx = negative(x);
+    y = nx ? -y : y;
     bool ny = negative(y);
-    R z = ny ? -H.d : H.d;
+    z = ny ? -z : z;
     bool nz = negative(z);
-    r11 = fabs(H.a);
+    r11 = fabs(x);
     r12 = fabs(y);
     r22 = fabs(z);
-    // U_+ = P_U S11 S22 = P_U diag(sgn x, sgn z'), V_+ = P_V S12 = P_V diag(1, sgn y')
-    if (nx) neg_col(Up, 0);
-    if (nz) neg_col(Up, 1);
-    if (pu) swap_rows(Up);
-    if (ny) neg_col(Vp, 1);
-    if (pv) swap_rows(Vp);
+    UL = sp_mul(sp_x(pu), sp_diag(nx, nz));
+    VL = sp_mul(sp_x(pv), sp_diag(false, ny));
     tri = true;
   } else {
     // Sect. 3.2.2: class 15, the fully pivoted URV
+    is15 = true;
     R w1 = hypot_cr(G.a, G.c), w2 = hypot_cr(G.b, G.d);
     bool pv = w1 < w2;
     if (pv) {
       R tw = w1; w1 = w2; w2 = tw;
-      swap_cols(G);
+      tw = G.a; G.a = G.b; G.b = tw;
+      tw = G.c; G.c = G.d; G.d = tw;
     }
-    s1n0 = negative(G.a);
-    s1n1 = negative(G.c);
+    bool s1n0 = negative(G.a), s1n1 = negative(G.c);
     if (s1n0) { G.a = -G.a; G.b = -G.b; }
     if (s1n1) { G.c = -G.c; G.d = -G.d; }
-    pu15 = G.a < G.c;
-    if (pu15) swap_rows(G);
+    bool pu15 = G.a < G.c;
+    if (pu15) {
+      R tw = G.a; G.a = G.c; G.c = tw;
+      tw = G.b; G.b = G.d; G.d = tw;
+    }
     // G''' = [G.a G.b; G.c G.d], G.a >= G.c > 0
     tan_t = G.c / G.a;
-    sec_t = hypot_cr(tan_t, (R)1);
+    sec_t = hypot1_le1(tan_t);  // 0 < tan(theta) <= 1
     r11 = w1;
     bool exact = fma(-tan_t, G.a, G.c) == (R)0;
     bool same = negative(G.b) == negative(G.d);
@@ -640,30 +704,22 @@ template <class R> __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11,
     }
     r12 = same ? rgood : rother;
     r22 = same ? rother : rgood;
-    Vp = mid<R>();
-    if (pv) swap_rows(Vp);
+    UL = sp_mul(sp_diag(s1n0, s1n1), sp_x(pu15));  // S_1 P_U
+    VL = sp_x(pv);                                  // P_V
     if (r12 == (R)0 || r22 == (R)0) {
       // a zero appeared: R'' = [r11 r12; 0 r22] is of type 9/1 or 5 and is
-      // finished as in Sect. 3.1; U = S_1 P_U U_theta U_R, V = P_V V_R
+      // finished as in Sect. 3.1; U = S_1 P_U U_theta U_R, V = P_V V_R, where
+      // U_R is a signed permutation in both cases
       info |= I_DEGEN;
       M2<R> Rpp = M2<R>{r11, r12, (R)0, r22};
       int t2 = ztype(Rpp.a, Rpp.c, Rpp.b, Rpp.d);
       part = (t2 == 5) ? part35(Rpp, t2) : part9(Rpp, t2);
-      M2<R> Ut = givens(tan_t);
-      // Ut * U_R: U_R is a signed permutation, apply its columns to Ut
-      M2<R> UR = part.U;
-      M2<R> U2 = M2<R>{Ut.a * UR.a + Ut.b * UR.c, Ut.a * UR.b + Ut.b * UR.d,
-                       Ut.c * UR.a + Ut.d * UR.c, Ut.c * UR.b + Ut.d * UR.d};
-      if (pu15) swap_rows(U2);
-      if (s1n0) neg_row(U2, 0);
-      if (s1n1) neg_row(U2, 1);
-      M2<R> VR = part.V;
-      if (pv) swap_rows(VR);
-      part.U = U2;
-      part.V = VR;
+      part.U = fac(UL, (R)1 / sec_t, tan_t / sec_t, part.U.L);
+      part.V = fac(sp_mul(VL, part.V.L), part.V.c, part.V.s, part.V.Rt);
     } else {
       bool n12 = negative(r12);
-      if (n12) { r22 = -r22; neg_col(Vp, 1); }
+      if (n12) r22 = -r22;
+      VL = sp_mul(VL, sp_diag(false, n12));  // V_+ = P_V S12
       r12 = fabs(r12);
       s22neg = negative(r22);
       r22 = fabs(r22);
@@ -678,20 +734,17 @@ template <class R> __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11,
     Tri<R> tr = swp ? tri_svd(r22, r12, r11) : tri_svd(r11, r12, r22);
     if (tr.ovf) info |= I_TPSI_OVF;
     if (tr.psig) info |= I_PSIG;
-    // U_bphi and V_bpsi of eq. RT (S2 = diag(1,-1) when swapped)
-    M2<R> Ub = swp ? mrot(tr.spsi, tr.cpsi) : mrot(tr.cphi, tr.sphi);
-    M2<R> Vb = swp ? mrot(tr.sphi, tr.cphi) : mrot(tr.cpsi, tr.spsi);
-    if (swp) {
-      neg_col(Ub, 1);
-      neg_col(Vb, 1);
-    }
-    M2<R> U;
-    if (tb1 & CL13) {
-      // U = U_+ U_bphi P_sigma: U_+ is a signed permutation
-      U = M2<R>{Up.a * Ub.a + Up.b * Ub.c, Up.a * Ub.b + Up.b * Ub.d,
-                Up.c * Ub.a + Up.d * Ub.c, Up.c * Ub.b + Up.d * Ub.d};
+    // common right factor S2 P_sigma (S2 = diag(1,-1) when swapped); the
+    // rotations of eq. RT are rot(sin psi, cos psi), rot(sin phi, cos phi) then
+    SP RT = sp_mul(sp_diag(false, swp), sp_x(tr.psig));
+    R cu_ = swp ? tr.spsi : tr.cphi, su_ = swp ? tr.cpsi : tr.sphi;
+    R cv_ = swp ? tr.sphi : tr.cpsi, sv_ = swp ? tr.cphi : tr.spsi;
+    part.V = fac(VL, cv_, sv_, RT);  // V = V_+ V_bpsi P_sigma
+    if (!is15) {
+      part.U = fac(UL, cu_, su_, RT);  // U = U_+ U_bphi P_sigma
     } else {
       // class 15: merge U_theta and U_bphi into one rotation by tan(bphi +- theta)
+      // (eqs. p+t, p-t, tan+-); S22 = diag(1, sgn r22) joins the left factor
       R tbp = swp ? (R)1 / tr.tpsi : tr.tphi;
       R ca, sa;
       if (isinf(tbp)) {
@@ -712,29 +765,16 @@ template <class R> __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11,
           sa = sd * (ta / sa_sec);
         }
       }
-      U = mrot(ca, sa);
-      if (swp) neg_col(U, 1);     // S2
-      if (s22neg) neg_row(U, 1);  // S22 on the left
-      if (pu15) swap_rows(U);
-      if (s1n0) neg_row(U, 0);
-      if (s1n1) neg_row(U, 1);
+      part.U = fac(sp_mul(UL, sp_diag(false, s22neg)), ca, sa, RT);
     }
-    M2<R> V = M2<R>{Vp.a * Vb.a + Vp.b * Vb.c, Vp.a * Vb.b + Vp.b * Vb.d,
-                    Vp.c * Vb.a + Vp.d * Vb.c, Vp.c * Vb.b + Vp.d * Vb.d};
-    if (tr.psig) {
-      swap_cols(U);
-      swap_cols(V);
-    }
-    part.U = U;
-    part.V = V;
     part.s1 = tr.s1;
     part.s2 = tr.s2;
   }
 
   // backscale: sigma_i = 2^-s (.) sigma~_i' (Sect. 3.3.2)
   bool nu_, nv_;
-  put_uv(part.U, out.cu, out.su, nu_);
-  put_uv(part.V, out.cv, out.sv, nv_);
+  fac_out(part.U, out.cu, out.su, nu_);
+  fac_out(part.V, out.cv, out.sv, nv_);
   if (nu_) info |= I_DETU;
   if (nv_) info |= I_DETV;
   out.f1 = part.s1.f;
