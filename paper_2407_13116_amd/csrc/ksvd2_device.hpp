@@ -279,7 +279,56 @@ __device__ __attribute__((always_inline)) inline float hypot1_le1(float t) {
 }
 
 // ---------------------------------------------------------------------------
-// (e,f) pairs (Sect. 2, eqs. unary, binary, plus, minus, prec).
+// Divisions.  hipcc lowers a binary64 a / b to a reciprocal estimate, two
+// Newton steps, a product, its residual and one correction (Markstein's
+// scheme), bracketed by two range-scaling instructions and a fix-up for
+// special operands.  Where the operands are known to need no scaling (normal
+// operands and quotient, numerator above 2^-960, divisor below 2^1020) the
+// bracket does nothing and is left out; one reciprocal then also serves two
+// numerators.  The results are the IEEE quotients, bit for bit.  binary32 keeps
+// the plain (correctly rounded) division.
+// ---------------------------------------------------------------------------
+__device__ inline double rcp_refined(double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-b, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline double div_with(double a, double b, double y) {
+  double q = a * y;
+  double r = fma(-b, q, a);
+  return fma(r, y, q);
+}
+
+// a / b for a, b in [1/2, 1) (mantissas in frexp form)
+__device__ inline double div_unit(double a, double b) { return div_with(a, b, rcp_refined(b)); }
+__device__ inline float div_unit(float a, float b) { return a / b; }
+
+// c = 1 / sec and s = t / sec, where sec = sqrt(1 + t^2) rounded (the secant of
+// the angle with tangent t): the quotients are normal whenever t is 0 or
+// |t| >= 2^-960, so only a huge secant or a tiny tangent takes the plain route.
+__device__ inline void cos_sin(double t, double sec, double &c, double &s) {
+  if (sec <= 0x1p1020 && (t == 0.0 || fabs(t) >= 0x1p-960)) {
+    double y = rcp_refined(sec);
+    c = div_with(1.0, sec, y);
+    s = (t == 0.0) ? t : div_with(t, sec, y);
+  } else {
+    c = 1.0 / sec;
+    s = t / sec;
+  }
+}
+__device__ inline void cos_sin(float t, float sec, float &c, float &s) {
+  c = 1.0f / sec;
+  s = t / sec;
+}
+
+// ---------------------------------------------------------------------------
+// (e,f) pairs (Sect. 2, eqs. unary, binary, plus, minus, prec).  Kept as frexp
+// returns them: x = f 2^e with f in [1/2, 1), and (0, 0) for zero; the pair of
+// the paper is (e - 1, 2 f), formed on output.  The two forms differ by exact
+// power-of-two scalings, so every product, quotient and comparison rounds and
+// orders as in the paper's form.
 // ---------------------------------------------------------------------------
 template <class R> struct EF {
   int e;
@@ -288,15 +337,7 @@ template <class R> struct EF {
 
 template <class R> __device__ inline EF<R> nrm(R x) {  // N(x)
   EF<R> r;
-  if (x == (R)0) {
-    r.e = 0;
-    r.f = (R)0;
-  } else {
-    int e;
-    R m = frexp_w(x, &e);  // x = m 2^e, |m| in [1/2, 1)
-    r.e = e - 1;
-    r.f = m * (R)2;
-  }
+  r.f = frexp_w(x, &r.e);  // frexp(0) = (0, 0)
   return r;
 }
 
@@ -307,15 +348,17 @@ template <class R> __device__ inline EF<R> ef_twice(EF<R> x) {  // 2 (.) x
   return x;
 }
 
+// products and quotients of non-zero pairs: the mantissa product lies in
+// [1/4, 1) and the quotient in (1/2, 2), both normal and non-zero
 template <class R> __device__ inline EF<R> ef_mul(EF<R> x, EF<R> y) {
   EF<R> z = nrm(x.f * y.f);
-  if (z.f != (R)0) z.e += x.e + y.e;
+  z.e += x.e + y.e;
   return z;
 }
 
 template <class R> __device__ inline EF<R> ef_div(EF<R> x, EF<R> y) {
-  EF<R> z = nrm(x.f / y.f);
-  if (z.f != (R)0) z.e += x.e - y.e;
+  EF<R> z = nrm(div_unit(x.f, y.f));
+  z.e += x.e - y.e;
   return z;
 }
 
@@ -531,7 +574,9 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R
   if (sw) { R t2 = a; a = b; b = t2; }
   R tn = b / a;
   R sec = hypot1_le1(tn);  // 0 <= tan <= 1
-  Fac<R> W = fac(sp_mul(sp_diag(na, nb), sp_x(sw)), (R)1 / sec, tn / sec, sp_id());
+  R gc, gs;
+  cos_sin(tn, sec, gc, gs);
+  Fac<R> W = fac(sp_mul(sp_diag(na, nb), sp_x(sw)), gc, gs, sp_id());
   Fac<R> P = fac(sp_x(pfirst), (R)1, (R)0, sp_id());
   Part<R> r;
   r.U = col ? W : P;
@@ -551,28 +596,37 @@ template <class R> struct Tri {
 template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a, R b, R d) {
   const R inf = (R)INFINITY;
   Tri<R> o;
-  // Algorithm tf: tan(2 phi), cases in their listed order
-  R t2;
-  if (a == d) {
-    t2 = ((R)2 * d) / b;  // eq. t2f''
-  } else if (b == d) {    // eq. t2f'''
-    t2 = flo(ef_div(ef_mul(ef_twice(nrm(b)), nrm(d)), ef_mul(nrm(a), nrm(a))));
-  } else if (a / b < Lim<R>::eps()) {
-    t2 = ((R)2 * d) / b;  // eq. t2f''
-  } else {
-    R h = hypot_cr(a, b);
-    if (h == d) {
-      t2 = inf;
+  // Algorithm tf: tan(2 phi), cases in their listed order.  The two cases that
+  // end in the (e,f) quotient 2bd / (x y) share one copy of it (x = y = a for
+  // eq. t2f''', x, y = h -+ d in the general case), and so do the two cases of
+  // eq. t2f'', so lanes of a wave that take different cases do not execute
+  // them twice.
+  R t2 = (R)0;
+  bool simple = (a == d);  // eq. t2f''
+  bool ef_case = false;
+  EF<R> x = nrm(a), y = x;
+  if (!simple) {
+    if (b == d) {  // eq. t2f'''
+      ef_case = true;
+    } else if (a / b < Lim<R>::eps()) {
+      simple = true;  // eq. t2f''
     } else {
-      EF<R> sm = ef_plus(h, d), df = ef_minus(h, d);
-      t2 = flo(ef_div(ef_mul(ef_twice(nrm(b)), nrm(d)), ef_mul(df, sm)));
+      R h = hypot_cr(a, b);
+      if (h == d) {
+        t2 = inf;
+      } else {
+        y = ef_plus(h, d);
+        x = ef_minus(h, d);
+        ef_case = true;
+      }
     }
   }
+  if (simple) t2 = ((R)2 * d) / b;
+  if (ef_case) t2 = flo(ef_div(ef_mul(ef_twice(nrm(b)), nrm(d)), ef_mul(x, y)));
   R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hypot_cr(t2, (R)1));  // eq. tf
   R sphi_sec = hypot1_le1(tphi);  // 0 <= tan(phi) <= 1
   o.tphi = tphi;
-  o.cphi = (R)1 / sphi_sec;
-  o.sphi = tphi / sphi_sec;
+  cos_sin(tphi, sphi_sec, o.cphi, o.sphi);
   // Algorithm tp
   R tt = fma(d, tphi, b);
   R tpsi = tt / a;
@@ -589,8 +643,7 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
   } else {  // eq. s'
     o.ovf = false;
     R spsi_sec = hypot_cr(tpsi, (R)1);
-    o.cpsi = (R)1 / spsi_sec;
-    o.spsi = tpsi / spsi_sec;
+    cos_sin(tpsi, spsi_sec, o.cpsi, o.spsi);
     EF<R> sp = ef_div(nrm(sphi_sec), nrm(spsi_sec));
     s1 = ef_div(nrm(a), sp);
     s2 = ef_mul(nrm(d), sp);
@@ -645,8 +698,12 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
   R tan_t = 0, sec_t = 1;
   bool is15 = false, s22neg = false;
 
-  if (tb1 & (CL9 | CL3 | CL5)) {
-    part = (tb1 & CL9) ? part9(G, t1) : part35(G, t1);
+  // the simple classes of Sect. 3.1, entered directly or from the degenerate
+  // exit of class 15 (one inlined copy serves both)
+  bool simple = (tb1 & (CL9 | CL3 | CL5)) != 0, degen = false;
+  M2<R> Gs = G;
+  int ts = t1;
+  if (simple) {
   } else if (tb1 & CL13) {
     // Sect. 3.2.1: permute into [x y; 0 z], then three sign changes:
     // U_+ = P_U S11 S22 = P_U diag(sgn x, sgn z'), V_+ = P_V S12 = P_V diag(1, sgn y')
@@ -711,11 +768,9 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
       // finished as in Sect. 3.1; U = S_1 P_U U_theta U_R, V = P_V V_R, where
       // U_R is a signed permutation in both cases
       info |= I_DEGEN;
-      M2<R> Rpp = M2<R>{r11, r12, (R)0, r22};
-      int t2 = ztype(Rpp.a, Rpp.c, Rpp.b, Rpp.d);
-      part = (t2 == 5) ? part35(Rpp, t2) : part9(Rpp, t2);
-      part.U = fac(UL, (R)1 / sec_t, tan_t / sec_t, part.U.L);
-      part.V = fac(sp_mul(VL, part.V.L), part.V.c, part.V.s, part.V.Rt);
+      Gs = M2<R>{r11, r12, (R)0, r22};
+      ts = ztype(Gs.a, Gs.c, Gs.b, Gs.d);
+      simple = degen = true;
     } else {
       bool n12 = negative(r12);
       if (n12) r22 = -r22;
@@ -727,11 +782,22 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
     }
   }
 
+  if (simple) {
+    part = ((1u << ts) & CL9) ? part9(Gs, ts) : part35(Gs, ts);
+    if (degen) {
+      R ct, st;
+      cos_sin(tan_t, sec_t, ct, st);
+      part.U = fac(UL, ct, st, part.U.L);
+      part.V = fac(sp_mul(VL, part.V.L), part.V.c, part.V.s, part.V.Rt);
+    }
+  }
+
   if (tri) {
     // phase 3: swap the diagonal through R^T (eq. RT) if r11 < r22
     bool swp = r11 < r22;
     if (swp) info |= I_RSWAP;
-    Tri<R> tr = swp ? tri_svd(r22, r12, r11) : tri_svd(r11, r12, r22);
+    R ta_ = swp ? r22 : r11, td_ = swp ? r11 : r22;  // one inlined copy for both cases
+    Tri<R> tr = tri_svd(ta_, r12, td_);
     if (tr.ovf) info |= I_TPSI_OVF;
     if (tr.psig) info |= I_PSIG;
     // common right factor S2 P_sigma (S2 = diag(1,-1) when swapped); the
@@ -748,7 +814,8 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
       R tbp = swp ? (R)1 / tr.tpsi : tr.tphi;
       R ca, sa;
       if (isinf(tbp)) {
-        R ct = (R)1 / sec_t, st = tan_t / sec_t;
+        R ct, st;
+        cos_sin(tan_t, sec_t, ct, st);
         ca = s22neg ? st : -st;
         sa = ct;
       } else {
@@ -761,8 +828,10 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
           R ta = num / den;
           R sa_sec = hypot_cr(ta, (R)1);
           R sd = negative(den) ? (R)-1 : (R)1;
-          ca = sd * ((R)1 / sa_sec);
-          sa = sd * (ta / sa_sec);
+          R c0, s0;
+          cos_sin(ta, sa_sec, c0, s0);
+          ca = sd * c0;
+          sa = sd * s0;
         }
       }
       part.U = fac(sp_mul(UL, sp_diag(false, s22neg)), ca, sa, RT);
@@ -777,10 +846,10 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
   fac_out(part.V, out.cv, out.sv, nv_);
   if (nu_) info |= I_DETU;
   if (nv_) info |= I_DETV;
-  out.f1 = part.s1.f;
-  out.f2 = part.s2.f;
-  out.e1 = (part.s1.f != (R)0) ? part.s1.e - s : 0;
-  out.e2 = (part.s2.f != (R)0) ? part.s2.e - s : 0;
+  out.f1 = part.s1.f * (R)2;  // frexp form -> the paper's (e, f), f in [1, 2)
+  out.f2 = part.s2.f * (R)2;
+  out.e1 = (part.s1.f != (R)0) ? part.s1.e - 1 - s : 0;
+  out.e2 = (part.s2.f != (R)0) ? part.s2.e - 1 - s : 0;
   out.info = info | ((uint32_t)(uint16_t)(int16_t)s << 16);
   return out;
 }
