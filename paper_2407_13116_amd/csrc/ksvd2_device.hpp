@@ -50,21 +50,11 @@ __device__ inline int ilog2(float x) {
 }
 
 // x 2^n rounded once to nearest-even, as IEEE scaleB: exact while the result
-// is normal, gradual underflow below that, +-inf on overflow.
-__device__ inline double scale2(double x, int n) {
-  if (x == 0.0) return x;
-  int r = ilog2(x) + n;
-  if (r >= -1022) return ldexp(x, n);
-  if (r < -1075) return copysign(0.0, x);
-  return ldexp(x, n + 128) * 0x1p-128;  // exact step, then one IEEE rounding
-}
-__device__ inline float scale2(float x, int n) {
-  if (x == 0.0f) return x;
-  int r = ilog2(x) + n;
-  if (r >= -126) return ldexpf(x, n);
-  if (r < -150) return copysignf(0.0f, x);
-  return ldexpf(x, n + 64) * 0x1p-64f;
-}
+// is normal, gradual underflow below that, +-inf on overflow.  v_ldexp_f64 and
+// v_ldexp_f32 are IEEE scaleB (with denormals enabled, as this library is
+// built), so this is one instruction.
+__device__ inline double scale2(double x, int n) { return ldexp(x, n); }
+__device__ inline float scale2(float x, int n) { return ldexpf(x, n); }
 
 __device__ inline double ldexp_w(double x, int n) { return ldexp(x, n); }
 __device__ inline double frexp_w(double x, int *e) { return frexp(x, e); }
@@ -323,6 +313,26 @@ __device__ inline void cos_sin(float t, float sec, float &c, float &s) {
   s = t / sec;
 }
 
+// a1 / sec and a2 / sec for sec in [1, 2): one reciprocal serves both wherever
+// 2^-960 <= |a_i| <= 2^1020 (normal quotients, exact residuals); zero and
+// extreme numerators take the plain division.
+__device__ inline void div_by_sec(double a1, double a2, double sec, double &q1, double &q2) {
+  bool f1 = fabs(a1) >= 0x1p-960 && fabs(a1) <= 0x1p1020;
+  bool f2 = fabs(a2) >= 0x1p-960 && fabs(a2) <= 0x1p1020;
+  if (f1 && f2) {
+    double y = rcp_refined(sec);
+    q1 = div_with(a1, sec, y);
+    q2 = div_with(a2, sec, y);
+  } else {
+    q1 = a1 / sec;
+    q2 = a2 / sec;
+  }
+}
+__device__ inline void div_by_sec(float a1, float a2, float sec, float &q1, float &q2) {
+  q1 = a1 / sec;
+  q2 = a2 / sec;
+}
+
 // ---------------------------------------------------------------------------
 // (e,f) pairs (Sect. 2, eqs. unary, binary, plus, minus, prec).  Kept as frexp
 // returns them: x = f 2^e with f in [1/2, 1), and (0, 0) for zero; the pair of
@@ -411,16 +421,20 @@ __device__ inline float ext_w(float x1, float y1, float x2, float y2, float d) {
 
 __device__ __attribute__((always_inline)) inline double ext_w(double x1, double y1, double x2, double y2,
                                                              double d) {
-  int a1 = ilog2(x1), b1 = ilog2(y1), a2 = ilog2(x2), b2 = ilog2(y2);
+  // factors as frexp mantissas in [1/2, 1): each product of two is 4 times
+  // smaller than the product of the [1, 2) mantissas, and the scalings below
+  // carry the factor 4 back before anything can round
+  int a1, b1, a2, b2;
+  double m1 = frexp(x1, &a1), n1 = frexp(y1, &b1), m2 = frexp(x2, &a2), n2 = frexp(y2, &b2);
   int k1 = a1 + b1, k2 = a2 + b2;
   int K = k1 > k2 ? k1 : k2;
   double p1h, p1l, p2h, p2l;
-  two_prod(ldexp(x1, -a1), ldexp(y1, -b1), p1h, p1l);
-  two_prod(ldexp(x2, -a2), ldexp(y2, -b2), p2h, p2l);
-  p1h = scale2(p1h, k1 - K);
-  p1l = scale2(p1l, k1 - K);
-  p2h = scale2(p2h, k2 - K);
-  p2l = scale2(p2l, k2 - K);
+  two_prod(m1, n1, p1h, p1l);
+  two_prod(m2, n2, p2h, p2l);
+  p1h = scale2(p1h, k1 - K + 2);
+  p1l = scale2(p1l, k1 - K + 2);
+  p2h = scale2(p2h, k2 - K + 2);
+  p2l = scale2(p2l, k2 - K + 2);
   // AccurateDWPlusDW
   double sh, sl, th, tl, vh, vl, xh, xl;
   two_sum(p1h, p2h, sh, sl);
@@ -437,7 +451,7 @@ __device__ __attribute__((always_inline)) inline double ext_w(double x1, double 
   double dl = ((xh - ph) + (xl - pl)) / dm;
   double zh, zl;
   fast_two_sum(qh, dl, zh, zl);
-  return scale2(zh, K - ed);
+  return scale2(zh, K - 2 - ed);  // K counts the two factors of 2 of the frexp form
 }
 
 // ---------------------------------------------------------------------------
@@ -748,17 +762,18 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
     bool same = negative(G.b) == negative(G.d);
     // the element without cancellation: r12 (same signs) or r22 (opposite)
     R P = same ? G.d : -G.b, Q = same ? G.b : G.d;
-    R rgood = fma(P, tan_t, Q) / sec_t;
-    R rother;
+    R ngood = fma(P, tan_t, Q), nother;
     if (exact) {
       R P2 = same ? -G.b : G.d, Q2 = same ? G.d : G.b;
-      rother = fma(P2, tan_t, Q2) / sec_t;
+      nother = fma(P2, tan_t, Q2);
     } else {
       // eq. EXT: r22 = (g22 g11 - g12 g21)/g11/sec or r12 = (g12 g11 + g22 g21)/g11/sec
       R x1 = same ? G.d : G.b, x2 = same ? -G.b : G.d;
-      rother = ext_w(x1, G.a, x2, G.c, G.a) / sec_t;
+      nother = ext_w(x1, G.a, x2, G.c, G.a);
       info |= I_EXT;
     }
+    R rgood, rother;
+    div_by_sec(ngood, nother, sec_t, rgood, rother);
     r12 = same ? rgood : rother;
     r22 = same ? rother : rgood;
     UL = sp_mul(sp_diag(s1n0, s1n1), sp_x(pu15));  // S_1 P_U
