@@ -12,15 +12,21 @@
 // A sweep is n - 1 steps; after each sweep the off-diagonal Frobenius norm
 // is compared with tol_factor * n * eps * ||G_0||_F.
 //
+// Only G feeds the next step's pivots, so step 4 is deferred: the rotations of
+// kChunk consecutive steps are kept in a table, and U and V are brought up to
+// date once per chunk, a tile of rows at a time in LDS.  Each row of U or V
+// receives exactly the same rotations in the same order as with per-step
+// updates; deferring changes the memory traffic, not a single bit.
+//
 // Executions of exactly the same arithmetic:
-//   mode 0  plain per-step launches: a pivot kernel and an update kernel per
-//           step, a check kernel per sweep, the host polls convergence;
-//   mode 1  persistent: one workgroup per matrix runs all its sweeps (pivot
-//           parameters in LDS, workgroup barriers between phases), one launch
-//           per size bucket, no host round trips;
+//   mode 0  plain per-step launches: a pivot kernel and a G kernel per step,
+//           a U/V kernel per chunk, a check kernel per sweep, the host polls
+//           convergence;
+//   mode 1  persistent: one workgroup per matrix runs all its sweeps (step
+//           parameters and the U/V tile in LDS, workgroup barriers between
+//           phases), one launch per size bucket, no host round trips;
 //   mode 2  mode 1 captured once into a hipGraph and replayed.
-// Every element's sequence of operations is identical in all modes, and the
-// reductions use a fixed order, so the results are bitwise identical.
+// The reductions use a fixed order, so the results are bitwise identical.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,23 +42,30 @@
 
 namespace ksvd2 {
 
-constexpr int kRed = 256;       // lanes of the fixed-order reductions
-constexpr int kMaxOrder = 8192; // pair indices are stored as int16
+constexpr int kRed = 256;        // lanes of the fixed-order reductions
+constexpr int kMaxOrder = 8192;  // pair indices are stored as int16
+constexpr int kChunk = 16;       // steps whose U/V rotations are applied together
+constexpr int kApplyBlock = 256; // workgroup of the mode-0 U/V kernel
+constexpr size_t kApplyLds = 64 * 1024;
 
 struct SweepDesc {
   const int32_t *n;      // order of matrix m
   const int64_t *off;    // element offset of matrix m in G, U, V
   const int64_t *soff;   // offset of matrix m in sigma
-  const int64_t *poff;   // offset of matrix m's pivots in the parameter table
+  const int64_t *poff;   // sum of n/2 over the matrices before m
   double *fro2;          // ||G_0||_F^2
   int32_t *sweeps;       // sweeps done so far
   int32_t *done;         // converged flag
 };
 
-// slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
-// slots 1..n-1 rotate by one position per step; slots s and n-1-s meet
+// Slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
+// slots 1..n-1 rotate by one position per step; slots s and n-1-s meet.
+// For 0 <= k <= n-2 and 1 <= s <= n-1, s - 1 + k < 2(n-1), so one conditional
+// subtraction is the remainder.
 __device__ inline int rr_player(int n, int k, int s) {
-  return s == 0 ? 0 : 1 + (s - 1 + k) % (n - 1);
+  if (s == 0) return 0;
+  int x = s - 1 + k;
+  return 1 + (x >= n - 1 ? x - (n - 1) : x);
 }
 
 __device__ inline void rr_pair(int n, int k, int q, int &i, int &j) {
@@ -86,55 +99,143 @@ template <class R> __device__ inline Piv<R> pivot_svd(const R *G, int n, int i, 
 
 template <class R> __device__ inline R lin(R a, R x, R b, R y) { return fma(a, x, b * y); }
 
-// One update item of step k, for a matrix of order n.  Items [0, np^2) are
-// the 2x2 blocks (p, q) of G (rows of pivot p, columns of pivot q); items
-// [np^2, np^2 + n np) rotate U[r, i_q], U[r, j_q]; the next n np items do the
-// same for V.  `pair(q, i, j)` and `piv(q)` read the step's tables.
-template <class R, class PairF, class PivF>
-__device__ inline void update_item(int64_t w, int n, R *G, R *U, R *V, PairF pair, PivF piv) {
-  int np = n >> 1;
-  int64_t nb = (int64_t)np * np;
-  if (w < nb) {
-    int p = (int)(w % np), q = (int)(w / np);
-    int ip, jp, iq, jq;
-    pair(p, ip, jp);
-    if (p == q) {
-      Piv<R> P = piv(p);
-      G[ip + (int64_t)ip * n] = P.s1;
-      G[jp + (int64_t)jp * n] = P.s2;
-      G[ip + (int64_t)jp * n] = (R)0;
-      G[jp + (int64_t)ip * n] = (R)0;
-      return;
+// ------------------------------------------------------------- the G update
+//
+// Block (p, q) of step k: rows (i_p, j_p) x columns (i_q, j_q).  Rows first
+// (row_i' = u11 row_i + u21 row_j, row_j' = u12 row_i + u22 row_j), then
+// columns (col_i' = col_i v11 + col_j v21, col_j' = col_i v12 + col_j v22);
+// the diagonal blocks become diag(sigma_1, sigma_2).
+
+template <class R>
+__device__ inline void g_block_store(R *G, int n, int ip, int jp, int iq, int jq, const Piv<R> &Pp,
+                                     const Piv<R> &Pq, R a, R b, R c, R d) {
+  R a1 = lin(Pp.u11, a, Pp.u21, b), b1 = lin(Pp.u12, a, Pp.u22, b);
+  R c1 = lin(Pp.u11, c, Pp.u21, d), d1 = lin(Pp.u12, c, Pp.u22, d);
+  R *ci = G + (int64_t)iq * n, *cj = G + (int64_t)jq * n;
+  ci[ip] = lin(Pq.v11, a1, Pq.v21, c1);
+  cj[ip] = lin(Pq.v12, a1, Pq.v22, c1);
+  ci[jp] = lin(Pq.v11, b1, Pq.v21, d1);
+  cj[jp] = lin(Pq.v12, b1, Pq.v22, d1);
+}
+
+template <class R>
+__device__ inline void g_diag_store(R *G, int n, int i, int j, const Piv<R> &P) {
+  G[i + (int64_t)i * n] = P.s1;
+  G[j + (int64_t)j * n] = P.s2;
+  G[i + (int64_t)j * n] = (R)0;
+  G[j + (int64_t)i * n] = (R)0;
+}
+
+// all np^2 blocks of one step by one workgroup of BS lanes, four blocks per
+// lane in flight (all loads issued before the first store)
+template <class R, int BS>
+__device__ void g_step_block(R *G, int n, const Piv<R> *P, const int16_t *pr) {
+  const int np = n >> 1;
+  const int dp = BS % np, dq = BS / np;
+  // block w = p + q np, walked with stride BS by carries
+  int p = threadIdx.x % np, q = threadIdx.x / np;
+  while (q < np) {
+    R a[4], b[4], c[4], d[4];
+    int ip[4], jp[4], iq[4], jq[4], pp[4], qq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pp[u] = -1;
+      if (q < np) {
+        pp[u] = p;
+        qq[u] = q;
+        ip[u] = pr[2 * p];
+        jp[u] = pr[2 * p + 1];
+        iq[u] = pr[2 * q];
+        jq[u] = pr[2 * q + 1];
+        if (p != q) {
+          const R *ci = G + (int64_t)iq[u] * n, *cj = G + (int64_t)jq[u] * n;
+          a[u] = ci[ip[u]];
+          b[u] = ci[jp[u]];
+          c[u] = cj[ip[u]];
+          d[u] = cj[jp[u]];
+        }
+        p += dp;
+        q += dq;
+        if (p >= np) {
+          p -= np;
+          q += 1;
+        }
+      }
     }
-    pair(q, iq, jq);
-    Piv<R> Pp = piv(p), Pq = piv(q);
-    R *ci = G + (int64_t)iq * n, *cj = G + (int64_t)jq * n;
-    R a = ci[ip], b = ci[jp], c = cj[ip], d = cj[jp];  // rows (ip, jp) x cols (iq, jq)
-    // rows: row_i' = u11 row_i + u21 row_j, row_j' = u12 row_i + u22 row_j
-    R a1 = lin(Pp.u11, a, Pp.u21, b), b1 = lin(Pp.u12, a, Pp.u22, b);
-    R c1 = lin(Pp.u11, c, Pp.u21, d), d1 = lin(Pp.u12, c, Pp.u22, d);
-    // columns: col_i' = col_i v11 + col_j v21, col_j' = col_i v12 + col_j v22
-    ci[ip] = lin(Pq.v11, a1, Pq.v21, c1);
-    cj[ip] = lin(Pq.v12, a1, Pq.v22, c1);
-    ci[jp] = lin(Pq.v11, b1, Pq.v21, d1);
-    cj[jp] = lin(Pq.v12, b1, Pq.v22, d1);
-    return;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (pp[u] < 0) continue;
+      if (pp[u] == qq[u])
+        g_diag_store(G, n, ip[u], jp[u], P[pp[u]]);
+      else
+        g_block_store(G, n, ip[u], jp[u], iq[u], jq[u], P[pp[u]], P[qq[u]], a[u], b[u], c[u],
+                      d[u]);
+    }
   }
-  w -= nb;
-  int64_t nu = (int64_t)n * np;
-  bool isv = w >= nu;
-  if (isv) w -= nu;
-  int r = (int)(w % n), q = (int)(w / n);
-  int iq, jq;
-  pair(q, iq, jq);
-  Piv<R> P = piv(q);
-  R *M = isv ? V : U;
-  R e1 = isv ? P.v11 : P.u11, e2 = isv ? P.v21 : P.u21;
-  R e3 = isv ? P.v12 : P.u12, e4 = isv ? P.v22 : P.u22;
-  R *ci = M + (int64_t)iq * n, *cj = M + (int64_t)jq * n;
-  R x = ci[r], y = cj[r];
-  ci[r] = lin(e1, x, e2, y);
-  cj[r] = lin(e3, x, e4, y);
+}
+
+// ------------------------------------------------------------ the U/V update
+//
+// Rows [r0, r0 + nr) of M (U or V, column-major n x n) are copied into an LDS
+// tile T (row-major, row stride n + 1), rotated by the pivots of steps
+// k0..k1 (whose parameters are in `tab`, slot k % kChunk, np per slot), and
+// copied back.  Each wave owns whole rows of the tile (rows w, w + nw, ...),
+// its lanes split a step's pivots, so a step only needs the wave's own
+// preceding LDS writes: waves never wait for each other inside a chunk.
+
+// element e = r + c nr of the tile, walked with stride blockDim.x (one
+// division per thread, then carries)
+template <class R, bool kLoad>
+__device__ void tile_copy(R *T, R *M, int n, int r0, int nr) {
+  const int ldt = n + 1;
+  const int bs = blockDim.x, dr = bs % nr, dc = bs / nr;
+  int r = threadIdx.x % nr, c = threadIdx.x / nr;
+  for (; c < n; r += dr, c += dc) {
+    if (r >= nr) {
+      r -= nr;
+      c += 1;
+      if (c >= n) break;
+    }
+    if (kLoad)
+      T[r * ldt + c] = M[r0 + r + (int64_t)c * n];
+    else
+      M[r0 + r + (int64_t)c * n] = T[r * ldt + c];
+  }
+}
+template <class R> __device__ void tile_load(R *T, const R *M, int n, int r0, int nr) {
+  tile_copy<R, true>(T, const_cast<R *>(M), n, r0, nr);
+}
+template <class R> __device__ void tile_store(const R *T, R *M, int n, int r0, int nr) {
+  tile_copy<R, false>(const_cast<R *>(T), M, n, r0, nr);
+}
+
+template <class R>
+__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const Piv<R> *tab, bool isv) {
+  const int ldt = n + 1;
+  const int np = n >> 1;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (wv >= nr) return;  // more waves than rows: this wave has none
+  for (int k = k0; k <= k1; ++k) {
+    const Piv<R> *P = tab + (k % kChunk) * np;
+    for (int q = lane; q < np; q += 64) {
+      int i, j;
+      rr_pair(n, k, q, i, j);
+      const Piv<R> &pq = P[q];
+      R e1 = isv ? pq.v11 : pq.u11, e2 = isv ? pq.v21 : pq.u21;
+      R e3 = isv ? pq.v12 : pq.u12, e4 = isv ? pq.v22 : pq.u22;
+      for (int r = wv; r < nr; r += nw) {
+        R *row = T + r * ldt;
+        R x = row[i], y = row[j];
+        row[i] = lin(e1, x, e2, y);
+        row[j] = lin(e3, x, e4, y);
+      }
+    }
+    // the next step reads what other lanes of this wave wrote in this one
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
@@ -193,6 +294,9 @@ __device__ void finish_matrix(const R *G, int n, R *sig, int32_t *sweeps_out, in
   if (threadIdx.x == 0 && sweeps_out) *sweeps_out = conv ? sweeps : -sweeps;
 }
 
+// the first step of the chunk that ends with step k
+__device__ inline int chunk_begin(int k) { return k - k % kChunk; }
+
 // ----------------------------------------------------------- mode 0 kernels
 
 template <class R>
@@ -219,33 +323,61 @@ __global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, P
   if (q >= np || k >= n - 1 || d.done[m]) return;
   int i, j;
   rr_pair(n, k, q, i, j);
-  int64_t po = d.poff[m];
-  pairs[2 * (po + q)] = (int16_t)i;
-  pairs[2 * (po + q) + 1] = (int16_t)j;
-  par[po + q] = pivot_svd(G + d.off[m], n, i, j);
+  int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
+  pairs[2 * (slot + q)] = (int16_t)i;
+  pairs[2 * (slot + q) + 1] = (int16_t)j;
+  par[slot + q] = pivot_svd(G + d.off[m], n, i, j);
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, R *U, R *V,
-                                                      const Piv<R> *par, const int16_t *pairs,
-                                                      int k) {
+__global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, const Piv<R> *par,
+                                                      const int16_t *pairs, int k) {
   int m = blockIdx.y;
   int n = d.n[m];
   if (k >= n - 1 || d.done[m]) return;
   int np = n >> 1;
-  int64_t items = (int64_t)np * np + 2 * (int64_t)n * np;
-  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= items) return;
-  int64_t po = d.poff[m], o = d.off[m];
-  const int16_t *pt = pairs + 2 * po;
-  const Piv<R> *pp = par + po;
-  update_item<R>(
-      w, n, G + o, U + o, V + o,
-      [pt](int q, int &i, int &j) {
-        i = pt[2 * q];
-        j = pt[2 * q + 1];
-      },
-      [pp](int q) { return pp[q]; });
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= np * np) return;
+  int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
+  const int16_t *pt = pairs + 2 * slot;
+  const Piv<R> *pp = par + slot;
+  R *Gm = G + d.off[m];
+  int p = w % np, q = w / np;
+  int ip = pt[2 * p], jp = pt[2 * p + 1];
+  if (p == q) {
+    g_diag_store(Gm, n, ip, jp, pp[p]);
+    return;
+  }
+  int iq = pt[2 * q], jq = pt[2 * q + 1];
+  const R *ci = Gm + (int64_t)iq * n, *cj = Gm + (int64_t)jq * n;
+  R a = ci[ip], b = ci[jp], c = cj[ip], dd = cj[jp];
+  g_block_store(Gm, n, ip, jp, iq, jq, pp[p], pp[q], a, b, c, dd);
+}
+
+// U/V of the chunk that ends at global step k (blockIdx.y: 0 = U, 1 = V;
+// blockIdx.x: the row tile); matrices whose last step came earlier were
+// brought up to date at their own last chunk.
+template <class R>
+__global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *V,
+                                                          const Piv<R> *par, int k,
+                                                          int tile_elems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  R *T = reinterpret_cast<R *>(smem);
+  int m = blockIdx.z;
+  int n = d.n[m];
+  if (d.done[m]) return;
+  int k0 = chunk_begin(k), k1 = min(k, n - 2);
+  if (k0 > k1) return;
+  int rows = min(n, tile_elems / (n + 1));
+  int r0 = blockIdx.x * rows;
+  if (r0 >= n) return;
+  int nr = min(rows, n - r0);
+  R *M = (blockIdx.y ? V : U) + d.off[m];
+  tile_load(T, M, n, r0, nr);
+  __syncthreads();
+  tile_rotate(T, n, nr, k0, k1, par + kChunk * d.poff[m], blockIdx.y != 0);
+  __syncthreads();
+  tile_store(T, M, n, r0, nr);
 }
 
 template <class R>
@@ -272,48 +404,69 @@ __global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, const R *G, R *
 // ------------------------------------------------------- mode 1: persistent
 //
 // One workgroup per matrix (the launch covers the matrices listed in `mats`,
-// longest first).  LDS holds the step's pivot parameters and pair table; the
-// matrix itself stays in global memory (L2/MALL resident while it is hot).
+// longest first).  LDS holds the reduction buffer, the step's pivot
+// parameters and pair table, and the U/V row tile; G stays in global memory
+// (L2/MALL resident while it is hot); the chunk's rotation table is in the
+// workspace.
+
+template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int maxn) {
+  size_t b = kRed * sizeof(double) + (size_t)(maxn / 2) * sizeof(Piv<R>) + (size_t)maxn * 2;
+  return (b + 15) & ~(size_t)15;
+}
 
 template <class R, int BS>
-__global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t *mats, R *G, R *U,
-                                                      R *V, R *sigma, int32_t *sweeps_out,
-                                                      int max_sweeps, double tolf,
-                                                      int accumulate) {
+__global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t *mats, R *G,
+                                                      R *U, R *V, Piv<R> *par, R *sigma,
+                                                      int32_t *sweeps_out, int max_sweeps,
+                                                      double tolf, int accumulate, int maxn,
+                                                      int tile_elems) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *red = reinterpret_cast<double *>(smem);
+  Piv<R> *spar = reinterpret_cast<Piv<R> *>(smem + kRed * sizeof(double));
+  int16_t *spair =
+      reinterpret_cast<int16_t *>(smem + kRed * sizeof(double) + (maxn / 2) * sizeof(Piv<R>));
+  R *T = reinterpret_cast<R *>(smem + persistent_fixed_lds<R>(maxn));
   int m = mats[blockIdx.x];
   int n = d.n[m];
   int np = n >> 1;
-  Piv<R> *spar = reinterpret_cast<Piv<R> *>(smem + kRed * sizeof(double));
-  int16_t *spair = reinterpret_cast<int16_t *>(smem + kRed * sizeof(double) + np * sizeof(Piv<R>));
   int64_t o = d.off[m];
   R *Gm = G + o, *Um = U + o, *Vm = V + o;
+  Piv<R> *tab = par + kChunk * d.poff[m];
+  int rows = min(n, tile_elems / (n + 1));
   double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red);
   __syncthreads();
-  int64_t items = (int64_t)np * np + 2 * (int64_t)n * np;
   int sw = 0;
   bool conv = false;
   for (; sw < max_sweeps && !conv; ++sw) {
     for (int k = 0; k < n - 1; ++k) {
+      Piv<R> *slot = tab + (k % kChunk) * np;
       for (int q = threadIdx.x; q < np; q += BS) {
         int i, j;
         rr_pair(n, k, q, i, j);
         spair[2 * q] = (int16_t)i;
         spair[2 * q + 1] = (int16_t)j;
-        spar[q] = pivot_svd(Gm, n, i, j);
+        Piv<R> P = pivot_svd(Gm, n, i, j);
+        spar[q] = P;
+        slot[q] = P;
       }
       __syncthreads();
-      for (int64_t w = threadIdx.x; w < items; w += BS) {
-        update_item<R>(
-            w, n, Gm, Um, Vm,
-            [spair](int q, int &i, int &j) {
-              i = spair[2 * q];
-              j = spair[2 * q + 1];
-            },
-            [spar](int q) { return spar[q]; });
-      }
+      g_step_block<R, BS>(Gm, n, spar, spair);
       __syncthreads();
+      if (k % kChunk == kChunk - 1 || k == n - 2) {
+        int k0 = chunk_begin(k);
+        for (int side = 0; side < 2; ++side) {
+          R *M = side ? Vm : Um;
+          for (int r0 = 0; r0 < n; r0 += rows) {
+            int nr = min(rows, n - r0);
+            tile_load(T, M, n, r0, nr);
+            __syncthreads();
+            tile_rotate(T, n, nr, k0, k, tab, side != 0);
+            __syncthreads();
+            tile_store(T, M, n, r0, nr);
+            __syncthreads();
+          }
+        }
+      }
     }
     double off2 = block_sumsq(Gm, n, true, red);
     conv = converged(off2, fro2, n, tolf, (double)Lim<R>::eps());
@@ -383,8 +536,8 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
   L.fro2 = p;   p = align256(p + nmat * 8);
   L.sweeps = p; p = align256(p + nmat * 4);
   L.done = p;   p = align256(p + nmat * 4);
-  L.par = p;    p = align256(p + npiv * 10 * w);
-  L.pairs = p;  p = align256(p + npiv * 4);
+  L.par = p;    p = align256(p + (size_t)kChunk * npiv * 10 * w);
+  L.pairs = p;  p = align256(p + (size_t)kChunk * npiv * 4);
   L.total = p;
   return L;
 }
@@ -404,27 +557,70 @@ static int bucket_of(int n) {
   return 4;
 }
 
-template <class R> static size_t persistent_lds(int n) {
-  return kRed * sizeof(double) + (size_t)(n / 2) * sizeof(Piv<R>) + (size_t)(n / 2) * 4 + 16;
+// LDS a workgroup may allocate on the current device (queried once per device)
+static size_t device_lds_limit() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    v = 0;
+  cache[dev] = (size_t)v;
+  return (size_t)v;
+}
+
+// LDS of a persistent launch over matrices of order <= maxn: the fixed part
+// plus the largest U/V tile that fits (at least one row of maxn + 1)
+template <class R> static size_t persistent_lds(int maxn, size_t limit, int &tile_elems) {
+  size_t fixed = persistent_fixed_lds<R>(maxn);
+  tile_elems = 0;
+  if (limit <= fixed) return 0;
+  size_t te = (limit - fixed) / sizeof(R);
+  if (te < (size_t)maxn + 1) return 0;
+  te = std::min(te, (size_t)maxn * (size_t)(maxn + 1));  // never more than the whole matrix
+  tile_elems = (int)std::min<size_t>(te, (size_t)1 << 30);
+  return fixed + (size_t)tile_elems * sizeof(R);
+}
+
+template <class R, int BS> static void set_lds_attr(size_t lds) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sw_persistent<R, BS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <class R>
 static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int count, int maxn,
-                             int block, R *G, R *U, R *V, R *sigma, int32_t *sweeps_out,
-                             int max_sweeps, double tolf, int accumulate, hipStream_t st) {
-  size_t lds = persistent_lds<R>(maxn);
+                             int block, R *G, R *U, R *V, Piv<R> *par, R *sigma,
+                             int32_t *sweeps_out, int max_sweeps, double tolf, int accumulate,
+                             size_t lds_limit, hipStream_t st) {
+  int tile_elems = 0;
+  size_t lds = persistent_lds<R>(maxn, lds_limit, tile_elems);
+  if (lds == 0)
+    return fail(KSVD2_EINVAL,
+                "order %d needs more LDS than a workgroup may allocate (%zu bytes) in the "
+                "persistent modes; use mode 0",
+                maxn, lds_limit);
   switch (block) {
     case 256:
+      set_lds_attr<R, 256>(lds);
       hipLaunchKernelGGL((k_sw_persistent<R, 256>), dim3(count), dim3(256), lds, st, d, mats_dev,
-                         G, U, V, sigma, sweeps_out, max_sweeps, tolf, accumulate);
+                         G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate, maxn,
+                         tile_elems);
       break;
     case 512:
+      set_lds_attr<R, 512>(lds);
       hipLaunchKernelGGL((k_sw_persistent<R, 512>), dim3(count), dim3(512), lds, st, d, mats_dev,
-                         G, U, V, sigma, sweeps_out, max_sweeps, tolf, accumulate);
+                         G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate, maxn,
+                         tile_elems);
       break;
     case 1024:
+      set_lds_attr<R, 1024>(lds);
       hipLaunchKernelGGL((k_sw_persistent<R, 1024>), dim3(count), dim3(1024), lds, st, d,
-                         mats_dev, G, U, V, sigma, sweeps_out, max_sweeps, tolf, accumulate);
+                         mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate,
+                         maxn, tile_elems);
       break;
     default:
       return fail(KSVD2_EINVAL, "unsupported block size %d", block);
@@ -510,22 +706,33 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.done = reinterpret_cast<int32_t *>(wsb + L.done);
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
+  Piv<R> *par = reinterpret_cast<Piv<R> *>(wsb + L.par);
   if (mode == 0) {
-    Piv<R> *par = reinterpret_cast<Piv<R> *>(wsb + L.par);
     int16_t *pairs = reinterpret_cast<int16_t *>(wsb + L.pairs);
     hipLaunchKernelGGL(k_sw_init<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, U, V,
                        accumulate);
     int rc = launch_status("kog_sweep init");
     if (rc) return rc;
     int maxnp = maxn / 2;
-    int64_t maxitems = (int64_t)maxnp * maxnp + 2 * (int64_t)maxn * maxnp;
+    int64_t maxblocks = (int64_t)maxnp * maxnp;
+    // U/V tiles of the mode-0 kernel: rows of the smallest order set the count
+    const int apply_elems = (int)(kApplyLds / sizeof(R));
+    int minrows = maxn;
+    for (int64_t m = 0; m < nmat; ++m)
+      minrows = std::min(minrows, std::min(n_host[m], apply_elems / (n_host[m] + 1)));
+    if (minrows < 1)
+      return fail(KSVD2_EINVAL, "order %d too large for the U/V tile", maxn);
+    unsigned apply_tiles = (unsigned)((maxn + minrows - 1) / minrows);
     std::vector<int32_t> done(nmat);
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int k = 0; k < maxn - 1; ++k) {
         hipLaunchKernelGGL(k_sw_pivots<R>, dim3(grid_for(maxnp), (unsigned)nmat), dim3(kBlock), 0,
                            st, d, G, par, pairs, k);
-        hipLaunchKernelGGL(k_sw_update<R>, dim3(grid_for(maxitems), (unsigned)nmat),
-                           dim3(kBlock), 0, st, d, G, U, V, par, pairs, k);
+        hipLaunchKernelGGL(k_sw_update<R>, dim3(grid_for(maxblocks), (unsigned)nmat),
+                           dim3(kBlock), 0, st, d, G, par, pairs, k);
+        if (k % kChunk == kChunk - 1 || k == maxn - 2)
+          hipLaunchKernelGGL(k_sw_apply<R>, dim3(apply_tiles, 2, (unsigned)nmat),
+                             dim3(kApplyBlock), kApplyLds, st, d, U, V, par, k, apply_elems);
       }
       hipLaunchKernelGGL(k_sw_check<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, tolf);
       rc = launch_status("kog_sweep step");
@@ -558,10 +765,12 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     segs.push_back(Seg{(int)a, (int)(bb - a), n_host[order[a]], tune.block[di][b0]});
     a = bb;
   }
+  size_t lds_limit = device_lds_limit();
   auto launch_all = [&]() -> int {
     for (const Seg &s : segs) {
       int rc = launch_persistent<R>(d, order_dev + s.begin, s.count, s.maxn, s.block, G, U, V,
-                                    sigma, sweeps_out, max_sweeps, tolf, accumulate, st);
+                                    par, sigma, sweeps_out, max_sweeps, tolf, accumulate,
+                                    lds_limit, st);
       if (rc) return rc;
     }
     return KSVD2_OK;
