@@ -99,6 +99,25 @@ template <class R> __device__ inline Piv<R> pivot_svd(const R *G, int n, int i, 
 
 template <class R> __device__ inline R lin(R a, R x, R b, R y) { return fma(a, x, b * y); }
 
+// Step tables are stored by component: a slot of np pivots holds the np values
+// of u11, then of u21, u12, u22, v11, v21, v12, v22, s1, s2, so that lanes
+// reading consecutive pivots read consecutive addresses.
+constexpr int kPivComp = 10;
+enum { C_U11, C_U21, C_U12, C_U22, C_V11, C_V21, C_V12, C_V22, C_S1, C_S2 };
+
+template <class R> __device__ inline void piv_store(R *slot, int np, int q, const Piv<R> &P) {
+  slot[C_U11 * np + q] = P.u11;
+  slot[C_U21 * np + q] = P.u21;
+  slot[C_U12 * np + q] = P.u12;
+  slot[C_U22 * np + q] = P.u22;
+  slot[C_V11 * np + q] = P.v11;
+  slot[C_V21 * np + q] = P.v21;
+  slot[C_V12 * np + q] = P.v12;
+  slot[C_V22 * np + q] = P.v22;
+  slot[C_S1 * np + q] = P.s1;
+  slot[C_S2 * np + q] = P.s2;
+}
+
 // ------------------------------------------------------------- the G update
 //
 // Block (p, q) of step k: rows (i_p, j_p) x columns (i_q, j_q).  Rows first
@@ -107,68 +126,69 @@ template <class R> __device__ inline R lin(R a, R x, R b, R y) { return fma(a, x
 // the diagonal blocks become diag(sigma_1, sigma_2).
 
 template <class R>
-__device__ inline void g_block_store(R *G, int n, int ip, int jp, int iq, int jq, const Piv<R> &Pp,
-                                     const Piv<R> &Pq, R a, R b, R c, R d) {
-  R a1 = lin(Pp.u11, a, Pp.u21, b), b1 = lin(Pp.u12, a, Pp.u22, b);
-  R c1 = lin(Pp.u11, c, Pp.u21, d), d1 = lin(Pp.u12, c, Pp.u22, d);
+__device__ inline void g_block_store(R *G, int n, int ip, int jp, int iq, int jq, const R *S,
+                                     int np, int p, int q, R a, R b, R c, R d) {
+  R u11 = S[C_U11 * np + p], u21 = S[C_U21 * np + p];
+  R u12 = S[C_U12 * np + p], u22 = S[C_U22 * np + p];
+  R v11 = S[C_V11 * np + q], v21 = S[C_V21 * np + q];
+  R v12 = S[C_V12 * np + q], v22 = S[C_V22 * np + q];
+  R a1 = lin(u11, a, u21, b), b1 = lin(u12, a, u22, b);
+  R c1 = lin(u11, c, u21, d), d1 = lin(u12, c, u22, d);
   R *ci = G + (int64_t)iq * n, *cj = G + (int64_t)jq * n;
-  ci[ip] = lin(Pq.v11, a1, Pq.v21, c1);
-  cj[ip] = lin(Pq.v12, a1, Pq.v22, c1);
-  ci[jp] = lin(Pq.v11, b1, Pq.v21, d1);
-  cj[jp] = lin(Pq.v12, b1, Pq.v22, d1);
+  ci[ip] = lin(v11, a1, v21, c1);
+  cj[ip] = lin(v12, a1, v22, c1);
+  ci[jp] = lin(v11, b1, v21, d1);
+  cj[jp] = lin(v12, b1, v22, d1);
 }
 
 template <class R>
-__device__ inline void g_diag_store(R *G, int n, int i, int j, const Piv<R> &P) {
-  G[i + (int64_t)i * n] = P.s1;
-  G[j + (int64_t)j * n] = P.s2;
+__device__ inline void g_diag_store(R *G, int n, int i, int j, const R *S, int np, int p) {
+  G[i + (int64_t)i * n] = S[C_S1 * np + p];
+  G[j + (int64_t)j * n] = S[C_S2 * np + p];
   G[i + (int64_t)j * n] = (R)0;
   G[j + (int64_t)i * n] = (R)0;
 }
 
-// all np^2 blocks of one step by one workgroup of BS lanes, four blocks per
-// lane in flight (all loads issued before the first store)
-template <class R, int BS>
-__device__ void g_step_block(R *G, int n, const Piv<R> *P, const int16_t *pr) {
+// all np^2 blocks of one step by one workgroup of BS lanes, D blocks per lane
+// in flight: the loads are issued without branches (a lane past the end reads
+// block (0, 0) and stores nothing), so none of them waits for another
+template <class R, int BS, int D>
+__device__ void g_step_block(R *G, int n, const R *S, const int16_t *pr) {
   const int np = n >> 1;
   const int dp = BS % np, dq = BS / np;
   // block w = p + q np, walked with stride BS by carries
   int p = threadIdx.x % np, q = threadIdx.x / np;
   while (q < np) {
-    R a[4], b[4], c[4], d[4];
-    int ip[4], jp[4], iq[4], jq[4], pp[4], qq[4];
+    R a[D], b[D], c[D], d[D];
+    int ip[D], jp[D], iq[D], jq[D], pp[D], qq[D];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      pp[u] = -1;
-      if (q < np) {
-        pp[u] = p;
-        qq[u] = q;
-        ip[u] = pr[2 * p];
-        jp[u] = pr[2 * p + 1];
-        iq[u] = pr[2 * q];
-        jq[u] = pr[2 * q + 1];
-        if (p != q) {
-          const R *ci = G + (int64_t)iq[u] * n, *cj = G + (int64_t)jq[u] * n;
-          a[u] = ci[ip[u]];
-          b[u] = ci[jp[u]];
-          c[u] = cj[ip[u]];
-          d[u] = cj[jp[u]];
-        }
-        p += dp;
-        q += dq;
-        if (p >= np) {
-          p -= np;
-          q += 1;
-        }
-      }
+    for (int u = 0; u < D; ++u) {
+      bool ok = q < np;
+      pp[u] = ok ? p : -1;
+      qq[u] = ok ? q : 0;
+      int ps = ok ? p : 0, qs = ok ? q : 0;
+      ip[u] = pr[2 * ps];
+      jp[u] = pr[2 * ps + 1];
+      iq[u] = pr[2 * qs];
+      jq[u] = pr[2 * qs + 1];
+      const R *ci = G + (int64_t)iq[u] * n, *cj = G + (int64_t)jq[u] * n;
+      a[u] = ci[ip[u]];
+      b[u] = ci[jp[u]];
+      c[u] = cj[ip[u]];
+      d[u] = cj[jp[u]];
+      p += dp;
+      q += dq;
+      bool carry = p >= np;
+      p = carry ? p - np : p;
+      q = carry ? q + 1 : q;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < D; ++u) {
       if (pp[u] < 0) continue;
       if (pp[u] == qq[u])
-        g_diag_store(G, n, ip[u], jp[u], P[pp[u]]);
+        g_diag_store(G, n, ip[u], jp[u], S, np, pp[u]);
       else
-        g_block_store(G, n, ip[u], jp[u], iq[u], jq[u], P[pp[u]], P[qq[u]], a[u], b[u], c[u],
+        g_block_store(G, n, ip[u], jp[u], iq[u], jq[u], S, np, pp[u], qq[u], a[u], b[u], c[u],
                       d[u]);
     }
   }
@@ -184,51 +204,90 @@ __device__ void g_step_block(R *G, int n, const Piv<R> *P, const int16_t *pr) {
 // preceding LDS writes: waves never wait for each other inside a chunk.
 
 // element e = r + c nr of the tile, walked with stride blockDim.x (one
-// division per thread, then carries)
-template <class R, bool kLoad>
+// division per thread, then carries), D elements per lane in flight; the
+// loads carry no branches (a lane past the end reads element (0, 0)), only
+// the stores are predicated
+template <class R, bool kLoad, int D>
 __device__ void tile_copy(R *T, R *M, int n, int r0, int nr) {
   const int ldt = n + 1;
   const int bs = blockDim.x, dr = bs % nr, dc = bs / nr;
   int r = threadIdx.x % nr, c = threadIdx.x / nr;
-  for (; c < n; r += dr, c += dc) {
-    if (r >= nr) {
-      r -= nr;
-      c += 1;
-      if (c >= n) break;
+  while (c < n) {
+    R v[D];
+    int lr[D], lc[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      bool ok = c < n;
+      lr[u] = ok ? r : -1;
+      lc[u] = ok ? c : 0;
+      int rs = ok ? r : 0;
+      v[u] = kLoad ? M[r0 + rs + (int64_t)lc[u] * n] : T[rs * ldt + lc[u]];
+      r += dr;
+      c += dc;
+      bool carry = r >= nr;
+      r = carry ? r - nr : r;
+      c = carry ? c + 1 : c;
     }
-    if (kLoad)
-      T[r * ldt + c] = M[r0 + r + (int64_t)c * n];
-    else
-      M[r0 + r + (int64_t)c * n] = T[r * ldt + c];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      if (lr[u] < 0) continue;
+      if (kLoad)
+        T[lr[u] * ldt + lc[u]] = v[u];
+      else
+        M[r0 + lr[u] + (int64_t)lc[u] * n] = v[u];
+    }
   }
 }
-template <class R> __device__ void tile_load(R *T, const R *M, int n, int r0, int nr) {
-  tile_copy<R, true>(T, const_cast<R *>(M), n, r0, nr);
+// D: 8 elements in flight per lane for small workgroups, 4 for 1024 lanes
+// (16 waves per CU already overlap their loads, and 128 registers is the cap)
+template <class R, int D = 8> __device__ void tile_load(R *T, const R *M, int n, int r0, int nr) {
+  tile_copy<R, true, D>(T, const_cast<R *>(M), n, r0, nr);
 }
-template <class R> __device__ void tile_store(const R *T, R *M, int n, int r0, int nr) {
-  tile_copy<R, false>(const_cast<R *>(T), M, n, r0, nr);
+template <class R, int D = 8> __device__ void tile_store(const R *T, R *M, int n, int r0, int nr) {
+  tile_copy<R, false, D>(const_cast<R *>(T), M, n, r0, nr);
 }
 
-template <class R>
-__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const Piv<R> *tab, bool isv) {
+// NG of the lane's pivots (q = q0 + 64 u, u < NG) per pass; a slot past the
+// last pivot rotates the padding column n of the tile (never copied back), so
+// the loop body has no branches
+template <class R, int NG>
+__device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv) {
   const int ldt = n + 1;
   const int np = n >> 1;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (wv >= nr) return;  // more waves than rows: this wave has none
   for (int k = k0; k <= k1; ++k) {
-    const Piv<R> *P = tab + (k % kChunk) * np;
-    for (int q = lane; q < np; q += 64) {
-      int i, j;
-      rr_pair(n, k, q, i, j);
-      const Piv<R> &pq = P[q];
-      R e1 = isv ? pq.v11 : pq.u11, e2 = isv ? pq.v21 : pq.u21;
-      R e3 = isv ? pq.v12 : pq.u12, e4 = isv ? pq.v22 : pq.u22;
+    const R *S = tab + (size_t)(k % kChunk) * kPivComp * np + (isv ? C_V11 : C_U11) * np;
+    for (int q0 = lane; q0 < np; q0 += 64 * NG) {
+      R e1[NG], e2[NG], e3[NG], e4[NG];
+      int ii[NG], jj[NG];
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        int q = q0 + 64 * u;
+        bool ok = q < np;
+        int qs = ok ? q : 0;
+        int i, j;
+        rr_pair(n, k, qs, i, j);
+        ii[u] = ok ? i : n;
+        jj[u] = ok ? j : n;
+        e1[u] = S[qs];           // u11 or v11
+        e2[u] = S[np + qs];      // u21 or v21
+        e3[u] = S[2 * np + qs];  // u12 or v12
+        e4[u] = S[3 * np + qs];  // u22 or v22
+      }
       for (int r = wv; r < nr; r += nw) {
         R *row = T + r * ldt;
-        R x = row[i], y = row[j];
-        row[i] = lin(e1, x, e2, y);
-        row[j] = lin(e3, x, e4, y);
+        R x[NG], y[NG];
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+          x[u] = row[ii[u]];
+          y[u] = row[jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+          row[ii[u]] = lin(e1[u], x[u], e2[u], y[u]);
+          row[jj[u]] = lin(e3[u], x[u], e4[u], y[u]);
+        }
       }
     }
     // the next step reads what other lanes of this wave wrote in this one
@@ -236,6 +295,16 @@ __device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const Piv<R> *t
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+}
+
+template <class R>
+__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv) {
+  if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
+  const int np = n >> 1;
+  if (np <= 64)
+    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv);
+  else
+    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv);
 }
 
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
@@ -314,7 +383,7 @@ __global__ __launch_bounds__(kRed) void k_sw_init(SweepDesc d, const R *G, R *U,
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, Piv<R> *par,
+__global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, R *par,
                                                       int16_t *pairs, int k) {
   int m = blockIdx.y;
   int n = d.n[m];
@@ -326,11 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, P
   int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
   pairs[2 * (slot + q)] = (int16_t)i;
   pairs[2 * (slot + q) + 1] = (int16_t)j;
-  par[slot + q] = pivot_svd(G + d.off[m], n, i, j);
+  piv_store(par + slot * kPivComp, np, q, pivot_svd(G + d.off[m], n, i, j));
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, const Piv<R> *par,
+__global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, const R *par,
                                                       const int16_t *pairs, int k) {
   int m = blockIdx.y;
   int n = d.n[m];
@@ -340,18 +409,18 @@ __global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, const P
   if (w >= np * np) return;
   int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
   const int16_t *pt = pairs + 2 * slot;
-  const Piv<R> *pp = par + slot;
+  const R *S = par + slot * kPivComp;
   R *Gm = G + d.off[m];
   int p = w % np, q = w / np;
   int ip = pt[2 * p], jp = pt[2 * p + 1];
   if (p == q) {
-    g_diag_store(Gm, n, ip, jp, pp[p]);
+    g_diag_store(Gm, n, ip, jp, S, np, p);
     return;
   }
   int iq = pt[2 * q], jq = pt[2 * q + 1];
   const R *ci = Gm + (int64_t)iq * n, *cj = Gm + (int64_t)jq * n;
   R a = ci[ip], b = ci[jp], c = cj[ip], dd = cj[jp];
-  g_block_store(Gm, n, ip, jp, iq, jq, pp[p], pp[q], a, b, c, dd);
+  g_block_store(Gm, n, ip, jp, iq, jq, S, np, p, q, a, b, c, dd);
 }
 
 // U/V of the chunk that ends at global step k (blockIdx.y: 0 = U, 1 = V;
@@ -359,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, const P
 // brought up to date at their own last chunk.
 template <class R>
 __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *V,
-                                                          const Piv<R> *par, int k,
+                                                          const R *par, int k,
                                                           int tile_elems) {
   extern __shared__ __align__(16) unsigned char smem[];
   R *T = reinterpret_cast<R *>(smem);
@@ -375,7 +444,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   R *M = (blockIdx.y ? V : U) + d.off[m];
   tile_load(T, M, n, r0, nr);
   __syncthreads();
-  tile_rotate(T, n, nr, k0, k1, par + kChunk * d.poff[m], blockIdx.y != 0);
+  tile_rotate(T, n, nr, k0, k1, par + kChunk * d.poff[m] * kPivComp, blockIdx.y != 0);
   __syncthreads();
   tile_store(T, M, n, r0, nr);
 }
@@ -410,28 +479,28 @@ __global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, const R *G, R *
 // workspace.
 
 template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int maxn) {
-  size_t b = kRed * sizeof(double) + (size_t)(maxn / 2) * sizeof(Piv<R>) + (size_t)maxn * 2;
+  size_t b = kRed * sizeof(double) + (size_t)(maxn / 2) * kPivComp * sizeof(R) + (size_t)maxn * 2;
   return (b + 15) & ~(size_t)15;
 }
 
 template <class R, int BS>
 __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t *mats, R *G,
-                                                      R *U, R *V, Piv<R> *par, R *sigma,
+                                                      R *U, R *V, R *par, R *sigma,
                                                       int32_t *sweeps_out, int max_sweeps,
                                                       double tolf, int accumulate, int maxn,
                                                       int tile_elems) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *red = reinterpret_cast<double *>(smem);
-  Piv<R> *spar = reinterpret_cast<Piv<R> *>(smem + kRed * sizeof(double));
-  int16_t *spair =
-      reinterpret_cast<int16_t *>(smem + kRed * sizeof(double) + (maxn / 2) * sizeof(Piv<R>));
+  R *spar = reinterpret_cast<R *>(smem + kRed * sizeof(double));
+  int16_t *spair = reinterpret_cast<int16_t *>(smem + kRed * sizeof(double) +
+                                               (size_t)(maxn / 2) * kPivComp * sizeof(R));
   R *T = reinterpret_cast<R *>(smem + persistent_fixed_lds<R>(maxn));
   int m = mats[blockIdx.x];
   int n = d.n[m];
   int np = n >> 1;
   int64_t o = d.off[m];
   R *Gm = G + o, *Um = U + o, *Vm = V + o;
-  Piv<R> *tab = par + kChunk * d.poff[m];
+  R *tab = par + kChunk * d.poff[m] * kPivComp;
   int rows = min(n, tile_elems / (n + 1));
   double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red);
   __syncthreads();
@@ -439,18 +508,20 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   bool conv = false;
   for (; sw < max_sweeps && !conv; ++sw) {
     for (int k = 0; k < n - 1; ++k) {
-      Piv<R> *slot = tab + (k % kChunk) * np;
+      R *slot = tab + (size_t)(k % kChunk) * kPivComp * np;
       for (int q = threadIdx.x; q < np; q += BS) {
         int i, j;
         rr_pair(n, k, q, i, j);
         spair[2 * q] = (int16_t)i;
         spair[2 * q + 1] = (int16_t)j;
         Piv<R> P = pivot_svd(Gm, n, i, j);
-        spar[q] = P;
-        slot[q] = P;
+        piv_store(spar, np, q, P);
+        piv_store(slot, np, q, P);
       }
       __syncthreads();
-      g_step_block<R, BS>(Gm, n, spar, spair);
+      // 1024 lanes keep 16 waves per CU in flight: two blocks each suffice and
+      // stay within the 128 registers that size allows
+      g_step_block<R, BS, (BS >= 1024 ? 2 : 4)>(Gm, n, spar, spair);
       __syncthreads();
       if (k % kChunk == kChunk - 1 || k == n - 2) {
         int k0 = chunk_begin(k);
@@ -458,11 +529,11 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
           R *M = side ? Vm : Um;
           for (int r0 = 0; r0 < n; r0 += rows) {
             int nr = min(rows, n - r0);
-            tile_load(T, M, n, r0, nr);
+            tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
             tile_rotate(T, n, nr, k0, k, tab, side != 0);
             __syncthreads();
-            tile_store(T, M, n, r0, nr);
+            tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
           }
         }
@@ -593,7 +664,7 @@ template <class R, int BS> static void set_lds_attr(size_t lds) {
 
 template <class R>
 static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int count, int maxn,
-                             int block, R *G, R *U, R *V, Piv<R> *par, R *sigma,
+                             int block, R *G, R *U, R *V, R *par, R *sigma,
                              int32_t *sweeps_out, int max_sweeps, double tolf, int accumulate,
                              size_t lds_limit, hipStream_t st) {
   int tile_elems = 0;
@@ -706,7 +777,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.done = reinterpret_cast<int32_t *>(wsb + L.done);
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
-  Piv<R> *par = reinterpret_cast<Piv<R> *>(wsb + L.par);
+  R *par = reinterpret_cast<R *>(wsb + L.par);
   if (mode == 0) {
     int16_t *pairs = reinterpret_cast<int16_t *>(wsb + L.pairs);
     hipLaunchKernelGGL(k_sw_init<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, U, V,
@@ -766,6 +837,13 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     a = bb;
   }
   size_t lds_limit = device_lds_limit();
+  // one launch over all matrices, longest first, when the buckets agree on the
+  // workgroup size: the dispatcher then starts each next matrix as soon as a
+  // CU frees up, with no drain between buckets
+  bool same_block = std::all_of(segs.begin(), segs.end(),
+                                [&](const Seg &x) { return x.block == segs[0].block; });
+  if (same_block && segs.size() > 1)
+    segs = {Seg{0, (int)nmat, n_host[order[0]], segs[0].block}};
   auto launch_all = [&]() -> int {
     for (const Seg &s : segs) {
       int rc = launch_persistent<R>(d, order_dev + s.begin, s.count, s.maxn, s.block, G, U, V,
