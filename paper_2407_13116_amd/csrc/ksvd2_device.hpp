@@ -111,14 +111,13 @@ __device__ inline bool even_sig(float y) { return (__float_as_uint(y) & 1u) == 0
 
 // ---------------------------------------------------------------------------
 // Correctly rounded hypot, binary64.
-//   hi >= lo > 0; once the exponent gap exceeds 30 the result is hi.
-//   Both subnormal: the result lies on the 2^-1074 grid; integer rounding of
-//   sqrt(H^2 + L^2) with an exact sign test (no ties are possible there).
-//   Otherwise scale hi into [1,2) (exact), form S = A^2 + B^2 as a double-word,
-//   y = RN(sqrt(RN(S))) is within one ulp of the answer; the residual
-//   t = S - y^2 (error < 2^-99) is compared with the squared rounding midpoints
-//   around y; only when t is within 2^-98 of one does an exact expansion sign
-//   test decide (this includes exact ties, e.g. Pythagorean midpoints).
+//   hi >= lo > 0.  Both subnormal: the result lies on the 2^-1074 grid;
+//   integer rounding of sqrt(H^2 + L^2) with an exact sign test (no ties are
+//   possible there).  Otherwise scale hi into [1,2) (exact), form S = A^2 + B^2
+//   as a double-word, take a candidate root y and prove it correctly rounded
+//   from its residual S - y^2 (sqrt_dw_cr below); only next to a rounding
+//   midpoint does an exact expansion sign test decide (this includes exact
+//   ties, e.g. Pythagorean midpoints).
 // ---------------------------------------------------------------------------
 __device__ __attribute__((noinline)) double hypot_tiny(double hi, double lo) {
   double H = ldexp(hi, 1074), L = ldexp(lo, 1074);  // integers < 2^52, exact
@@ -156,12 +155,14 @@ __device__ __attribute__((noinline)) double hypot_resolve(double p, double pe, d
 
 // sqrt(S), S = sh + sl a double-word in [1, 8), correctly rounded to binary64.
 // A reciprocal square root estimate and one Goldschmidt step give g ~ sqrt(S)
-// (within about an ulp) and h ~ 1/(2 sqrt S); the residual t = S - g^2 is formed
-// exactly to 2^-99 (sh - g^2 is exact by Sterbenz), the first-order correction
-// c = t h gives the candidate y = RN(g + c) and w ~ sqrt(S) - y with an error
-// below 2^-92.  y is the answer unless w lies within 2^-88 of a rounding
-// midpoint of y; then the exact expansion sign test settles it (p, pe, q, qe
-// are the exact parts of S).
+// and h ~ 1/(2 sqrt S); one Newton step on the double-word S gives the
+// candidate y, within far less than an ulp of sqrt(S) except next to a
+// rounding midpoint.  Its residual rho = S - y^2 (sh - y^2 by one fma, then
+// + sl) is within 2^-100 y^2 of the exact one, and sqrt(S) - y = rho /
+// (sqrt(S) + y).  So |rho| < y ulp(y) (1 - 2^-40) proves |sqrt(S) - y| <
+// ulp(y)/2, i.e. y is the correctly rounded root (below y = 2 the gap is half
+// as wide, so that side is left to the fallback).  Otherwise the exact
+// expansion sign test settles it (p, pe, q, qe are the exact parts of S).
 __device__ __attribute__((always_inline)) inline double sqrt_dw_cr(double sh, double sl,
                                                                     double p, double pe,
                                                                     double q, double qe) {
@@ -171,19 +172,16 @@ __device__ __attribute__((always_inline)) inline double sqrt_dw_cr(double sh, do
   double e = fma(-h, g, 0.5);
   g = fma(g, e, g);
   h = fma(h, e, h);
-  double d = fma(-g, g, s);
-  g = fma(d, h, g);
-  double gg, gge;
-  two_prod(g, g, gg, gge);
-  double t = ((sh - gg) - gge) + sl;
-  double c = t * h;
-  double y = g + c;
-  double w = (g - y) + c;
-  double hg = (y >= 2.0) ? 0x1p-52 : 0x1p-53;  // half an ulp of y (y in [1, 4))
-  const double M = 0x1p-88;
-  bool pow2 = (y == 1.0) || (y == 2.0);         // the gap below y is half as wide
-  bool ok = (fabs(w) < hg - M) && !(pow2 && w < -(0.5 * hg - M));
+  double d = fma(-g, g, sh) + sl;
+  double y = fma(d, h, g);
+  double rho = fma(-y, y, sh) + sl;
+  constexpr double c1 = 0x1p-52 * (1.0 - 0x1p-40), c2 = 0x1p-51 * (1.0 - 0x1p-40);
+  bool big = y >= 2.0;
+  double thr = y * (big ? c2 : c1);
+  bool ok = fabs(rho) < thr && !(y == 2.0 && rho < 0.0);
   if (ok) return y;
+  double hg = big ? 0x1p-52 : 0x1p-53;          // half an ulp of y (y in [1, 4))
+  bool pow2 = (y == 1.0) || (y == 2.0);         // the gap below y is half as wide
   return hypot_resolve(p, pe, q, qe, y, 2.0 * hg, pow2 ? hg : 2.0 * hg);
 }
 
@@ -192,6 +190,9 @@ __device__ __attribute__((always_inline)) inline double hypot_cr(double x, doubl
   double hi = fmax(a, b), lo = fmin(a, b);
   if (lo == 0.0 || isinf(hi)) return hi;
   int eh = ilog2(hi), el = ilog2(lo);
+  // beyond an exponent gap of 30, lo^2 < 2^-60 hi^2 cannot move the rounding
+  // of hi (the general path would return hi as well; on wide-range data whole
+  // waves skip it here)
   if (eh - el > 30) return hi;
   if (eh < -1022) return hypot_tiny(hi, lo);
   double A = ldexp(hi, -eh), B = ldexp(lo, -eh);  // A in [1,2), B >= 2^-31: exact
@@ -204,10 +205,9 @@ __device__ __attribute__((always_inline)) inline double hypot_cr(double x, doubl
 }
 
 // hypot(t, 1) for 0 <= t <= 1 (the secants of angles up to pi/4): the larger
-// argument is exactly 1, so no scaling is needed.
+// argument is exactly 1, so no scaling is needed; below 2^-30 the result is 1.
 __device__ __attribute__((always_inline)) inline double hypot1_le1(double t) {
-  int et = ilog2(t);
-  if (t == 0.0 || et < -30) return 1.0;
+  if (t < 0x1p-30) return 1.0;
   double q, qe;
   two_prod(t, t, q, qe);
   double sh = 1.0 + q;

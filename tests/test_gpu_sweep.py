@@ -2,7 +2,8 @@
 
 * With a fixed number of sweeps (stopping test off): G, U, V and sigma bit for bit equal
   to the oracle's sweep, for every execution mode (plain per-step launches, persistent,
-  hipGraph), on an uneven batch (orders 2 .. 66, both precisions).
+  hipGraph), on an uneven batch (orders 2 .. 66, both precisions), and on orders 130 ..
+  520 whose deferred U/V update spans several LDS row tiles and pivot passes.
 * Converged runs: the three modes bitwise identical to each other; sigma against LAPACK,
   orthogonality of U and V, reconstruction, the off-diagonal stopping test.
 * The uniform-size workload at full size (256 matrices of order 256, FP64) in the
@@ -20,6 +21,7 @@ from paper_2407_13116_amd import inputs
 
 pytestmark = pytest.mark.gpu
 MODES = ["plain", "persistent", "graph"]
+_LARGE_REF = {}
 
 
 def _mats(rng, ns, dtype, emax=3):
@@ -60,6 +62,26 @@ def test_fixed_sweeps_bitwise_vs_oracle(orc, dtype, mode):
         assert _same(got["U"][k], U), (mode, k, ns[k], "U")
         assert _same(got["V"][k], V), (mode, k, ns[k], "V")
         assert _same(got["sigma"][k], np.diag(G)), (mode, k, "sigma")
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_larger_orders_bitwise_vs_oracle(orc, dtype, mode):
+    """Orders whose U/V update spans several row tiles and several pivots per lane
+    (n/2 not a multiple of 64, n/2 > 128, n/2 > 256), one full sweep plus the first
+    chunk of the next."""
+    ns = [130, 150, 300, 520]
+    mats = _mats(np.random.default_rng(31), ns, dtype)
+    key = np.dtype(dtype).name
+    if key not in _LARGE_REF:  # the oracle's result, shared by the three modes
+        _LARGE_REF[key] = [orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0) for G0 in mats]
+    p, got = _run(mats, dtype, mode, max_sweeps=2, tolf=-1.0)
+    assert list(got["sweeps"]) == [-2] * len(ns)
+    for k in range(len(ns)):
+        G, U, V, st, swp = _LARGE_REF[key][k]
+        assert _same(got["G"][k], G), (mode, ns[k], "G")
+        assert _same(got["U"][k], U), (mode, ns[k], "U")
+        assert _same(got["V"][k], V), (mode, ns[k], "V")
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
