@@ -29,12 +29,14 @@ template <> struct Lim<double> {
   __device__ static double mu() { return 0x1p-1022; }
   __device__ static double nu() { return 0x1.fffffffffffffp+1023; }
   __device__ static double eps() { return 0x1p-53; }
+  __device__ static double eps_normal_from() { return 0x1p-960; }  // b eps normal above
 };
 template <> struct Lim<float> {
   static constexpr int p = 24, e_mu = -126, e_nu = 127;
   __device__ static float mu() { return 0x1p-126f; }
   __device__ static float nu() { return 0x1.fffffep+127f; }
   __device__ static float eps() { return 0x1p-24f; }
+  __device__ static float eps_normal_from() { return 0x1p-100f; }
 };
 
 // floor(lg|x|) for finite x != 0 (also for subnormal x).
@@ -445,10 +447,22 @@ __device__ __attribute__((always_inline)) inline double ext_w(double x1, double 
   // DWDivFP3 by the mantissa of d
   int ed = ilog2(d);
   double dm = ldexp(d, -ed);
-  double qh = xh / dm;
+  // both quotients by dm in [1, 2) share one refined reciprocal while their
+  // numerators are zero or at least 2^-960 (see the division section)
+  double yd = rcp_refined(dm);
+  double qh;
+  if (fabs(xh) >= 0x1p-960)
+    qh = div_with(xh, dm, yd);
+  else
+    qh = xh / dm;
   double ph, pl;
   two_prod(qh, dm, ph, pl);
-  double dl = ((xh - ph) + (xl - pl)) / dm;
+  double r2 = (xh - ph) + (xl - pl);
+  double dl;
+  if (r2 == 0.0 || fabs(r2) >= 0x1p-960)
+    dl = div_with(r2, dm, yd);
+  else
+    dl = r2 / dm;
   double zh, zl;
   fast_two_sum(qh, dl, zh, zl);
   return scale2(zh, K - 2 - ed);  // K counts the two factors of 2 of the frexp form
@@ -600,6 +614,17 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R
   return r;
 }
 
+// fl(a / b) < eps for a >= 0, b > 0, without the division.  eps is a power of
+// two, so the quotient rounds below eps iff it lies below the midpoint
+// eps (1 - 2^-(p+1)) (a tie rounds up to the even eps), and since the float
+// next below b eps is at least b eps 2^-p away, that holds iff a < b eps
+// exactly.  fma(-b, eps, a) rounds a - b eps once, keeping its sign whenever
+// b eps is normal (a non-zero difference is then at least 2^-1074 in size).
+template <class R> __device__ inline bool ratio_below_eps(R a, R b) {
+  if (b >= Lim<R>::eps_normal_from()) return fma(-b, Lim<R>::eps(), a) < (R)0;
+  return a / b < Lim<R>::eps();
+}
+
 // The SVD of R~ = [a b; 0 d], a >= d > 0, b > 0 (Sect. 3.3.1).
 template <class R> struct Tri {
   R cphi, sphi, tphi, cpsi, spsi, tpsi;
@@ -622,7 +647,7 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
   if (!simple) {
     if (b == d) {  // eq. t2f'''
       ef_case = true;
-    } else if (a / b < Lim<R>::eps()) {
+    } else if (ratio_below_eps(a, b)) {
       simple = true;  // eq. t2f''
     } else {
       R h = hypot_cr(a, b);
