@@ -8,6 +8,7 @@
 // every plane.
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
 #include <string>
 
 #include "abi_common.hpp"
@@ -47,30 +48,76 @@ __global__ __launch_bounds__(kBlock) void k_fwd_soa(int64_t n, const R *__restri
   if (s2) s2[i] = scale2(r.f2, r.e2);
 }
 
+// [B,2,2] blocks (4 consecutive values) and [B,2] pairs, moved as 16-byte
+// (binary32 pairs: 8-byte) vectors when every pointer of the launch is
+// aligned for it (kVec), else value by value.
+template <class R, bool kVec>
+__device__ inline void ld4(const R *p, R &a, R &b, R &c, R &d) {
+  if constexpr (kVec && sizeof(R) == 8) {
+    double2 x = reinterpret_cast<const double2 *>(p)[0], y = reinterpret_cast<const double2 *>(p)[1];
+    a = x.x; b = x.y; c = y.x; d = y.y;
+  } else if constexpr (kVec) {
+    float4 x = *reinterpret_cast<const float4 *>(p);
+    a = x.x; b = x.y; c = x.z; d = x.w;
+  } else {
+    a = p[0]; b = p[1]; c = p[2]; d = p[3];
+  }
+}
+template <class R, bool kVec> __device__ inline void st4(R *p, R a, R b, R c, R d) {
+  if constexpr (kVec && sizeof(R) == 8) {
+    reinterpret_cast<double2 *>(p)[0] = double2{a, b};
+    reinterpret_cast<double2 *>(p)[1] = double2{c, d};
+  } else if constexpr (kVec) {
+    *reinterpret_cast<float4 *>(p) = float4{a, b, c, d};
+  } else {
+    p[0] = a; p[1] = b; p[2] = c; p[3] = d;
+  }
+}
+template <class R, bool kVec> __device__ inline void ld2(const R *p, R &a, R &b) {
+  if constexpr (kVec && sizeof(R) == 8) {
+    double2 x = *reinterpret_cast<const double2 *>(p);
+    a = x.x; b = x.y;
+  } else if constexpr (kVec) {
+    float2 x = *reinterpret_cast<const float2 *>(p);
+    a = x.x; b = x.y;
+  } else {
+    a = p[0]; b = p[1];
+  }
+}
+template <class R, bool kVec> __device__ inline void st2(R *p, R a, R b) {
+  if constexpr (kVec && sizeof(R) == 8) {
+    *reinterpret_cast<double2 *>(p) = double2{a, b};
+  } else if constexpr (kVec) {
+    *reinterpret_cast<float2 *>(p) = float2{a, b};
+  } else {
+    p[0] = a; p[1] = b;
+  }
+}
+
+// whether every non-null pointer is aligned for the vector forms above
+static bool vec_aligned(size_t w, std::initializer_list<const void *> ps) {
+  for (const void *p : ps)
+    if (p && (reinterpret_cast<uintptr_t>(p) % 16 != 0)) return false;
+  (void)w;
+  return true;
+}
+
 // Autograd layout: G, U, V are [B,2,2] row-major, S is [B,2] (plain sigma).
-template <class R>
+template <class R, bool kVec>
 __global__ __launch_bounds__(kBlock) void k_fwd_full(int64_t n, const R *__restrict__ G,
                                                      R *__restrict__ U, R *__restrict__ S,
                                                      R *__restrict__ V,
                                                      int32_t *__restrict__ info) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const R *g = G + 4 * i;
-  Svd2<R> r = svd2<R>(g[0], g[2], g[1], g[3]);
+  R g11, g12, g21, g22;
+  ld4<R, kVec>(G + 4 * i, g11, g12, g21, g22);
+  Svd2<R> r = svd2<R>(g11, g21, g12, g22);
   R du = (r.info & I_DETU) ? (R)-1 : (R)1;
   R dv = (r.info & I_DETV) ? (R)-1 : (R)1;
-  R *u = U + 4 * i;
-  u[0] = r.cu;
-  u[1] = -du * r.su;
-  u[2] = r.su;
-  u[3] = du * r.cu;
-  R *v = V + 4 * i;
-  v[0] = r.cv;
-  v[1] = -dv * r.sv;
-  v[2] = r.sv;
-  v[3] = dv * r.cv;
-  S[2 * i] = scale2(r.f1, r.e1);
-  S[2 * i + 1] = scale2(r.f2, r.e2);
+  st4<R, kVec>(U + 4 * i, r.cu, -du * r.su, r.su, du * r.cu);
+  st4<R, kVec>(V + 4 * i, r.cv, -dv * r.sv, r.sv, dv * r.cv);
+  st2<R, kVec>(S + 2 * i, scale2(r.f1, r.e1), scale2(r.f2, r.e2));
   if (info) info[i] = (int32_t)r.info;
 }
 
@@ -81,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_full(int64_t n, const R *__restr
 //   dG = U M V^T.
 // 1/(s1-s2): with tau > 0 replaced by (s1-s2)/((s1-s2)^2 + (tau s1)^2);
 // with tau = 0 taken as 0 when s1 == s2; 1/(s1+s2) taken as 0 when s1+s2 == 0.
-template <class R>
+template <class R, bool kVec>
 __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__ U,
                                                 const R *__restrict__ S,
                                                 const R *__restrict__ V,
@@ -91,20 +138,21 @@ __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__
                                                 R tau) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const R *u = U + 4 * i;
-  const R *v = V + 4 * i;
-  R u11 = u[0], u12 = u[1], u21 = u[2], u22 = u[3];
-  R v11 = v[0], v12 = v[1], v21 = v[2], v22 = v[3];
-  R s1 = S[2 * i], s2 = S[2 * i + 1];
+  R u11, u12, u21, u22, v11, v12, v21, v22, s1, s2;
+  ld4<R, kVec>(U + 4 * i, u11, u12, u21, u22);
+  ld4<R, kVec>(V + 4 * i, v11, v12, v21, v22);
+  ld2<R, kVec>(S + 2 * i, s1, s2);
   R a = 0, b = 0;
   if (dU) {
-    const R *w = dU + 4 * i;
+    R w11, w12, w21, w22;
+    ld4<R, kVec>(dU + 4 * i, w11, w12, w21, w22);
     // (U^T dU)_12 = u11 w12 + u21 w22 ; (U^T dU)_21 = u12 w11 + u22 w21
-    a = fma(u11, w[1], u21 * w[3]) - fma(u12, w[0], u22 * w[2]);
+    a = fma(u11, w12, u21 * w22) - fma(u12, w11, u22 * w21);
   }
   if (dV) {
-    const R *w = dV + 4 * i;
-    b = fma(v11, w[1], v21 * w[3]) - fma(v12, w[0], v22 * w[2]);
+    R w11, w12, w21, w22;
+    ld4<R, kVec>(dV + 4 * i, w11, w12, w21, w22);
+    b = fma(v11, w12, v21 * w22) - fma(v12, w11, v22 * w21);
   }
   R p = (R)0.5 * (a + b), q = (R)0.5 * (a - b);
   R dm = s1 - s2, sm = s1 + s2;
@@ -117,17 +165,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__
     idm = (dm != (R)0) ? (R)1 / dm : (R)0;
   }
   R ism = (sm != (R)0) ? (R)1 / sm : (R)0;
-  R m11 = dS ? dS[2 * i] : (R)0, m22 = dS ? dS[2 * i + 1] : (R)0;
+  R m11 = 0, m22 = 0;
+  if (dS) ld2<R, kVec>(dS + 2 * i, m11, m22);
   R pd = p * idm, qs = q * ism;
   R m12 = qs - pd, m21 = -pd - qs;
   // T = U M, then dG = T V^T
   R t11 = fma(u11, m11, u12 * m21), t12 = fma(u11, m12, u12 * m22);
   R t21 = fma(u21, m11, u22 * m21), t22 = fma(u21, m12, u22 * m22);
-  R *g = dG + 4 * i;
-  g[0] = fma(t11, v11, t12 * v12);
-  g[1] = fma(t11, v21, t12 * v22);
-  g[2] = fma(t21, v11, t22 * v12);
-  g[3] = fma(t21, v21, t22 * v22);
+  st4<R, kVec>(dG + 4 * i, fma(t11, v11, t12 * v12), fma(t11, v21, t12 * v22),
+               fma(t21, v11, t22 * v12), fma(t21, v21, t22 * v22));
 }
 
 template <class R>
@@ -161,8 +207,12 @@ static int fwd_full(int64_t n, const R *G, R *U, R *S, R *V, int32_t *info, void
   const size_t w = sizeof(R);
   KSVD2_REQ(G, w); KSVD2_REQ(U, w); KSVD2_REQ(S, w); KSVD2_REQ(V, w);
   KSVD2_OPT(info, 4);
-  hipLaunchKernelGGL(k_fwd_full<R>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
-                     G, U, S, V, info);
+  if (vec_aligned(w, {G, U, S, V}))
+    hipLaunchKernelGGL((k_fwd_full<R, true>), dim3(grid_for(n)), dim3(kBlock), 0,
+                       (hipStream_t)stream, n, G, U, S, V, info);
+  else
+    hipLaunchKernelGGL((k_fwd_full<R, false>), dim3(grid_for(n)), dim3(kBlock), 0,
+                       (hipStream_t)stream, n, G, U, S, V, info);
   return launch_status("ksvd2 forward (full layout) launch");
 }
 
@@ -175,9 +225,14 @@ static int bwd(int64_t n, const void *U, const void *S, const void *V, const voi
   const size_t w = sizeof(R);
   KSVD2_REQ(U, w); KSVD2_REQ(S, w); KSVD2_REQ(V, w); KSVD2_REQ(dG, w);
   KSVD2_OPT(dS, w); KSVD2_OPT(dU, w); KSVD2_OPT(dV, w);
-  hipLaunchKernelGGL(k_bwd<R>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
-                     (const R *)U, (const R *)S, (const R *)V, (const R *)dS, (const R *)dU,
-                     (const R *)dV, (R *)dG, (R)tau);
+  if (vec_aligned(w, {U, S, V, dS, dU, dV, dG}))
+    hipLaunchKernelGGL((k_bwd<R, true>), dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream,
+                       n, (const R *)U, (const R *)S, (const R *)V, (const R *)dS, (const R *)dU,
+                       (const R *)dV, (R *)dG, (R)tau);
+  else
+    hipLaunchKernelGGL((k_bwd<R, false>), dim3(grid_for(n)), dim3(kBlock), 0,
+                       (hipStream_t)stream, n, (const R *)U, (const R *)S, (const R *)V,
+                       (const R *)dS, (const R *)dU, (const R *)dV, (R *)dG, (R)tau);
   return launch_status("ksvd2 backward launch");
 }
 

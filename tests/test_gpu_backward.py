@@ -9,7 +9,8 @@
   gauge-invariant loss for FP32 vs FP64 differences to 1e-3), near-degenerate matrices
   (the polar-factor loss, differences through a 300-bit SVD; FP32 uses tau = 2^-12),
   rank-deficient matrices (first singular triple);
-* the full 2^22 batch in both precisions: finite, and sampled outputs vs the oracle.
+* the full 2^22 batch in both precisions: finite, and sampled outputs vs the oracle;
+* the kernels' 16-byte vector paths and their element-wise paths give the same bits.
 """
 import numpy as np
 import pytest
@@ -70,6 +71,37 @@ def test_backward_kernel_vs_oracle(orc, dtype):
     want2 = orc.svd2_backward(U, S, V, dS)
     assert np.all(np.abs(dG2 - want2).reshape(len(G), -1).max(1)
                   <= _bound(U, S, V, dS, 0 * dU, 0 * dV, dtype))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_vector_and_element_paths_agree(dtype):
+    """Tensors on 16-byte boundaries take the kernels' vector loads and stores; a view
+    one element off such a boundary takes the element-wise path: same bits."""
+    import torch
+
+    from paper_2407_13116_amd import api
+
+    G, dS, dU, dV, _ = inputs.diff_batch(dtype, B=1 << 12)
+    tdt = torch.float64 if np.dtype(dtype) == np.float64 else torch.float32
+
+    def shifted(x):
+        x = torch.as_tensor(x).to("cuda")
+        flat = torch.empty(x.numel() + 1, dtype=tdt, device="cuda")
+        v = flat[1:].view(x.shape)
+        v.copy_(x)
+        assert v.data_ptr() % 16 != 0
+        return v
+
+    t = to_dev(G, dS, dU, dV)
+    U, S, V = api.svd2x2_raw(t[0])
+    U2, S2, V2 = api.svd2x2_raw(shifted(G))
+    for a, b in ((U, U2), (S, S2), (V, V2)):
+        assert torch.equal(a, b)
+    dG = api.svd2x2_backward(U, S, V, t[1], t[2], t[3])
+    dG2 = api.svd2x2_backward(shifted(U), shifted(S), shifted(V), shifted(t[1]), shifted(t[2]),
+                              shifted(t[3]))
+    torch.cuda.synchronize()
+    assert torch.equal(dG, dG2)
 
 
 def _fd_gpu(G64, loss, h_rel=1e-6):
