@@ -182,6 +182,14 @@ def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=6
                      "eff_GBs": bytes_ / times[-1] / 1e9,
                      "matrices_per_s": len(mats) / times[-1]}
         log(f"[bench] sweep {mode}: {res[mode]}")
+    # the sigma gradient dG = U diag(dsigma) V^T of the last solve: 2 n^3 flops per matrix
+    ds = torch.from_numpy(np.random.default_rng(17).standard_normal(int(p.n.sum())).astype(dtype)).cuda()
+    fl = float(np.sum(2.0 * p.n.astype(np.float64) ** 3))
+    ms_w, ms_ev = timed_loop(lambda: sw.sigma_grad(p, out["U"], out["V"], ds, workspace=ws), 10, 2)
+    res["sigma_grad"] = {"ms": ms_ev, "TFLOPs": fl / (ms_ev * 1e-3) / 1e12,
+                         "frac_fp64_vector_peak": fl / (ms_ev * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS
+                         if dtype == np.float64 else None}
+    log(f"[bench] sigma_grad: {res['sigma_grad']}")
     del p, G0
     torch.cuda.empty_cache()
     return res

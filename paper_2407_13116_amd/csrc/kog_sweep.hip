@@ -549,43 +549,105 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
 // ------------------------------------------------------------ sigma gradient
 //
 // dG = U diag(dsigma) V^T per matrix (d sigma_i / dG = u_i v_i^T, summed with
-// weights dsigma_i): a 32x32 output tile per 256-lane workgroup, k-panels of
-// 32 staged through LDS, each lane accumulating 4 outputs of one column.
+// weights dsigma_i): a dense contraction over k, run on the matrix cores.  A
+// 64 x 64 output tile per 256-lane workgroup, 32 x 32 per wave as 2 x 2 MFMA
+// blocks of 16 x 16 x 4: per step of four k, each lane supplies one element
+// of A = U diag(dsigma) (row l mod 16, column k0 + l / 16) and of B = V^T (row
+// k0 + l / 16, column l mod 16) per block, i.e. 16 consecutive rows of a
+// column of U or V per quarter wave.  Out-of-range rows, columns and k read a
+// clamped element and contribute zero.  Result element (i, j) of a block sits
+// in lane j + 16 (i mod 4), register i / 4 for binary64 and in lane
+// j + 16 (i / 4), register i mod 4 for binary32 (as the instructions lay
+// them out on gfx950).
 
+template <class R> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// the operands of one step of four k: A = U diag(dsigma) at rows ra, rb and
+// B = V^T at columns ca, cb, zero outside the matrix
+template <class R> struct SgOps {
+  R a0, a1, b0, b1;
+};
 template <class R>
-__global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, const R *U, const R *V,
-                                                    const R *ds, R *dG) {
-  __shared__ R su[32][33];  // U tile: rows r0.., columns k0..
-  __shared__ R sv[32][33];  // V tile scaled by ds: rows c0.., columns k0..
-  int m = blockIdx.z;
+__device__ inline SgOps<R> sg_load(const R *Um, const R *Vm, const R *dsm, int n, int k,
+                                   int ra, int rb, int ca, int cb, bool ia, bool ib, bool ja,
+                                   bool jb) {
+  bool kin = k < n;
+  int ks = kin ? k : n - 1;
+  const R *uk = Um + (int64_t)ks * n, *vk = Vm + (int64_t)ks * n;
+  R s = dsm[ks];
+  R u0 = uk[ra], u1 = uk[rb], v0 = vk[ca], v1 = vk[cb];
+  SgOps<R> o;
+  o.a0 = (kin && ia) ? u0 * s : (R)0;
+  o.a1 = (kin && ib) ? u1 * s : (R)0;
+  o.b0 = (kin && ja) ? v0 : (R)0;
+  o.b1 = (kin && jb) ? v1 : (R)0;
+  return o;
+}
+
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so the
+// 1-D grid is read as b = x + 8 j (x = b mod 8 the XCD): XCD x takes matrices
+// x, x + 8, ..., tile after tile, and the tiles of one matrix, which share
+// its U and V panels, meet in one L2.  tpm = tiles per matrix of the largest.
+template <class R>
+__global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, int64_t nmat, int tpm,
+                                                    const R *U, const R *V, const R *ds, R *dG) {
+  typedef typename Mfma<R>::v4 v4;
+  int64_t b = blockIdx.x, j = b >> 3;
+  int64_t m = (b & 7) + 8 * (j / tpm);
+  if (m >= nmat) return;
+  int t = (int)(j % tpm);
   int n = d.n[m];
-  int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
-  if (r0 >= n || c0 >= n) return;
+  int tiles = (n + 63) / 64;
+  if (t >= tiles * tiles) return;
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int r0 = (t % tiles) * 64 + (w & 1) * 32, c0 = (t / tiles) * 64 + (w >> 1) * 32;
+  if (r0 >= n || c0 >= n) return;  // the whole wave is outside the matrix
   int64_t o = d.off[m];
   const R *Um = U + o, *Vm = V + o, *dsm = ds + d.soff[m];
-  int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty in 0..7
-  R acc[4] = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < n; k0 += 32) {
-    for (int t = threadIdx.x; t < 32 * 32; t += 256) {
-      int rr = t & 31, kk = t >> 5;
-      int r = r0 + rr, c = c0 + rr, k = k0 + kk;
-      su[rr][kk] = (r < n && k < n) ? Um[r + (int64_t)k * n] : (R)0;
-      sv[rr][kk] = (c < n && k < n) ? Vm[c + (int64_t)k * n] * dsm[k] : (R)0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      R u = su[tx][kk];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) acc[a] = fma(u, sv[ty + 8 * a][kk], acc[a]);
-    }
-    __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  int ra = r0 + li, rb = r0 + 16 + li, ca = c0 + li, cb = c0 + 16 + li;
+  bool ia = ra < n, ib = rb < n, ja = ca < n, jb = cb < n;
+  ra = ia ? ra : n - 1;
+  rb = ib ? rb : n - 1;
+  ca = ja ? ca : n - 1;
+  cb = jb ? cb : n - 1;
+  v4 acc00 = v4{0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  // software pipeline: the operands of step k0 + 4 are loaded before the
+  // matrix instructions of step k0 are issued
+  SgOps<R> cur = sg_load(Um, Vm, dsm, n, lk, ra, rb, ca, cb, ia, ib, ja, jb);
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    SgOps<R> nxt = sg_load(Um, Vm, dsm, n, k0 + 4 + lk, ra, rb, ca, cb, ia, ib, ja, jb);
+    acc00 = Mfma<R>::mma(cur.a0, cur.b0, acc00);
+    acc01 = Mfma<R>::mma(cur.a0, cur.b1, acc01);
+    acc10 = Mfma<R>::mma(cur.a1, cur.b0, acc10);
+    acc11 = Mfma<R>::mma(cur.a1, cur.b1, acc11);
+    cur = nxt;
   }
   R *out = dG + o;
-  for (int a = 0; a < 4; ++a) {
-    int r = r0 + tx, c = c0 + ty + 8 * a;
-    if (r < n && c < n) out[r + (int64_t)c * n] = acc[a];
-  }
+  const v4 *accs[2][2] = {{&acc00, &acc01}, {&acc10, &acc11}};
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = r0 + 16 * x + Mfma<R>::row(lane, v), c = c0 + 16 * y + li;
+        if (r < n && c < n) out[r + (int64_t)c * n] = (*accs[x][y])[v];
+      }
 }
 
 // ----------------------------------------------------------------- host side
@@ -922,9 +984,10 @@ static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *o
   d.n = reinterpret_cast<const int32_t *>(wsb + o_n);
   d.off = reinterpret_cast<const int64_t *>(wsb + o_off);
   d.soff = reinterpret_cast<const int64_t *>(wsb + o_soff);
-  unsigned t = (unsigned)((maxn + 31) / 32);
-  hipLaunchKernelGGL(k_sigma_grad<R>, dim3(t, t, (unsigned)nmat), dim3(256), 0, st, d, U, V, ds,
-                     dG);
+  int t = (maxn + 63) / 64;
+  int64_t groups = (nmat + 7) / 8;
+  hipLaunchKernelGGL(k_sigma_grad<R>, dim3((unsigned)(8 * groups * t * t)), dim3(256), 0, st, d,
+                     nmat, t * t, U, V, ds, dG);
   return launch_status("kog_sigma_grad launch");
 }
 

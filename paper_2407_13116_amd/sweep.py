@@ -101,12 +101,15 @@ def _side_stream(device):
     return _SIDE[key]
 
 
-def sigma_grad(packed: Packed, U, V, dsigma):
-    """dG = U diag(dsigma) V^T per matrix (the gradient of sum dsigma_i sigma_i)."""
+def sigma_grad(packed: Packed, U, V, dsigma, workspace=None):
+    """dG = U diag(dsigma) V^T per matrix (the gradient of sum dsigma_i sigma_i).
+    `workspace` may be the one kog_sweep_batch returned (it is large enough)."""
     L = _lib.lib()
     dG = torch.empty_like(U)
     need = workspace_bytes(U.dtype, packed.n)
-    ws = torch.empty(need + 256, dtype=torch.uint8, device=U.device)
+    ws = workspace
+    if ws is None or ws.numel() < need + 256:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=U.device)
     pad = (-ws.data_ptr()) % 256
     n = np.ascontiguousarray(packed.n)
     off = np.ascontiguousarray(packed.off)
