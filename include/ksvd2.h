@@ -161,7 +161,10 @@ int ksvd2_hypot_batch(int dtype, int64_t n, const void *x, const void *y, void *
  * mode: 0 = plain per-step launches (the host polls convergence once per sweep,
  *           so the call returns after the work is done);
  *       1 = persistent kernels (one workgroup per matrix, one launch per order
- *           bucket), asynchronous;
+ *           bucket), asynchronous; a workgroup keeps the step's parameters in
+ *           LDS, which bounds the order (on MI355X, with 160 KB per workgroup:
+ *           n <= 3,200 in binary64, n <= 6,200 in binary32); larger orders
+ *           return KSVD2_EINVAL naming mode 0, which takes every order;
  *       2 = mode 1 captured into a hipGraph on first use and replayed on later
  *           calls with identical arguments (needs a non-null stream).
  * All modes perform the same arithmetic in the same order: bitwise identical.

@@ -848,8 +848,16 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     if (rc) return rc;
     int maxnp = maxn / 2;
     int64_t maxblocks = (int64_t)maxnp * maxnp;
-    // U/V tiles of the mode-0 kernel: rows of the smallest order set the count
-    const int apply_elems = (int)(kApplyLds / sizeof(R));
+    // U/V tiles of the mode-0 kernel: 64 KB, or as much LDS as a workgroup may
+    // take when one row of the largest order needs more; the rows of the
+    // smallest order set the tile count
+    size_t apply_lds = std::max(kApplyLds, (size_t)(maxn + 1) * sizeof(R));
+    if (apply_lds > kApplyLds) {
+      apply_lds = device_lds_limit();
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sw_apply<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_lds);
+    }
+    const int apply_elems = (int)(apply_lds / sizeof(R));
     int minrows = maxn;
     for (int64_t m = 0; m < nmat; ++m)
       minrows = std::min(minrows, std::min(n_host[m], apply_elems / (n_host[m] + 1)));
@@ -865,7 +873,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
                            dim3(kBlock), 0, st, d, G, par, pairs, k);
         if (k % kChunk == kChunk - 1 || k == maxn - 2)
           hipLaunchKernelGGL(k_sw_apply<R>, dim3(apply_tiles, 2, (unsigned)nmat),
-                             dim3(kApplyBlock), kApplyLds, st, d, U, V, par, k, apply_elems);
+                             dim3(kApplyBlock), apply_lds, st, d, U, V, par, k, apply_elems);
       }
       hipLaunchKernelGGL(k_sw_check<R>, dim3((unsigned)nmat), dim3(kRed), 0, st, d, G, tolf);
       rc = launch_status("kog_sweep step");

@@ -226,3 +226,53 @@ def test_resume_and_edges(orc, mode):
     sig = p3.unpack_sigma(o3["sigma"])
     assert sorted(sig[3]) == [0.5, 1.0, 2.0, 3.0]
     assert np.all(sig[4] == 0)
+
+
+def test_persistent_order_limit_names_mode0():
+    """Orders whose step parameters do not fit a workgroup's LDS are refused by the
+    persistent modes with a message naming mode 0 (nothing is launched)."""
+    from paper_2407_13116_amd import KSVD2Error
+    from paper_2407_13116_amd import sweep as sw
+
+    n = 3400
+    p = sw.Packed([np.asfortranarray(np.eye(n))])
+    with pytest.raises(KSVD2Error, match="mode 0"):
+        sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="persistent")
+
+
+def test_mode0_largest_order_one_sweep():
+    """Order 8192 (the largest accepted; one row of its U/V tile exceeds 64 KB of LDS in
+    binary64): one plain-mode sweep keeps U, V orthogonal and U^T G0 V equal to the
+    iterated G, both to a few n eps, and lowers the off-diagonal norm (checked on the
+    device)."""
+    import torch
+
+    from paper_2407_13116_amd import sweep as sw
+
+    n = 8192
+    g = torch.Generator(device="cuda").manual_seed(8192)
+    G0 = torch.randn((n, n), dtype=torch.float64, device="cuda", generator=g)
+    p = sw.Packed.__new__(sw.Packed)
+    p.n = np.array([n], dtype=np.int32)
+    p.off = np.array([0], dtype=np.int64)
+    p.soff = np.array([0], dtype=np.int64)
+    p.G = G0.t().contiguous().reshape(-1).clone()   # column-major G0
+    p.dtype = p.G.dtype
+    out = sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="plain")
+    torch.cuda.synchronize()
+    assert int(out["sweeps"][0]) == -1
+    U = out["U"].reshape(n, n).t()                  # column-major -> matrix view
+    V = out["V"].reshape(n, n).t()
+    G = out["G"].reshape(n, n).t()
+    eps = 2.0 ** -53
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    assert float(torch.linalg.norm(U.t().contiguous() @ U.contiguous() - eye)) <= 10 * n * eps
+    assert float(torch.linalg.norm(V.t().contiguous() @ V.contiguous() - eye)) <= 10 * n * eps
+    R = U.t().contiguous() @ G0 @ V.contiguous()
+    assert float(torch.linalg.norm(R - G)) <= 10 * n * eps * float(torch.linalg.norm(G0))
+    # one sweep of a large Gaussian matrix lowers the off-diagonal norm (to about
+    # 0.76 of it here; the first sweeps of the two-sided method move slowly)
+    off0 = float(torch.linalg.norm(G0 - torch.diag(torch.diagonal(G0))))
+    off = float(torch.linalg.norm(G - torch.diag(torch.diagonal(G))))
+    assert off < 0.9 * off0
+
