@@ -21,8 +21,11 @@ std::string &last_error_ref() {
   return s;
 }
 
+// 6 waves per SIMD (at most 80 registers): the straight-line SVD code issues
+// back-to-back dependent FP64 instructions, and one more resident wave hides
+// more of their latency than the few registers given up cost (measured)
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_fwd_soa(int64_t n, const R *__restrict__ g11,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_soa(int64_t n, const R *__restrict__ g11,
                                                     const R *__restrict__ g21,
                                                     const R *__restrict__ g12,
                                                     const R *__restrict__ g22, R *__restrict__ cu,
@@ -104,7 +107,7 @@ static bool vec_aligned(size_t w, std::initializer_list<const void *> ps) {
 
 // Autograd layout: G, U, V are [B,2,2] row-major, S is [B,2] (plain sigma).
 template <class R, bool kVec>
-__global__ __launch_bounds__(kBlock) void k_fwd_full(int64_t n, const R *__restrict__ G,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_full(int64_t n, const R *__restrict__ G,
                                                      R *__restrict__ U, R *__restrict__ S,
                                                      R *__restrict__ V,
                                                      int32_t *__restrict__ info) {
