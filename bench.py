@@ -170,7 +170,7 @@ def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=6
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode=mode,
-                                     workspace=ws)
+                                     workspace=ws, sort=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             ws = out["workspace"]

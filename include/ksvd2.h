@@ -178,6 +178,22 @@ int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_
                     int32_t max_sweeps, double tol_factor, int accumulate, int mode,
                     void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * kog_sweep_sort -- the delivered singular values in the usual order: for each
+ * matrix of a kog_sweep_batch result, sigma (packed as kog_sweep_batch writes
+ * it, on entry the iterate's diagonal) is put in descending order, equal values
+ * keeping their index order, and the columns of U and V are permuted the same
+ * way, all in place, so that G_0 = U diag(sigma) V^T with sigma_1 >= sigma_2 >=
+ * ... >= 0.  The paper takes sigma_i as the diagonal of the final iterate (Sect.
+ * 1, eq. SVD) without ordering them; this is the ordering convention on top.
+ * G is not touched, so an iteration resumed with `accumulate` needs the U and V
+ * from before this call.  Layouts and workspace as for kog_sweep_batch; orders
+ * up to 8192 (an order's values, ranks and one row of U must fit a workgroup's
+ * LDS).  Status codes as above.
+ */
+int kog_sweep_sort(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                   void *U, void *V, void *sigma, void *workspace, size_t ws_bytes, void *stream);
+
 /* Bytes of workspace kog_sweep_batch and kog_sigma_grad need for this batch
    (0 for invalid arguments). */
 size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);

@@ -49,6 +49,8 @@ def lib():
             L.kog_sweep_workspace_size.argtypes = [i32, i64, p]
             L.kog_sigma_grad.restype = i32
             L.kog_sigma_grad.argtypes = [i32, i64, p, p, p, p, p, p, p, ctypes.c_size_t, p]
+            L.kog_sweep_sort.restype = i32
+            L.kog_sweep_sort.argtypes = [i32, i64, p, p, p, p, p, p, ctypes.c_size_t, p]
             L.kog_sweep_tune.restype = i32
             L.kog_sweep_tune.argtypes = [i32, i32, i32]
         _lib = L

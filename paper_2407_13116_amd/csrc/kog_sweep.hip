@@ -650,6 +650,57 @@ __global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, int64_t nmat, i
       }
 }
 
+// ------------------------------------------------------- sorted convention
+//
+// sigma of matrix m in descending order (equal values keep their index order)
+// with the columns of U and V permuted to match, so that G0 = U diag(sigma) V^T
+// holds with sigma_1 >= sigma_2 >= ...  One workgroup per matrix: the rank of
+// every value is counted in LDS (stable, so the ranks are a permutation), then
+// U and V are rewritten a tile of whole rows at a time (a row's columns move
+// within the tile, so the permutation is in place).
+
+template <class R>
+__global__ __launch_bounds__(kRed) void k_sw_sort(SweepDesc d, R *U, R *V, R *sigma,
+                                                 int tile_elems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int m = blockIdx.x;
+  int n = d.n[m];
+  R *sv = reinterpret_cast<R *>(smem);
+  int *rk = reinterpret_cast<int *>(smem + (size_t)n * sizeof(R));
+  size_t fixed = ((size_t)n * (sizeof(R) + sizeof(int)) + 15) & ~(size_t)15;
+  R *T = reinterpret_cast<R *>(smem + fixed);
+  R *sg = sigma + d.soff[m];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sv[i] = sg[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    R x = sv[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      R y = sv[j];
+      r += (y > x) || (y == x && j < i);
+    }
+    rk[i] = r;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sg[rk[i]] = sv[i];
+  const int ldt = n + 1;
+  int rows = min(n, (tile_elems - (int)(fixed / sizeof(R))) / ldt);
+  for (int side = 0; side < 2; ++side) {
+    R *M = (side ? V : U) + d.off[m];
+    for (int r0 = 0; r0 < n; r0 += rows) {
+      int nr = min(rows, n - r0);
+      tile_load(T, M, n, r0, nr);
+      __syncthreads();
+      // column c of the tile goes to column rank(c)
+      for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
+        int r = e % nr, c = e / nr;
+        M[r0 + r + (int64_t)rk[c] * n] = T[r * ldt + c];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ----------------------------------------------------------------- host side
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -999,6 +1050,57 @@ static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *o
   return launch_status("kog_sigma_grad launch");
 }
 
+template <class R>
+static int sort_impl(int64_t nmat, const int32_t *n_host, const int64_t *off_host, R *U, R *V,
+                     R *sigma, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (nmat < 0) return fail(KSVD2_EINVAL, "nmat < 0");
+  if (nmat == 0) return KSVD2_OK;
+  if (!n_host || !off_host) return fail(KSVD2_EINVAL, "n_host and off_host are required");
+  if (nmat > 65535) return fail(KSVD2_EINVAL, "at most 65535 matrices per call");
+  const size_t w = sizeof(R);
+  KSVD2_REQ(U, w); KSVD2_REQ(V, w); KSVD2_REQ(sigma, w); KSVD2_REQ(ws, 256);
+  int maxn = 0;
+  int64_t stot = 0;
+  std::vector<int64_t> soff(nmat);
+  for (int64_t m = 0; m < nmat; ++m) {
+    int n = n_host[m];
+    if (n < 1 || n > kMaxOrder) return fail(KSVD2_EINVAL, "bad order %d", n);
+    if (off_host[m] < 0) return fail(KSVD2_EINVAL, "matrix %lld: negative offset", (long long)m);
+    soff[m] = stot;
+    stot += n;
+    maxn = std::max(maxn, n);
+  }
+  size_t need = align256(nmat * 4) + align256(nmat * 8) * 2;
+  if (ws_bytes < need)
+    return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  // LDS: the values and ranks of the largest order, plus at least one tile row
+  size_t fixed = ((size_t)maxn * (w + sizeof(int)) + 15) & ~(size_t)15;
+  size_t lds = std::max((size_t)64 * 1024, fixed + (size_t)(maxn + 1) * w);
+  if (lds > 64 * 1024) {
+    size_t lim = device_lds_limit();
+    if (lds > lim)
+      return fail(KSVD2_EINVAL, "order %d needs %zu bytes of LDS, %zu available", maxn, lds, lim);
+    lds = lim;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sw_sort<R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  std::vector<unsigned char> host(need, 0);
+  size_t o_n = 0, o_off = align256(nmat * 4), o_soff = o_off + align256(nmat * 8);
+  std::memcpy(host.data() + o_n, n_host, nmat * 4);
+  std::memcpy(host.data() + o_off, off_host, nmat * 8);
+  std::memcpy(host.data() + o_soff, soff.data(), nmat * 8);
+  unsigned char *wsb = static_cast<unsigned char *>(ws);
+  hipError_t e = hipMemcpyAsync(wsb, host.data(), need, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(KSVD2_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  SweepDesc d{};
+  d.n = reinterpret_cast<const int32_t *>(wsb + o_n);
+  d.off = reinterpret_cast<const int64_t *>(wsb + o_off);
+  d.soff = reinterpret_cast<const int64_t *>(wsb + o_soff);
+  hipLaunchKernelGGL(k_sw_sort<R>, dim3((unsigned)nmat), dim3(kRed), lds, st, d, U, V, sigma,
+                     (int)(lds / w));
+  return launch_status("kog_sweep_sort launch");
+}
+
 }  // namespace ksvd2
 
 using namespace ksvd2;
@@ -1050,6 +1152,18 @@ int kog_sigma_grad(int dtype, int64_t nmat, const int32_t *n_host, const int64_t
   if (dtype == 0)
     return sigma_grad_impl<float>(nmat, n_host, off_host, (const float *)U, (const float *)V,
                                   (const float *)dsigma, (float *)dG, workspace, ws_bytes, st);
+  return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+int kog_sweep_sort(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
+                   void *U, void *V, void *sigma, void *workspace, size_t ws_bytes, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == 1)
+    return sort_impl<double>(nmat, n_host, off_host, (double *)U, (double *)V, (double *)sigma,
+                             workspace, ws_bytes, st);
+  if (dtype == 0)
+    return sort_impl<float>(nmat, n_host, off_host, (float *)U, (float *)V, (float *)sigma,
+                            workspace, ws_bytes, st);
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
 }
 

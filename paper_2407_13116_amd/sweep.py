@@ -49,10 +49,13 @@ def workspace_bytes(dtype, n):
 
 
 def kog_sweep_batch(packed: Packed, max_sweeps: int = 30, tol_factor: float = 1.0,
-                    mode: str | int = "persistent", U=None, V=None, workspace=None):
+                    mode: str | int = "persistent", U=None, V=None, workspace=None,
+                    sort: bool = False):
     """Run the sweep in place on packed.G.  Returns dict(G, U, V, sigma, sweeps).
 
-    ``U``/``V`` given => accumulate (continue from them)."""
+    ``U``/``V`` given => accumulate (continue from them).  ``sort`` => sigma in
+    descending order with the columns of U and V permuted to match (kog_sweep_sort);
+    G stays the iterate, so resume only from unsorted U and V."""
     L = _lib.lib()
     mode = MODES.get(mode, mode)
     G = packed.G
@@ -84,6 +87,13 @@ def kog_sweep_batch(packed: Packed, max_sweeps: int = 30, tol_factor: float = 1.
                                float(tol_factor), int(acc), int(mode), wsp + pad,
                                workspace.numel() - pad, stream.cuda_stream or None)
     _lib.check(rc, "kog_sweep_batch")
+    if sort:
+        with torch.cuda.stream(stream):
+            rc = L.kog_sweep_sort(dt, len(n), n.ctypes.data_as(ctypes.c_void_p),
+                                  off.ctypes.data_as(ctypes.c_void_p), U.data_ptr(),
+                                  V.data_ptr(), sigma.data_ptr(), wsp + pad,
+                                  workspace.numel() - pad, stream.cuda_stream or None)
+        _lib.check(rc, "kog_sweep_sort")
     if side is not None:
         cur.wait_stream(side)
         for t in (G, U, V, sigma, sweeps, workspace):

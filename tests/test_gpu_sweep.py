@@ -276,3 +276,34 @@ def test_mode0_largest_order_one_sweep():
     off = float(torch.linalg.norm(G - torch.diag(torch.diagonal(G))))
     assert off < 0.9 * off0
 
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_sorted_convention(dtype, mode):
+    """sort=True: sigma descending (ties in index order), U and V columns permuted the
+    same way -- bit for bit the unsorted result permuted by a stable sort -- and
+    G0 = U diag(sigma) V^T."""
+    import torch
+
+    rng = np.random.default_rng(41)
+    ns = [2, 6, 34, 66, 130, 300]
+    mats = _mats(rng, ns, dtype)
+    mats.append(np.asfortranarray(np.diag([1.0, 3.0, 3.0, 2.0, 0.0, 3.0]).astype(dtype)))
+    ns.append(6)
+    _, ref = _run(mats, dtype, mode, max_sweeps=40, tolf=1.0)
+    from paper_2407_13116_amd import sweep as sw
+
+    p = sw.Packed(mats, dtype=dtype)
+    out = sw.kog_sweep_batch(p, max_sweeps=40, tol_factor=1.0, mode=mode, sort=True)
+    torch.cuda.synchronize()
+    sig, Us, Vs = p.unpack_sigma(out["sigma"]), p.unpack(out["U"]), p.unpack(out["V"])
+    eps = 2.0 ** (-53 if dtype == np.float64 else -24)
+    for k, G0 in enumerate(mats):
+        s0 = ref["sigma"][k]
+        perm = np.argsort(-s0, kind="stable")
+        assert _same(sig[k], s0[perm]), k
+        assert np.all(np.diff(sig[k].astype(np.float64)) <= 0), k
+        assert _same(Us[k], ref["U"][k][:, perm]) and _same(Vs[k], ref["V"][k][:, perm]), k
+        R = Us[k].astype(np.float64) @ np.diag(sig[k].astype(np.float64)) @ Vs[k].astype(np.float64).T
+        assert np.linalg.norm(R - G0) <= 50 * ns[k] * eps * max(np.linalg.norm(G0), 1e-300)
+
