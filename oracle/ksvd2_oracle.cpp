@@ -935,6 +935,10 @@ static int batch_fwd(int64_t n, const R *g11, const R *g21, const R *g12, const 
 /*    embedded U_k^T is applied to the pivot rows, then V_k to the pivot     */
 /*    columns; the pivot off-diagonals become 0 and its diagonal sigma; U_k  */
 /*    and V_k accumulate into U and V.  Matrices are column-major.           */
+/*    G is first scaled by a power of two so that the two-sided updates      */
+/*    cannot overflow (Sect. 4, on the order-n implementation; read as       */
+/*    2^s_G with s_G = e_nu - 2 - e_G - ceil(lg n), applied only when        */
+/*    negative) and scaled back at the end.                                   */
 /* ------------------------------------------------------------------------ */
 
 /* Round-robin (circle) ordering: position 0 is fixed, positions 1..n-1
@@ -957,9 +961,26 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
         V[i + (int64_t)j * n] = (i == j) ? (R)1 : (R)0;
       }
   }
-  /* ||G_0||_F in binary64 (the threshold of the stopping criterion) */
+  /* the global scaling: e_G the largest exponent of a non-zero entry */
+  int eg = INT_MIN;
+  for (int64_t k = 0; k < (int64_t)n * n; ++k)
+    if (G[k] != 0) eg = std::max(eg, std::ilogb(G[k]));
+  int lgn = 0;
+  while ((1 << lgn) < n) ++lgn;
+  int sg = (eg == INT_MIN) ? 0 : std::min(0, Fmt<R>::e_nu - 2 - eg - lgn);
+  if (sg < 0)
+    for (int64_t k = 0; k < (int64_t)n * n; ++k) G[k] = std::scalbn(G[k], sg);
+  /* ||G_0||_F in binary64 (the threshold of the stopping criterion), as the
+     norm of G 2^-t with t the largest exponent after the scaling, so that no
+     square overflows; the off-diagonal norm below is taken the same way (the
+     stopping test compares the two, so the factor cancels) */
+  int t = (eg == INT_MIN) ? 0 : eg + sg;
+  double ns = std::scalbn(1.0, -t);
   double fro2 = 0;
-  for (int64_t k = 0; k < (int64_t)n * n; ++k) fro2 += (double)G[k] * (double)G[k];
+  for (int64_t k = 0; k < (int64_t)n * n; ++k) {
+    double x = (double)G[k] * ns;
+    fro2 += x * x;
+  }
   double tol = tol_factor * n * (double)Fmt<R>::eps() * std::sqrt(fro2);
   int np = n / 2;
   R *pc = new R[4 * np]; /* per pivot: u11 u21 u12 u22 */
@@ -1041,7 +1062,10 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
     double off2 = 0;
     for (int c = 0; c < n; ++c)
       for (int r = 0; r < n; ++r)
-        if (r != c) off2 += (double)G[r + (int64_t)c * n] * (double)G[r + (int64_t)c * n];
+        if (r != c) {
+          double x = (double)G[r + (int64_t)c * n] * ns;
+          off2 += x * x;
+        }
     if (std::sqrt(off2) <= tol) {
       status = 0;
       ++sw;
@@ -1049,6 +1073,8 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
     }
   }
   *sweeps_done = sw;
+  if (sg < 0)
+    for (int64_t k = 0; k < (int64_t)n * n; ++k) G[k] = std::scalbn(G[k], -sg);
   delete[] pc;
   delete[] pv;
   delete[] pi;

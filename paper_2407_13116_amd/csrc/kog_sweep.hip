@@ -10,7 +10,11 @@
 //   3. the pivot block becomes diag(sigma_1, sigma_2) exactly;
 //   4. columns i, j of U and V are rotated by U_p and V_p.
 // A sweep is n - 1 steps; after each sweep the off-diagonal Frobenius norm
-// is compared with tol_factor * n * eps * ||G_0||_F.
+// is compared with tol_factor * n * eps * ||G_0||_F.  G is first scaled by
+// 2^s_G, s_G = e_nu - 2 - e_G - ceil(lg n) when that is negative (e_G the
+// largest exponent of an entry), so that the two-sided updates cannot
+// overflow (Sect. 4, on the order-n implementation), and scaled back at the
+// end.
 //
 // Only G feeds the next step's pivots, so step 4 is deferred: the rotations of
 // kChunk consecutive steps are kept in a table, and U and V are brought up to
@@ -30,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -56,6 +61,8 @@ struct SweepDesc {
   double *fro2;          // ||G_0||_F^2
   int32_t *sweeps;       // sweeps done so far
   int32_t *done;         // converged flag
+  int32_t *scale;        // s_G of matrix m (0: not scaled)
+  int32_t *nexp;         // t of matrix m: the norms are taken of G 2^-t
 };
 
 // Slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
@@ -310,8 +317,11 @@ __device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, b
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
 // diagonal ones): lane t < 256 sums rows t, t+256, ... of every column in
 // column order; then a fixed halving tree.  Every thread of the block calls it.
+// The entries are multiplied by sc = 2^-t (t the largest exponent of G_0
+// after the global scaling), so no square overflows; the stopping test
+// compares two such sums, so the factor cancels.
 template <class R>
-__device__ double block_sumsq(const R *G, int n, bool offdiag, double *red) {
+__device__ double block_sumsq(const R *G, int n, bool offdiag, double *red, double sc) {
   int t = threadIdx.x;
   if (t < kRed) {
     double acc = 0.0;
@@ -319,7 +329,7 @@ __device__ double block_sumsq(const R *G, int n, bool offdiag, double *red) {
       const R *col = G + (int64_t)c * n;
       for (int r = t; r < n; r += kRed) {
         if (offdiag && r == c) continue;
-        double x = (double)col[r];
+        double x = (double)col[r] * sc;
         acc = fma(x, x, acc);
       }
     }
@@ -335,8 +345,43 @@ __device__ double block_sumsq(const R *G, int n, bool offdiag, double *red) {
   return v;
 }
 
+// The largest exponent of a non-zero entry (INT_MIN for a zero matrix); every
+// thread of the block (a multiple of kRed lanes) calls it: the block folds into
+// kRed slots one group of kRed lanes at a time, then a halving tree.  This and
+// scale_matrix run once per matrix and stay out of line, so they do not add to
+// the persistent kernel's registers.
 template <class R>
-__device__ double init_matrix(const R *G, R *U, R *V, int n, bool accumulate, double *red) {
+__device__ __attribute__((noinline)) int max_exponent(const R *G, int n, double *red) {
+  int *ired = reinterpret_cast<int *>(red);
+  int64_t tot = (int64_t)n * n;
+  int eg = INT_MIN;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x)
+    if (G[e] != (R)0) eg = max(eg, ilog2(G[e]));
+  const int t = threadIdx.x, groups = blockDim.x / kRed;
+  for (int g = 0; g < groups; ++g) {
+    if (t / kRed == g) ired[t % kRed] = (g == 0) ? eg : max(ired[t % kRed], eg);
+    __syncthreads();
+  }
+  for (int st = kRed / 2; st > 0; st >>= 1) {
+    if (t < st) ired[t] = max(ired[t], ired[t + st]);
+    __syncthreads();
+  }
+  int emax = ired[0];
+  __syncthreads();
+  return emax;
+}
+
+template <class R> __device__ __attribute__((noinline)) void scale_matrix(R *G, int n, int s) {
+  int64_t tot = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) G[e] = scale2(G[e], s);
+}
+
+// identity U, V (unless continuing), the global scaling of G: s_G = e_nu - 2 -
+// e_G - ceil(lg n) when negative (returned in sg), the exponent t of the norm
+// factor (returned in nt), and ||G_0 2^-t||_F^2 of the scaled G
+template <class R>
+__device__ double init_matrix(R *G, R *U, R *V, int n, bool accumulate, double *red, int &sg,
+                              int &nt) {
   if (!accumulate) {
     int64_t tot = (int64_t)n * n;
     for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -346,7 +391,15 @@ __device__ double init_matrix(const R *G, R *U, R *V, int n, bool accumulate, do
       V[e] = v;
     }
   }
-  return block_sumsq(G, n, false, red);
+  int emax = __builtin_amdgcn_readfirstlane(max_exponent(G, n, red));  // uniform: scalar
+  int lgn = 32 - __clz(n - 1);                                          // ceil(lg n), n >= 2
+  sg = (emax == INT_MIN) ? 0 : min(0, Lim<R>::e_nu - 2 - emax - lgn);
+  nt = (emax == INT_MIN) ? 0 : emax + sg;
+  if (sg < 0) {
+    scale_matrix(G, n, sg);
+    __syncthreads();
+  }
+  return block_sumsq(G, n, false, red, ldexp(1.0, -nt));
 }
 
 __device__ inline bool converged(double off2, double fro2, int n, double tolf, double eps) {
@@ -355,9 +408,14 @@ __device__ inline bool converged(double off2, double fro2, int n, double tolf, d
   return off2 <= tol * tol * fro2;
 }
 
+// undo the global scaling, then the singular values off the diagonal
 template <class R>
-__device__ void finish_matrix(const R *G, int n, R *sig, int32_t *sweeps_out, int sweeps,
+__device__ void finish_matrix(R *G, int n, int sg, R *sig, int32_t *sweeps_out, int sweeps,
                               bool conv) {
+  if (sg < 0) {
+    scale_matrix(G, n, -sg);
+    __syncthreads();
+  }
   if (sig)
     for (int i = threadIdx.x; i < n; i += blockDim.x) sig[i] = G[i + (int64_t)i * n];
   if (threadIdx.x == 0 && sweeps_out) *sweeps_out = conv ? sweeps : -sweeps;
@@ -369,16 +427,19 @@ __device__ inline int chunk_begin(int k) { return k - k % kChunk; }
 // ----------------------------------------------------------- mode 0 kernels
 
 template <class R>
-__global__ __launch_bounds__(kRed) void k_sw_init(SweepDesc d, const R *G, R *U, R *V,
+__global__ __launch_bounds__(kRed) void k_sw_init(SweepDesc d, R *G, R *U, R *V,
                                                   int accumulate) {
   __shared__ double red[kRed];
   int m = blockIdx.x;
   int64_t o = d.off[m];
-  double f2 = init_matrix(G + o, U + o, V + o, d.n[m], accumulate != 0, red);
+  int sg, nt;
+  double f2 = init_matrix(G + o, U + o, V + o, d.n[m], accumulate != 0, red, sg, nt);
   if (threadIdx.x == 0) {
     d.fro2[m] = f2;
     d.sweeps[m] = 0;
     d.done[m] = 0;
+    d.scale[m] = sg;
+    d.nexp[m] = nt;
   }
 }
 
@@ -455,7 +516,7 @@ __global__ __launch_bounds__(kRed) void k_sw_check(SweepDesc d, const R *G, doub
   int m = blockIdx.x;
   if (d.done[m]) return;  // uniform over the block
   int n = d.n[m];
-  double off2 = block_sumsq(G + d.off[m], n, true, red);
+  double off2 = block_sumsq(G + d.off[m], n, true, red, ldexp(1.0, -d.nexp[m]));
   if (threadIdx.x == 0) {
     d.sweeps[m] += 1;
     if (converged(off2, d.fro2[m], n, tolf, (double)Lim<R>::eps())) d.done[m] = 1;
@@ -463,10 +524,10 @@ __global__ __launch_bounds__(kRed) void k_sw_check(SweepDesc d, const R *G, doub
 }
 
 template <class R>
-__global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, const R *G, R *sigma,
+__global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, R *G, R *sigma,
                                                     int32_t *sweeps_out) {
   int m = blockIdx.x;
-  finish_matrix(G + d.off[m], d.n[m], sigma ? sigma + d.soff[m] : nullptr,
+  finish_matrix(G + d.off[m], d.n[m], d.scale[m], sigma ? sigma + d.soff[m] : nullptr,
                 sweeps_out ? sweeps_out + m : nullptr, d.sweeps[m], d.done[m] != 0);
 }
 
@@ -502,7 +563,9 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   R *Gm = G + o, *Um = U + o, *Vm = V + o;
   R *tab = par + kChunk * d.poff[m] * kPivComp;
   int rows = min(n, tile_elems / (n + 1));
-  double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red);
+  int sg, nt;
+  double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red, sg, nt);
+  const double nsc = ldexp(1.0, -nt);
   __syncthreads();
   int sw = 0;
   bool conv = false;
@@ -539,11 +602,12 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
         }
       }
     }
-    double off2 = block_sumsq(Gm, n, true, red);
+    double off2 = block_sumsq(Gm, n, true, red, nsc);
     conv = converged(off2, fro2, n, tolf, (double)Lim<R>::eps());
   }
-  finish_matrix(Gm, n, sigma ? sigma + d.soff[m] : nullptr, sweeps_out ? sweeps_out + m : nullptr,
-                sw, conv);
+  __syncthreads();
+  finish_matrix(Gm, n, sg, sigma ? sigma + d.soff[m] : nullptr,
+                sweeps_out ? sweeps_out + m : nullptr, sw, conv);
 }
 
 // ------------------------------------------------------------ sigma gradient
@@ -706,7 +770,7 @@ __global__ __launch_bounds__(kRed) void k_sw_sort(SweepDesc d, R *U, R *V, R *si
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t n, off, soff, poff, order, fro2, sweeps, done, par, pairs, total;
+  size_t n, off, soff, poff, order, fro2, sweeps, done, scale, nexp, par, pairs, total;
 };
 
 static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
@@ -720,6 +784,8 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
   L.fro2 = p;   p = align256(p + nmat * 8);
   L.sweeps = p; p = align256(p + nmat * 4);
   L.done = p;   p = align256(p + nmat * 4);
+  L.scale = p;  p = align256(p + nmat * 4);
+  L.nexp = p;   p = align256(p + nmat * 4);
   L.par = p;    p = align256(p + (size_t)kChunk * npiv * 10 * w);
   L.pairs = p;  p = align256(p + (size_t)kChunk * npiv * 4);
   L.total = p;
@@ -888,6 +954,8 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.fro2 = reinterpret_cast<double *>(wsb + L.fro2);
   d.sweeps = reinterpret_cast<int32_t *>(wsb + L.sweeps);
   d.done = reinterpret_cast<int32_t *>(wsb + L.done);
+  d.scale = reinterpret_cast<int32_t *>(wsb + L.scale);
+  d.nexp = reinterpret_cast<int32_t *>(wsb + L.nexp);
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
   R *par = reinterpret_cast<R *>(wsb + L.par);

@@ -307,3 +307,24 @@ def test_sorted_convention(dtype, mode):
         R = Us[k].astype(np.float64) @ np.diag(sig[k].astype(np.float64)) @ Vs[k].astype(np.float64).T
         assert np.linalg.norm(R - G0) <= 50 * ns[k] * eps * max(np.linalg.norm(G0), 1e-300)
 
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_global_scaling_bitwise_vs_oracle(orc, dtype, mode):
+    """Matrices whose largest entries sit a few binades below the overflow threshold
+    (scaled by 2^s_G < 1 before the sweep and back after it), mixed with ordinary ones:
+    G, U, V bit for bit equal to the oracle after two fixed sweeps, all finite."""
+    e_nu = 1023 if np.dtype(dtype) == np.float64 else 127
+    rng = np.random.default_rng(77)
+    ns = [8, 34, 66, 130]
+    mats = _mats(rng, ns, dtype)
+    for k in (0, 2):
+        mats[k] = np.asfortranarray((mats[k].astype(np.float64) * 2.0 ** (e_nu - 6)).astype(dtype))
+    p, got = _run(mats, dtype, mode, max_sweeps=2, tolf=-1.0)
+    for k, G0 in enumerate(mats):
+        G, U, V, st, swp = orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0)
+        assert np.all(np.isfinite(got["G"][k])), (mode, ns[k])
+        assert _same(got["G"][k], G), (mode, ns[k], "G")
+        assert _same(got["U"][k], U), (mode, ns[k], "U")
+        assert _same(got["V"][k], V), (mode, ns[k], "V")
+

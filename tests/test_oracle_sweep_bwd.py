@@ -2,7 +2,8 @@
 
 Sweep: converged results are checked against LAPACK's singular values (numpy.linalg.svd,
 run as a library), the stopping test (off-diagonal norm <= n eps ||G||_F), orthogonality of
-U and V and the reconstruction G = U Sigma V^T.
+U and V and the reconstruction G = U Sigma V^T, also for entries near the overflow
+threshold (the global power-of-two scaling).
 
 Adjoint: central finite differences of the oracle's own forward map (an independent
 numerical derivative) on general, near-degenerate (gauge-invariant polar-factor loss) and
@@ -62,6 +63,31 @@ def test_sweep_graded_columns(orc):
     ref = np.linalg.svd(G0, compute_uv=False)
     sig = np.sort(np.abs(np.diag(G)))[::-1]
     assert np.max(np.abs(sig - ref) / ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sweep_global_scaling_near_overflow(orc, dtype):
+    """Entries within a few binades of the overflow threshold: the power-of-two scaling
+    (s_G = e_nu - 2 - e_G - ceil(lg n) < 0) lets the two-sided updates run without
+    overflow; the singular values match LAPACK on the scaled-down copy, scaled up, and
+    U diag(sigma) V^T reconstructs G_0."""
+    n, e_nu = 32, (1023 if np.dtype(dtype) == np.float64 else 127)
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((n, n))
+    k = e_nu - 5                       # largest entries near 2^(e_nu - 3): s_G < 0
+    G0 = np.asfortranarray((A * 2.0 ** k).astype(dtype))
+    G, U, V, st, sw = orc.kog_sweep(G0, max_sweeps=40, tol_factor=1.0)
+    assert st == 0 and np.all(np.isfinite(G)) and np.all(np.isfinite(U))
+    eps = _eps(dtype)
+    ref = np.linalg.svd(G0.astype(np.float64) * 2.0 ** -k, compute_uv=False)
+    sig = np.sort(np.abs(np.diag(G).astype(np.float64)))[::-1] * 2.0 ** -k
+    assert np.max(np.abs(sig - ref)) <= 20 * n * eps * ref[0]
+    R = (U.astype(np.float64) @ np.diag(np.diag(G).astype(np.float64) * 2.0 ** -k)
+         @ V.astype(np.float64).T)
+    assert np.linalg.norm(R - G0.astype(np.float64) * 2.0 ** -k) <= 20 * n * eps * np.linalg.norm(ref)
+    # no sweep: the scaling is undone exactly
+    G2, *_ = orc.kog_sweep(G0, max_sweeps=0, tol_factor=-1.0)
+    assert np.array_equal(G2, G0)
 
 
 # ------------------------------------------------------------------ adjoint
