@@ -51,15 +51,17 @@ def lib():
         L.orc_hypot_f64.argtypes = [d, d]
         L.orc_hypot_f32.restype = f
         L.orc_hypot_f32.argtypes = [f, f]
-        L.orc_hypot_batch_f64.argtypes = [i64, p, p, p]
-        L.orc_hypot_batch_f32.argtypes = [i64, p, p, p]
+        for name in ("orc_hypot_batch_f64", "orc_hypot_batch_f32", "orc_hypot_fast_batch_f64",
+                     "orc_hypot_fast_batch_f32"):
+            getattr(L, name).argtypes = [i64, p, p, p]
         L.orc_ef_op_f64.argtypes = [i32, d, d, ctypes.POINTER(i32), ctypes.POINTER(d)]
         L.orc_ef_op_f32.argtypes = [i32, f, f, ctypes.POINTER(i32), ctypes.POINTER(f)]
         L.orc_ext_f64.restype = d
         L.orc_ext_f64.argtypes = [d, d, d, d, i32, d]
         L.orc_ext_f32.restype = f
         L.orc_ext_f32.argtypes = [f, f, f, f, i32, f]
-        for name in ("orc_ksvd2_f64", "orc_ksvd2_f32"):
+        for name in ("orc_ksvd2_f64", "orc_ksvd2_f32", "orc_ksvd2_fast_f64",
+                     "orc_ksvd2_fast_f32"):
             fn = getattr(L, name)
             fn.restype = i32
             fn.argtypes = [i64] + [p] * 15 + [i32]
@@ -86,12 +88,14 @@ def _dt(dtype):
     raise TypeError(f"unsupported dtype {dtype}")
 
 
-def hypot(x, y):
-    """Correctly rounded hypot, elementwise (float64 or float32 arrays)."""
+def hypot(x, y, fast: bool = False):
+    """hypot, elementwise (float64 or float32 arrays): correctly rounded, or (``fast``)
+    the variant hi * sqrt(fma(r, r, 1)), r = lo / hi."""
     x = np.ascontiguousarray(x)
     y = np.ascontiguousarray(y, dtype=x.dtype)
     out = np.empty_like(x)
-    getattr(lib(), "orc_hypot_batch_" + _dt(x.dtype))(x.size, _ptr(x), _ptr(y), _ptr(out))
+    kind = "orc_hypot_fast_batch_" if fast else "orc_hypot_batch_"
+    getattr(lib(), kind + _dt(x.dtype))(x.size, _ptr(x), _ptr(y), _ptr(out))
     return out
 
 
@@ -132,8 +136,9 @@ def urv15(g11, g21, g12, g22, dtype=np.float64):
     return (*vals, bool(fl.value & 1), bool(fl.value & 2))
 
 
-def ksvd2(g11, g21, g12, g22, nthreads: int = 0, plain: bool = True):
-    """Batched 2x2 SVD, SoA planes in, dict of SoA planes out.
+def ksvd2(g11, g21, g12, g22, nthreads: int = 0, plain: bool = True, fast: bool = False):
+    """Batched 2x2 SVD, SoA planes in, dict of SoA planes out (``fast``: the variant
+    for a hypot that is not correctly rounded, Algorithm tf).
 
     Keys: cu su cv sv (U = [cu, -dU su; su, dU cu], likewise V, with dU/dV from the
     info bits 8/9), f1 f2 e1 e2 (sigma_i = f_i 2^e_i), info, and s1 s2 (sigma as
@@ -148,7 +153,7 @@ def ksvd2(g11, g21, g12, g22, nthreads: int = 0, plain: bool = True):
     if plain:
         out["s1"] = np.empty(n, dt)
         out["s2"] = np.empty(n, dt)
-    fn = getattr(lib(), "orc_ksvd2_" + _dt(dt))
+    fn = getattr(lib(), ("orc_ksvd2_fast_" if fast else "orc_ksvd2_") + _dt(dt))
     bad = fn(n, _ptr(g11), _ptr(g21), _ptr(g12), _ptr(g22), _ptr(out["cu"]), _ptr(out["su"]),
              _ptr(out["cv"]), _ptr(out["sv"]), _ptr(out["f1"]), _ptr(out["f2"]),
              _ptr(out["e1"]), _ptr(out["e2"]), _ptr(out["info"]),

@@ -219,6 +219,25 @@ static R cr_hypot(R x, R y) {
   }
 }
 
+/* 1b. The hypot of the variant for a hypot that is not correctly rounded
+   (Algorithm tf names that case without fixing the function; read here as the
+   textbook scaled form): with hi = max(|x|,|y|), lo = min(|x|,|y|),
+   hypot(x, y) = hi sqrt(1 + (lo/hi)^2), every operation rounded once and the
+   sum of 1 and the square taken by one fma; hi itself if hi is 0 or inf. */
+template <class R> static R fast_hypot(R x, R y) {
+  R hi = std::max(std::fabs(x), std::fabs(y));
+  R lo = std::min(std::fabs(x), std::fabs(y));
+  if (hi == 0 || std::isinf(hi)) return hi;
+  R r = lo / hi;
+  return hi * std::sqrt(std::fma(r, r, (R)1));
+}
+
+/* the hypot of the method: CR = true is the correctly rounded one the
+   analysis of Sect. 3 assumes, false the variant above */
+template <bool CR, class R> static R hyp(R x, R y) {
+  return CR ? cr_hypot(x, y) : fast_hypot(x, y);
+}
+
 /* ------------------------------------------------------------------------ */
 /* 2. (e,f) pairs (Sect. 2): w = 2^e f with 1 <= |f| < 2, zero is (0,0).     */
 /* ------------------------------------------------------------------------ */
@@ -515,8 +534,8 @@ template <class R> static Part<R> svd_z9(const M2<R> &G, int t) {
 
 /* Givens rotation by theta from tan(theta) (eq. Givens, Lemma sincostheta):
    sec = hypot(tan, 1), cos = fl(1/sec), sin = fl(tan/sec). */
-template <class R> static M2<R> givens(R tan_t) {
-  R sec = cr_hypot(tan_t, (R)1);
+template <bool CR, class R> static M2<R> givens(R tan_t) {
+  R sec = hyp<CR>(tan_t, (R)1);
   return m_rot((R)1 / sec, tan_t / sec);
 }
 
@@ -524,7 +543,7 @@ template <class R> static M2<R> givens(R tan_t) {
    t = 12 matrix (P_V), make the column positive by row signs (S_U), put the
    larger element on top (P_U), one QR rotation with tan = g21''/g11''
    (eq. theta); sigma1 = hypot, sigma2 = 0; U = S_U P_U U_theta, V = P_V. */
-template <class R> static Part<R> svd_z3(const M2<R> &G, int t) {
+template <bool CR, class R> static Part<R> svd_z3(const M2<R> &G, int t) {
   M2<R> PV = (t == 12) ? m_x<R>() : m_id<R>();
   M2<R> H = m_mul(G, PV);
   R a = H.a[0][0], b = H.a[1][0];
@@ -537,9 +556,9 @@ template <class R> static Part<R> svd_z3(const M2<R> &G, int t) {
     std::swap(a, b);
   }
   Part<R> r;
-  r.U = m_mul(m_mul(SU, PU), givens(b / a));
+  r.U = m_mul(m_mul(SU, PU), givens<CR>(b / a));
   r.V = PV;
-  r.s1 = ef_of(cr_hypot(a, b));
+  r.s1 = ef_of(hyp<CR>(a, b));
   r.s2 = ef_of((R)0);
   return r;
 }
@@ -547,7 +566,7 @@ template <class R> static Part<R> svd_z3(const M2<R> &G, int t) {
 /* Class t ~ 5 (Sect. 3.1): one non-zero row; the transposed analogue:
    P_U for t = 10, column signs S_V, column order P_V, one RQ rotation with
    tan = g12''/g11''; U = P_U, V = S_V P_V V_theta. */
-template <class R> static Part<R> svd_z5(const M2<R> &G, int t) {
+template <bool CR, class R> static Part<R> svd_z5(const M2<R> &G, int t) {
   M2<R> PU = (t == 10) ? m_x<R>() : m_id<R>();
   M2<R> H = m_mul(m_t(PU), G);
   R a = H.a[0][0], b = H.a[0][1];
@@ -561,8 +580,8 @@ template <class R> static Part<R> svd_z5(const M2<R> &G, int t) {
   }
   Part<R> r;
   r.U = PU;
-  r.V = m_mul(m_mul(SV, PV), givens(b / a));
-  r.s1 = ef_of(cr_hypot(a, b));
+  r.V = m_mul(m_mul(SV, PV), givens<CR>(b / a));
+  r.s1 = ef_of(hyp<CR>(a, b));
   r.s2 = ef_of((R)0);
   return r;
 }
@@ -576,7 +595,7 @@ template <class R> struct Tri {
   bool ovf;                    /* tan(psi) overflowed */
 };
 
-template <class R> static Tri<R> tri_svd(R a, R b, R d) {
+template <bool CR, class R> static Tri<R> tri_svd(R a, R b, R d) {
   const R eps = Fmt<R>::eps();
   const R inf = (R)INFINITY;
   Tri<R> o;
@@ -588,6 +607,21 @@ template <class R> static Tri<R> tri_svd(R a, R b, R d) {
     t2 = ef_fl(ef_div(ef_mul(ef_pow2(1, ef_of(b)), ef_of(d)), ef_mul(ef_of(a), ef_of(a))));
   } else if (a / b < eps) {
     t2 = ((R)2 * d) / b; /* eq. t2f'' */
+  } else if (!CR) {
+    /* hypot not correctly rounded: x and y are the smaller of a, b and d
+       divided by the larger of a, b, and tan(2 phi) = 2xy / (1 + (x-y)(x+y))
+       when a is the larger, 2y / (1 + (x-y)(x+y)) when b is; no square of an
+       input is formed, and a negative denominator is taken as 0 */
+    R x, y;
+    if (a > b) {
+      x = b / a;
+      y = d / a;
+      t2 = (((R)2 * x) * y) / std::max(std::fma(x - y, x + y, (R)1), (R)0);
+    } else {
+      x = a / b;
+      y = d / b;
+      t2 = ((R)2 * y) / std::max(std::fma(x - y, x + y, (R)1), (R)0);
+    }
   } else {
     R h = cr_hypot(a, b);
     if (h == d) {
@@ -598,8 +632,8 @@ template <class R> static Tri<R> tri_svd(R a, R b, R d) {
     }
   }
   /* tan(phi) by eq. tf, then sec, cos, sin */
-  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + cr_hypot(t2, (R)1));
-  R sec_phi = cr_hypot(tphi, (R)1);
+  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hyp<CR>(t2, (R)1));
+  R sec_phi = hyp<CR>(tphi, (R)1);
   o.tphi = tphi;
   o.sec_phi = sec_phi;
   o.cphi = (R)1 / sec_phi;
@@ -621,7 +655,7 @@ template <class R> static Tri<R> tri_svd(R a, R b, R d) {
     s2 = ef_mul(ef_of(d), cpsi);
   } else {
     o.ovf = false;
-    R sec_psi = cr_hypot(tpsi, (R)1);
+    R sec_psi = hyp<CR>(tpsi, (R)1);
     o.cpsi = (R)1 / sec_psi;
     o.spsi = tpsi / sec_psi;
     EF<R> sp = ef_div(ef_of(sec_phi), ef_of(sec_psi));
@@ -646,10 +680,10 @@ template <class R> struct Urv15 {
   bool ext, exact;
 };
 
-template <class R> static Urv15<R> urv15(const M2<R> &Gp) {
+template <bool CR, class R> static Urv15<R> urv15(const M2<R> &Gp) {
   Urv15<R> q;
-  R w1 = cr_hypot(Gp.a[0][0], Gp.a[1][0]);
-  R w2 = cr_hypot(Gp.a[0][1], Gp.a[1][1]);
+  R w1 = hyp<CR>(Gp.a[0][0], Gp.a[1][0]);
+  R w2 = hyp<CR>(Gp.a[0][1], Gp.a[1][1]);
   q.PV = m_id<R>();
   if (w1 < w2) {
     q.PV = m_x<R>();
@@ -662,7 +696,7 @@ template <class R> static Urv15<R> urv15(const M2<R> &Gp) {
   M2<R> G3 = m_mul(m_t(q.PU), G2);
   R g11 = G3.a[0][0], g21 = G3.a[1][0], g12 = G3.a[0][1], g22 = G3.a[1][1];
   q.tan_t = g21 / g11;
-  q.sec_t = cr_hypot(q.tan_t, (R)1);
+  q.sec_t = hyp<CR>(q.tan_t, (R)1);
   q.r11 = w1;
   /* Theorem R: tan(theta) is exact iff g21 - tan g11 = 0; that residual of
      a correctly rounded quotient is representable, so fma yields it exactly */
@@ -705,7 +739,7 @@ template <class R> struct Res {
   uint32_t info;
 };
 
-template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
+template <class R, bool CR = true> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
   Res<R> res;
   M2<R> G = {{{g11, g12}, {g21, g22}}};
   int t = type_of(G);
@@ -743,10 +777,10 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
     part = svd_z9(Gp, t1);
     done = true;
   } else if (c1 == Z3) {
-    part = svd_z3(Gp, t1);
+    part = svd_z3<CR>(Gp, t1);
     done = true;
   } else if (c1 == Z5) {
-    part = svd_z5(Gp, t1);
+    part = svd_z5<CR>(Gp, t1);
     done = true;
   }
 
@@ -780,7 +814,7 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
     Uplus = m_mul(m_mul(PU, S11), S22);
     Vplus = m_mul(PV, S12);
   } else if (!done && c1 == Z15) {
-    Urv15<R> q = urv15(Gp);
+    Urv15<R> q = urv15<CR>(Gp);
     if (q.ext) info |= INFO_EXT;
     M2<R> PV = q.PV;
     S1 = q.S1;
@@ -795,8 +829,8 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
       info |= INFO_DEGEN;
       M2<R> Rpp = {{{r11, r12}, {(R)0, r22}}};
       int t2 = type_of(Rpp);
-      Part<R> sub = (cls_of(t2) == Z5) ? svd_z5(Rpp, t2) : svd_z9(Rpp, t2);
-      part.U = m_mul(m_mul(m_mul(S1, PU15), givens(tan_t)), sub.U);
+      Part<R> sub = (cls_of(t2) == Z5) ? svd_z5<CR>(Rpp, t2) : svd_z9(Rpp, t2);
+      part.U = m_mul(m_mul(m_mul(S1, PU15), givens<CR>(tan_t)), sub.U);
       part.V = m_mul(PV, sub.V);
       part.s1 = sub.s1;
       part.s2 = sub.s2;
@@ -816,7 +850,7 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
        R^T symmetrically with X (eq. RT), compute the SVD of R~ and assemble */
     bool swapped = r11 < r22;
     if (swapped) info |= INFO_RSWAP;
-    Tri<R> tr = swapped ? tri_svd(r22, r12, r11) : tri_svd(r11, r12, r22);
+    Tri<R> tr = swapped ? tri_svd<CR>(r22, r12, r11) : tri_svd<CR>(r11, r12, r22);
     if (tr.ovf) info |= INFO_TPSI_OVF;
     if (tr.psig) info |= INFO_PSIG;
     M2<R> S2 = swapped ? m_diag((R)1, (R)-1) : m_id<R>();
@@ -845,7 +879,7 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
       if (std::isinf(tbphi)) {
         /* tan(psi) underflowed to 0 in the swapped case: bphi = pi/2, and the
            merged angle is pi/2 + theta (S22 = I) or pi/2 - theta */
-        R sec_t = cr_hypot(tan_t, (R)1);
+        R sec_t = hyp<CR>(tan_t, (R)1);
         R ct = (R)1 / sec_t, st = tan_t / sec_t;
         ca = s22neg ? st : -st;
         sa = ct;
@@ -854,7 +888,7 @@ template <class R> static Res<R> ksvd2(R g11, R g21, R g12, R g22) {
         sa = sgn(num);
       } else {
         R ta = num / den;
-        R sec_a = cr_hypot(ta, (R)1);
+        R sec_a = hyp<CR>(ta, (R)1);
         R sd = sgn(den);
         ca = sd * ((R)1 / sec_a);
         sa = sd * (ta / sec_a);
@@ -892,7 +926,7 @@ template <class R> static bool compact(const M2<R> &U, R &c, R &s, bool &neg) {
   return ok;
 }
 
-template <class R>
+template <class R, bool CR = true>
 static int batch_fwd(int64_t n, const R *g11, const R *g21, const R *g12, const R *g22, R *cu,
                      R *su, R *cv, R *sv, R *f1, R *f2, int32_t *e1, int32_t *e2, int32_t *info,
                      R *s1, R *s2, int nthreads) {
@@ -902,7 +936,7 @@ static int batch_fwd(int64_t n, const R *g11, const R *g21, const R *g12, const 
 #pragma omp parallel for schedule(static) reduction(+ : bad)
 #endif
   for (int64_t i = 0; i < n; ++i) {
-    Res<R> r = ksvd2<R>(g11[i], g21[i], g12[i], g22[i]);
+    Res<R> r = ksvd2<R, CR>(g11[i], g21[i], g12[i], g22[i]);
     bool nu, nv;
     R c, s;
     bool okU = compact(r.U, c, s, nu);
@@ -1110,6 +1144,14 @@ void orc_hypot_batch_f32(int64_t n, const float *x, const float *y, float *out) 
   for (int64_t i = 0; i < n; ++i) out[i] = cr_hypot(x[i], y[i]);
 }
 
+void orc_hypot_fast_batch_f64(int64_t n, const double *x, const double *y, double *out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = fast_hypot(x[i], y[i]);
+}
+
+void orc_hypot_fast_batch_f32(int64_t n, const float *x, const float *y, float *out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = fast_hypot(x[i], y[i]);
+}
+
 /* (e,f) operations, exposed for their pins: op 0 = plus, 1 = minus,
    2 = mul, 3 = div (the last two on N(x), N(y)) */
 void orc_ef_op_f64(int op, double x, double y, int *e, double *f) {
@@ -1164,7 +1206,7 @@ float orc_ext_f32(float x1, float y1, float x2, float y2, int minus, float d) {
    checks): out = {r11, r12, r22, tan(theta)}, flags bit0 exact tan, bit1 EXT. */
 void orc_urv15_f64(double g11, double g21, double g12, double g22, double *out, int *flags) {
   M2<double> G = {{{g11, g12}, {g21, g22}}};
-  Urv15<double> q = urv15(G);
+  Urv15<double> q = urv15<true>(G);
   out[0] = q.r11;
   out[1] = q.r12;
   out[2] = q.r22;
@@ -1174,7 +1216,7 @@ void orc_urv15_f64(double g11, double g21, double g12, double g22, double *out, 
 
 void orc_urv15_f32(float g11, float g21, float g12, float g22, float *out, int *flags) {
   M2<float> G = {{{g11, g12}, {g21, g22}}};
-  Urv15<float> q = urv15(G);
+  Urv15<float> q = urv15<true>(G);
   out[0] = q.r11;
   out[1] = q.r12;
   out[2] = q.r22;
@@ -1198,6 +1240,23 @@ int orc_ksvd2_f32(int64_t n, const float *g11, const float *g21, const float *g1
                   int nthreads) {
   return batch_fwd<float>(n, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1, s2,
                           nthreads);
+}
+
+/* the variant for a hypot that is not correctly rounded (Algorithm tf) */
+int orc_ksvd2_fast_f64(int64_t n, const double *g11, const double *g21, const double *g12,
+                       const double *g22, double *cu, double *su, double *cv, double *sv,
+                       double *f1, double *f2, int32_t *e1, int32_t *e2, int32_t *info,
+                       double *s1, double *s2, int nthreads) {
+  return batch_fwd<double, false>(n, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
+                                  s1, s2, nthreads);
+}
+
+int orc_ksvd2_fast_f32(int64_t n, const float *g11, const float *g21, const float *g12,
+                       const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
+                       float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1, float *s2,
+                       int nthreads) {
+  return batch_fwd<float, false>(n, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
+                                 s1, s2, nthreads);
 }
 
 /* One n x n matrix (column-major, in place): returns 0 when converged,
