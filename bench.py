@@ -78,16 +78,17 @@ def timed_loop(fn, steps, warmup):
     return wall / steps * 1e3, ev0.elapsed_time(ev1) / steps
 
 
-def fwd_case(dtype, steps, warmup):
+def fwd_case(dtype, steps, warmup, fast=False):
     import torch
 
     from paper_2407_13116_amd import api, inputs
 
     g = inputs.forward_sweep(dtype)
     d = [torch.from_numpy(x).cuda() for x in g]
-    out = api.ksvd2_batch(*d, plain=False)
+    out = api.ksvd2_batch(*d, plain=False, fast=fast)
     torch.cuda.synchronize()
-    ms_wall, ms_ev = timed_loop(lambda: api.ksvd2_batch(*d, plain=False, out=out), steps, warmup)
+    ms_wall, ms_ev = timed_loop(lambda: api.ksvd2_batch(*d, plain=False, out=out, fast=fast),
+                                steps, warmup)
     B = g[0].size
     res = {"B": B, "ms_wall": ms_wall, "ms_kernel": ms_ev, "rate": B / (ms_wall * 1e-3)}
     res["GBs"] = B * BYTES_FWD[dtype] / (ms_ev * 1e-3) / 1e9
@@ -300,6 +301,14 @@ def main():
                             "GBs": f32["GBs"], "hbm_frac": f32["GBs"] / HBM_PEAK_GBS,
                             "alg_TFLOPs": 2.0 * ALG_VALU_SLOTS[np.float32] * f32["B"]
                             / (f32["ms_kernel"] * 1e-3) / 1e12}
+        fast_err = {}
+        for dt, name in ((np.float64, "fwd_fast_f64"), (np.float32, "fwd_fast_f32")):
+            log(f"[bench] {name}: the variant without a correctly rounded hypot, 2^24")
+            ff, gf, hf = fwd_case(dt, args.steps, args.warmup, fast=True)
+            extra[name] = {"rate": ff["rate"], "ms_per_launch": ff["ms_kernel"],
+                           "GBs": ff["GBs"], "hbm_frac": ff["GBs"] / HBM_PEAK_GBS}
+            fast_err[name] = sigma2_error_sample(gf, hf, dt)
+            del gf, hf
         for dt, name in ((np.float64, "fwdbwd_f64"), (np.float32, "fwdbwd_f32")):
             log(f"[bench] {name}, 2^22 matrices")
             fb = fwdbwd_case(dt, args.steps, args.warmup)
@@ -317,6 +326,8 @@ def main():
                                            "f32": sigma2_error_sample(g32, h32, np.float32),
                                            "unit": "eps (2^-53 / 2^-24)",
                                            "sample": "1,500 matrices per precision"}
+        extra["max_rel_err_sigma2_ulp_fast"] = dict(fast_err, unit="eps (2^-53 / 2^-24)",
+                                                    sample="1,500 matrices per precision")
     res["extra"] = extra
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")

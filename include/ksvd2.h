@@ -96,6 +96,25 @@ int ksvd2_batch_f32(int64_t batch, const float *g11, const float *g21, const flo
                     float *s2_plain, void *stream);
 
 /*
+ * ksvd2_batch_fast_f64 / ksvd2_batch_fast_f32 -- the variant of the method for
+ * a hypot that is not correctly rounded (Algorithm tf's branch for that case,
+ * Sect. 3.2): every hypot is hi * sqrt(1 + (lo/hi)^2) with each operation
+ * correctly rounded (a few ulps from the exact value; see ksvd2_hypot_fast_batch),
+ * and tan(2 phi) of the triangular factor is formed from the quotients of
+ * r12 (or r11) and r22 by the larger of r11, r12, without squaring.  The paper
+ * gives no relative error bound for this variant.  Arguments, layout, ownership,
+ * info words and errors as for ksvd2_batch_f64 / ksvd2_batch_f32.
+ */
+int ksvd2_batch_fast_f64(int64_t batch, const double *g11, const double *g21, const double *g12,
+                         const double *g22, double *cu, double *su, double *cv, double *sv,
+                         double *f1, double *f2, int32_t *e1, int32_t *e2, int32_t *info,
+                         double *s1_plain, double *s2_plain, void *stream);
+int ksvd2_batch_fast_f32(int64_t batch, const float *g11, const float *g21, const float *g12,
+                         const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
+                         float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1_plain,
+                         float *s2_plain, void *stream);
+
+/*
  * ksvd2_svd2x2 -- the same SVD in the layout of an autograd graph: G, U, V are
  * [batch,2,2] row-major arrays (element (i,j) of matrix k at 4k + 2i + j), S is
  * [batch,2] with the plain singular values (rounded once to the working
@@ -134,6 +153,16 @@ int ksvd2_batch_backward(int dtype, int64_t batch, const void *U, const void *S,
  */
 int ksvd2_hypot_batch(int dtype, int64_t n, const void *x, const void *y, void *out,
                       void *stream);
+
+/*
+ * ksvd2_hypot_fast_batch -- the hypot of the fast variant: with hi = max(|x|,
+ * |y|) and lo = min(|x|, |y|), fl(hi * fl(sqrt(fl(fma(r, r, 1))))) where r =
+ * fl(lo / hi); hi itself when hi is 0 or infinite.  Not correctly rounded (its
+ * error is a few ulps), and it may overflow when hi is within a few ulps of the
+ * largest finite value.  Arguments and errors as for ksvd2_hypot_batch.
+ */
+int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, void *out,
+                           void *stream);
 
 /*
  * kog_sweep_batch -- the two-sided Kogbetliantz iteration (Sect. 1, eq. SVD) on

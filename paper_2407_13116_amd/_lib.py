@@ -31,7 +31,8 @@ def lib():
         L.ksvd2_version.argtypes = []
         L.ksvd2_last_error.restype = ctypes.c_char_p
         L.ksvd2_last_error.argtypes = []
-        for name in ("ksvd2_batch_f64", "ksvd2_batch_f32"):
+        for name in ("ksvd2_batch_f64", "ksvd2_batch_f32", "ksvd2_batch_fast_f64",
+                     "ksvd2_batch_fast_f32"):
             fn = getattr(L, name)
             fn.restype = i32
             fn.argtypes = [i64] + [p] * 15 + [p]
@@ -39,8 +40,10 @@ def lib():
         L.ksvd2_svd2x2.argtypes = [i32, i64, p, p, p, p, p, p]
         L.ksvd2_batch_backward.restype = i32
         L.ksvd2_batch_backward.argtypes = [i32, i64, p, p, p, p, p, p, p, d, p]
-        L.ksvd2_hypot_batch.restype = i32
-        L.ksvd2_hypot_batch.argtypes = [i32, i64, p, p, p, p]
+        for name in ("ksvd2_hypot_batch", "ksvd2_hypot_fast_batch"):
+            fn = getattr(L, name)
+            fn.restype = i32
+            fn.argtypes = [i32, i64, p, p, p, p]
         if hasattr(L, "kog_sweep_batch"):
             L.kog_sweep_batch.restype = i32
             L.kog_sweep_batch.argtypes = [i32, i64, p, p, p, p, p, p, p, i32, d, i32, i32, p,

@@ -43,11 +43,14 @@ def _check_gpu(*ts):
     return dt
 
 
-def ksvd2_batch(g11, g21, g12, g22, plain: bool = True, out: dict | None = None):
+def ksvd2_batch(g11, g21, g12, g22, plain: bool = True, out: dict | None = None,
+                fast: bool = False):
     """The 2x2 SVD of a batch given as four planes (structure of arrays).
 
     Returns a dict of tensors: cu su cv sv f1 f2 (working precision), e1 e2 info
-    (int32), and s1 s2 (plain sigma) when ``plain``.  See include/ksvd2.h."""
+    (int32), and s1 s2 (plain sigma) when ``plain``.  ``fast`` selects the variant
+    for a hypot that is not correctly rounded (ksvd2_batch_fast_*).  See
+    include/ksvd2.h."""
     dt = _check_gpu(g11, g21, g12, g22)
     n = g11.numel()
     for g in (g21, g12, g22):
@@ -61,7 +64,11 @@ def ksvd2_batch(g11, g21, g12, g22, plain: bool = True, out: dict | None = None)
         if plain:
             out["s1"] = torch.empty(n, dtype=dt, device=dev)
             out["s2"] = torch.empty(n, dtype=dt, device=dev)
-    fn = _lib.lib().ksvd2_batch_f64 if dt == torch.float64 else _lib.lib().ksvd2_batch_f32
+    L = _lib.lib()
+    if fast:
+        fn = L.ksvd2_batch_fast_f64 if dt == torch.float64 else L.ksvd2_batch_fast_f32
+    else:
+        fn = L.ksvd2_batch_f64 if dt == torch.float64 else L.ksvd2_batch_f32
     rc = fn(n, _ptr(g11), _ptr(g21), _ptr(g12), _ptr(g22), _ptr(out["cu"]), _ptr(out["su"]),
             _ptr(out["cv"]), _ptr(out["sv"]), _ptr(out["f1"]), _ptr(out["f2"]), _ptr(out["e1"]),
             _ptr(out["e2"]), _ptr(out["info"]), _ptr(out.get("s1")), _ptr(out.get("s2")),
@@ -97,11 +104,13 @@ def svd2x2_backward(U, S, V, dS=None, dU=None, dV=None, tau: float = 0.0):
     return dG
 
 
-def hypot(x, y):
-    """Correctly rounded hypot on the device (elementwise)."""
+def hypot(x, y, fast: bool = False):
+    """hypot on the device (elementwise): correctly rounded, or the fast variant's."""
     dt = _check_gpu(x, y)
     out = torch.empty_like(x)
-    rc = _lib.lib().ksvd2_hypot_batch(_DT[dt], x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream())
+    L = _lib.lib()
+    fn = L.ksvd2_hypot_fast_batch if fast else L.ksvd2_hypot_batch
+    rc = fn(_DT[dt], x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream())
     _lib.check(rc, "ksvd2_hypot_batch")
     return out
 

@@ -336,6 +336,78 @@ __device__ inline void div_by_sec(float a1, float a2, float sec, float &q1, floa
 }
 
 // ---------------------------------------------------------------------------
+// A hypot that is not correctly rounded, for the fast variant of the method
+// (Algorithm tf has a branch of its own for it): with hi = max(|x|, |y|) and
+// lo = min(|x|, |y|), hi sqrt(fma(r, r, 1)) for r = lo / hi, each operation
+// rounded once (a few ulps from the exact value).  Computed here so that the
+// result is that value bit for bit, with less work:
+//  - r < 2^-27 (2^-12 in binary32) leaves fma(r, r, 1) = 1, so an exponent gap
+//    that guarantees it returns hi at once, as does lo = 0;
+//  - r is the quotient of lo and hi both scaled by 2^-e(hi) (exact: hi lands
+//    in [1, 2) and lo, at least 2^-28 of it, stays normal), where the
+//    reciprocal-based IEEE division needs no range scaling;
+//  - 1 + r^2 lies in [1, 2], where sqrt_1p gives the correctly rounded root.
+// hypot1_fast is the same function for (t, 1) with 0 <= t <= 1, where hi = 1
+// and no division is needed.
+// ---------------------------------------------------------------------------
+
+// Correctly rounded sqrt(s) for s in [1, 2].  Just above 1, s = 1 + k 2^-52
+// with a small k puts sqrt(s) = 1 + k 2^-53 - (k 2^-52)^2 / 8 + ... within far
+// less than an ulp below 1 + k 2^-53: the nearest double for even k, a rounding
+// midpoint for odd k, which then rounds down.  Such near-midpoints would send
+// sqrt_dw_cr to its exact fallback for a large share of small tangents, so for
+// s - 1 < 2^-26 (where the second-order term stays below 2^-55) the root is
+// formed directly: 1 + ((s - 1)/2 - 2^-54) rounds to exactly that value (the
+// inner terms are exact; the offset breaks the midpoint downwards and moves an
+// even k's result by a quarter ulp only).
+__device__ __attribute__((always_inline)) inline double sqrt_1p(double s) {
+  if (s < 1.0 + 0x1p-26) return 1.0 + fma(s - 1.0, 0.5, -0x1p-54);
+  return sqrt_dw_cr(s, 0.0, s, 0.0, 0.0, 0.0);
+}
+__device__ __attribute__((always_inline)) inline double hypot_fast(double x, double y) {
+  double a = fabs(x), b = fabs(y);
+  double hi = fmax(a, b), lo = fmin(a, b);
+  if (lo == 0.0 || isinf(hi)) return hi;
+  int eh = ilog2(hi);
+  if (eh - ilog2(lo) >= 28) return hi;
+  double hs = scale2(hi, -eh), ls = scale2(lo, -eh);
+  double r = div_with(ls, hs, rcp_refined(hs));
+  return hi * sqrt_1p(fma(r, r, 1.0));
+}
+__device__ __attribute__((always_inline)) inline double hypot1_fast(double t) {
+  if (t < 0x1p-27) return 1.0;
+  return sqrt_1p(fma(t, t, 1.0));
+}
+__device__ __attribute__((always_inline)) inline float hypot_fast(float x, float y) {
+  float a = fabsf(x), b = fabsf(y);
+  float hi = fmaxf(a, b), lo = fminf(a, b);
+  if (lo == 0.0f || isinf(hi)) return hi;
+  if (ilog2(hi) - ilog2(lo) >= 13) return hi;
+  float r = lo / hi;
+  float s = fmaf(r, r, 1.0f);
+  return hi * sqrtf(s);  // correctly rounded: the library is built for it
+}
+__device__ __attribute__((always_inline)) inline float hypot1_fast(float t) {
+  if (t < 0x1p-12f) return 1.0f;
+  return sqrtf(fmaf(t, t, 1.0f));
+}
+
+// the hypot of the variant: correctly rounded (CR) or fast
+template <bool CR, class R> __device__ __attribute__((always_inline)) inline R hyp(R x, R y) {
+  if constexpr (CR)
+    return hypot_cr(x, y);
+  else
+    return hypot_fast(x, y);
+}
+// the same for (t, 1) with 0 <= t <= 1
+template <bool CR, class R> __device__ __attribute__((always_inline)) inline R hyp1(R t) {
+  if constexpr (CR)
+    return hypot1_le1(t);
+  else
+    return hypot1_fast(t);
+}
+
+// ---------------------------------------------------------------------------
 // (e,f) pairs (Sect. 2, eqs. unary, binary, plus, minus, prec).  Kept as frexp
 // returns them: x = f 2^e with f in [1/2, 1), and (0, 0) for zero; the pair of
 // the paper is (e - 1, 2 f), formed on output.  The two forms differ by exact
@@ -589,7 +661,7 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part9(M2<R>
 // Sect. 3.1, classes 3 (one non-zero column) and 5 (one non-zero row): the
 // non-zero pair made non-negative by signs, the larger one first, and one Givens
 // rotation with tangent smaller/larger (eq. Givens, Lemma sincostheta).
-template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R> G, int t) {
+template <class R, bool CR> __device__ __attribute__((always_inline)) Part<R> part35(M2<R> G, int t) {
   bool col = (t == 3 || t == 12);
   bool pfirst = (t == 12 || t == 10);  // P_V for t = 12, P_U for t = 10
   R a, b;
@@ -601,7 +673,7 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R
   bool sw = a < b;
   if (sw) { R t2 = a; a = b; b = t2; }
   R tn = b / a;
-  R sec = hypot1_le1(tn);  // 0 <= tan <= 1
+  R sec = hyp1<CR>(tn);  // 0 <= tan <= 1
   R gc, gs;
   cos_sin(tn, sec, gc, gs);
   Fac<R> W = fac(sp_mul(sp_diag(na, nb), sp_x(sw)), gc, gs, sp_id());
@@ -609,7 +681,7 @@ template <class R> __device__ __attribute__((always_inline)) Part<R> part35(M2<R
   Part<R> r;
   r.U = col ? W : P;
   r.V = col ? P : W;
-  r.s1 = nrm(hypot_cr(a, b));
+  r.s1 = nrm(hyp<CR>(a, b));
   r.s2 = nrm((R)0);
   return r;
 }
@@ -632,7 +704,7 @@ template <class R> struct Tri {
   bool psig, ovf;
 };
 
-template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a, R b, R d) {
+template <class R, bool CR> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a, R b, R d) {
   const R inf = (R)INFINITY;
   Tri<R> o;
   // Algorithm tf: tan(2 phi), cases in their listed order.  The two cases that
@@ -649,6 +721,16 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
       ef_case = true;
     } else if (ratio_below_eps(a, b)) {
       simple = true;  // eq. t2f''
+    } else if (!CR) {
+      // the branch for a hypot that is not correctly rounded: x and y are the
+      // smaller of a, b and d divided by the larger of a, b, and tan(2 phi) =
+      // 2xy / (1 + (x-y)(x+y)) for a > b, 2y / (1 + (x-y)(x+y)) otherwise (no
+      // squares of the inputs; a negative denominator counts as 0).  Written
+      // without a branch so that lanes of both kinds share the divisions.
+      R m = fmax(a, b);
+      R xq = fmin(a, b) / m, yq = d / m;
+      R num = (a > b) ? ((R)2 * xq) * yq : (R)2 * yq;
+      t2 = num / fmax(fma(xq - yq, xq + yq, (R)1), (R)0);
     } else {
       R h = hypot_cr(a, b);
       if (h == d) {
@@ -662,8 +744,8 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
   }
   if (simple) t2 = ((R)2 * d) / b;
   if (ef_case) t2 = flo(ef_div(ef_mul(ef_twice(nrm(b)), nrm(d)), ef_mul(x, y)));
-  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hypot_cr(t2, (R)1));  // eq. tf
-  R sphi_sec = hypot1_le1(tphi);  // 0 <= tan(phi) <= 1
+  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hyp<CR>(t2, (R)1));  // eq. tf
+  R sphi_sec = hyp1<CR>(tphi);  // 0 <= tan(phi) <= 1
   o.tphi = tphi;
   cos_sin(tphi, sphi_sec, o.cphi, o.sphi);
   // Algorithm tp
@@ -681,7 +763,7 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
     s2 = ef_mul(nrm(d), bcos);
   } else {  // eq. s'
     o.ovf = false;
-    R spsi_sec = hypot_cr(tpsi, (R)1);
+    R spsi_sec = hyp<CR>(tpsi, (R)1);
     cos_sin(tpsi, spsi_sec, o.cpsi, o.spsi);
     EF<R> sp = ef_div(nrm(sphi_sec), nrm(spsi_sec));
     s1 = ef_div(nrm(a), sp);
@@ -693,8 +775,9 @@ template <class R> __device__ __attribute__((always_inline)) Tri<R> tri_svd(R a,
   return o;
 }
 
-// The whole method for one matrix.
-template <class R>
+// The whole method for one matrix; CR selects the correctly rounded hypot (the
+// method as analysed) or the fast variant.
+template <class R, bool CR = true>
 __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g22) {
   Svd2<R> out;
   int t = ztype(g11, g21, g12, g22);
@@ -764,7 +847,7 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
   } else {
     // Sect. 3.2.2: class 15, the fully pivoted URV
     is15 = true;
-    R w1 = hypot_cr(G.a, G.c), w2 = hypot_cr(G.b, G.d);
+    R w1 = hyp<CR>(G.a, G.c), w2 = hyp<CR>(G.b, G.d);
     bool pv = w1 < w2;
     if (pv) {
       R tw = w1; w1 = w2; w2 = tw;
@@ -781,7 +864,7 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
     }
     // G''' = [G.a G.b; G.c G.d], G.a >= G.c > 0
     tan_t = G.c / G.a;
-    sec_t = hypot1_le1(tan_t);  // 0 < tan(theta) <= 1
+    sec_t = hyp1<CR>(tan_t);  // 0 < tan(theta) <= 1
     r11 = w1;
     bool exact = fma(-tan_t, G.a, G.c) == (R)0;
     bool same = negative(G.b) == negative(G.d);
@@ -823,7 +906,7 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
   }
 
   if (simple) {
-    part = ((1u << ts) & CL9) ? part9(Gs, ts) : part35(Gs, ts);
+    part = ((1u << ts) & CL9) ? part9(Gs, ts) : part35<R, CR>(Gs, ts);
     if (degen) {
       R ct, st;
       cos_sin(tan_t, sec_t, ct, st);
@@ -837,7 +920,7 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
     bool swp = r11 < r22;
     if (swp) info |= I_RSWAP;
     R ta_ = swp ? r22 : r11, td_ = swp ? r11 : r22;  // one inlined copy for both cases
-    Tri<R> tr = tri_svd(ta_, r12, td_);
+    Tri<R> tr = tri_svd<R, CR>(ta_, r12, td_);
     if (tr.ovf) info |= I_TPSI_OVF;
     if (tr.psig) info |= I_PSIG;
     // common right factor S2 P_sigma (S2 = diag(1,-1) when swapped); the
@@ -866,7 +949,7 @@ __device__ __attribute__((always_inline)) Svd2<R> svd2(R g11, R g21, R g12, R g2
           sa = negative(num) ? (R)-1 : (R)1;
         } else {
           R ta = num / den;
-          R sa_sec = hypot_cr(ta, (R)1);
+          R sa_sec = hyp<CR>(ta, (R)1);
           R sd = negative(den) ? (R)-1 : (R)1;
           R c0, s0;
           cos_sin(ta, sa_sec, c0, s0);

@@ -23,8 +23,9 @@ std::string &last_error_ref() {
 
 // 6 waves per SIMD (at most 80 registers): the straight-line SVD code issues
 // back-to-back dependent FP64 instructions, and one more resident wave hides
-// more of their latency than the few registers given up cost (measured)
-template <class R>
+// more of their latency than the few registers given up cost (measured).
+// CR: the correctly rounded hypot (the method as analysed) or the fast variant.
+template <class R, bool CR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_soa(int64_t n, const R *__restrict__ g11,
                                                     const R *__restrict__ g21,
                                                     const R *__restrict__ g12,
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
                                                     R *__restrict__ s1, R *__restrict__ s2) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  Svd2<R> r = svd2<R>(g11[i], g21[i], g12[i], g22[i]);
+  Svd2<R> r = svd2<R, CR>(g11[i], g21[i], g12[i], g22[i]);
   cu[i] = r.cu;
   su[i] = r.su;
   cv[i] = r.cv;
@@ -179,15 +180,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__
                fma(t21, v11, t22 * v12), fma(t21, v21, t22 * v22));
 }
 
-template <class R>
+template <class R, bool CR>
 __global__ __launch_bounds__(kBlock) void k_hypot(int64_t n, const R *__restrict__ x,
                                                   const R *__restrict__ y, R *__restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = hypot_cr(x[i], y[i]);
+  out[i] = hyp<CR>(x[i], y[i]);
 }
 
-template <class R>
+template <class R, bool CR>
 static int fwd_soa(int64_t n, const R *g11, const R *g21, const R *g12, const R *g22, R *cu, R *su,
                    R *cv, R *sv, R *f1, R *f2, int32_t *e1, int32_t *e2, int32_t *info, R *s1,
                    R *s2, void *stream) {
@@ -198,7 +199,7 @@ static int fwd_soa(int64_t n, const R *g11, const R *g21, const R *g12, const R 
   KSVD2_REQ(cu, w); KSVD2_REQ(su, w); KSVD2_REQ(cv, w); KSVD2_REQ(sv, w);
   KSVD2_REQ(f1, w); KSVD2_REQ(f2, w); KSVD2_REQ(e1, 4); KSVD2_REQ(e2, 4); KSVD2_REQ(info, 4);
   KSVD2_OPT(s1, w); KSVD2_OPT(s2, w);
-  hipLaunchKernelGGL(k_fwd_soa<R>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
+  hipLaunchKernelGGL((k_fwd_soa<R, CR>), dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
                      g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1, s2);
   return launch_status("ksvd2 forward launch");
 }
@@ -239,13 +240,32 @@ static int bwd(int64_t n, const void *U, const void *S, const void *V, const voi
   return launch_status("ksvd2 backward launch");
 }
 
+template <bool CR>
+static int hypot_launch(int dtype, int64_t n, const void *x, const void *y, void *out,
+                        void *stream) {
+  if (n < 0) return fail(KSVD2_EINVAL, "n < 0");
+  if (dtype != 0 && dtype != 1)
+    return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+  if (n == 0) return KSVD2_OK;
+  size_t w = dtype ? 8 : 4;
+  KSVD2_REQ(x, w); KSVD2_REQ(y, w); KSVD2_REQ(out, w);
+  if (dtype)
+    hipLaunchKernelGGL((k_hypot<double, CR>), dim3(grid_for(n)), dim3(kBlock), 0,
+                       (hipStream_t)stream, n, (const double *)x, (const double *)y,
+                       (double *)out);
+  else
+    hipLaunchKernelGGL((k_hypot<float, CR>), dim3(grid_for(n)), dim3(kBlock), 0,
+                       (hipStream_t)stream, n, (const float *)x, (const float *)y, (float *)out);
+  return launch_status("ksvd2 hypot launch");
+}
+
 }  // namespace ksvd2
 
 using namespace ksvd2;
 
 extern "C" {
 
-int ksvd2_version(void) { return 1; }
+int ksvd2_version(void) { return 2; }
 
 const char *ksvd2_last_error(void) { return last_error_ref().c_str(); }
 
@@ -253,7 +273,7 @@ int ksvd2_batch_f64(int64_t batch, const double *g11, const double *g21, const d
                     const double *g22, double *cu, double *su, double *cv, double *sv, double *f1,
                     double *f2, int32_t *e1, int32_t *e2, int32_t *info, double *s1_plain,
                     double *s2_plain, void *stream) {
-  return fwd_soa<double>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
+  return fwd_soa<double, true>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
                          s1_plain, s2_plain, stream);
 }
 
@@ -261,7 +281,7 @@ int ksvd2_batch_f32(int64_t batch, const float *g11, const float *g21, const flo
                     const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
                     float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1_plain,
                     float *s2_plain, void *stream) {
-  return fwd_soa<float>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1_plain,
+  return fwd_soa<float, true>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1_plain,
                         s2_plain, stream);
 }
 
@@ -284,21 +304,30 @@ int ksvd2_batch_backward(int dtype, int64_t batch, const void *U, const void *S,
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
 }
 
+int ksvd2_batch_fast_f64(int64_t batch, const double *g11, const double *g21, const double *g12,
+                         const double *g22, double *cu, double *su, double *cv, double *sv,
+                         double *f1, double *f2, int32_t *e1, int32_t *e2, int32_t *info,
+                         double *s1_plain, double *s2_plain, void *stream) {
+  return fwd_soa<double, false>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
+                                s1_plain, s2_plain, stream);
+}
+
+int ksvd2_batch_fast_f32(int64_t batch, const float *g11, const float *g21, const float *g12,
+                         const float *g22, float *cu, float *su, float *cv, float *sv, float *f1,
+                         float *f2, int32_t *e1, int32_t *e2, int32_t *info, float *s1_plain,
+                         float *s2_plain, void *stream) {
+  return fwd_soa<float, false>(batch, g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info,
+                               s1_plain, s2_plain, stream);
+}
+
 int ksvd2_hypot_batch(int dtype, int64_t n, const void *x, const void *y, void *out,
                       void *stream) {
-  if (n < 0) return fail(KSVD2_EINVAL, "n < 0");
-  if (dtype != 0 && dtype != 1)
-    return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
-  if (n == 0) return KSVD2_OK;
-  size_t w = dtype ? 8 : 4;
-  KSVD2_REQ(x, w); KSVD2_REQ(y, w); KSVD2_REQ(out, w);
-  if (dtype)
-    hipLaunchKernelGGL(k_hypot<double>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream,
-                       n, (const double *)x, (const double *)y, (double *)out);
-  else
-    hipLaunchKernelGGL(k_hypot<float>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream,
-                       n, (const float *)x, (const float *)y, (float *)out);
-  return launch_status("ksvd2 hypot launch");
+  return hypot_launch<true>(dtype, n, x, y, out, stream);
+}
+
+int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, void *out,
+                           void *stream) {
+  return hypot_launch<false>(dtype, n, x, y, out, stream);
 }
 
 }  // extern "C"

@@ -3,6 +3,8 @@
 python -m paper_2407_13116_amd.probe --workload NAME [--reps K]
 
   fwd64 / fwd32     the 2^24-matrix forward workload (k_fwd_soa)
+  fast64 / fast32   the same workload, the variant without a correctly rounded hypot
+                    (--fast selects that variant for the cls* workloads too)
   cls15_64 / cls13_64 / cls15_32 / cls13_32
                     2^22 matrices of one class only (general, upper triangular; exponents
                     in [-20,20]): no lane divergence between classes, so the per-wave VALU
@@ -27,11 +29,11 @@ def _dev(*a):
     return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in a]
 
 
-def _fwd(g, reps):
+def _fwd(g, reps, fast=False):
     d = _dev(*g)
-    out = api.ksvd2_batch(*d, plain=False)
+    out = api.ksvd2_batch(*d, plain=False, fast=fast)
     for _ in range(reps):
-        api.ksvd2_batch(*d, plain=False, out=out)
+        api.ksvd2_batch(*d, plain=False, out=out, fast=fast)
 
 
 def _class_batch(dtype, tri, B=1 << 22, seed=31):
@@ -46,13 +48,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", required=True)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--fast", action="store_true")
     a = ap.parse_args(argv)
     w, reps = a.workload, a.reps
-    if w in ("fwd64", "fwd32"):
-        _fwd(inputs.forward_sweep(np.float64 if w == "fwd64" else np.float32), reps)
+    if w in ("fwd64", "fwd32", "fast64", "fast32"):
+        dt = np.float64 if w.endswith("64") else np.float32
+        _fwd(inputs.forward_sweep(dt), reps, fast=w.startswith("fast"))
     elif w.startswith("cls"):
         dt = np.float64 if w.endswith("64") else np.float32
-        _fwd(_class_batch(dt, tri=w.startswith("cls13")), reps)
+        _fwd(_class_batch(dt, tri=w.startswith("cls13")), reps, fast=a.fast)
     elif w in ("bwd64", "bwd32"):
         dt = np.float64 if w == "bwd64" else np.float32
         G, dS, dU, dV, _ = inputs.diff_batch(dt)

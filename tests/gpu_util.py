@@ -12,12 +12,12 @@ def to_host(d):
     return {k: v.cpu().numpy() for k, v in d.items()}
 
 
-def gpu_ksvd2(planes, plain=True):
+def gpu_ksvd2(planes, plain=True, fast=False):
     import torch
 
     from paper_2407_13116_amd import api
 
-    out = api.ksvd2_batch(*to_dev(*planes), plain=plain)
+    out = api.ksvd2_batch(*to_dev(*planes), plain=plain, fast=fast)
     torch.cuda.synchronize()
     return to_host(out)
 
