@@ -70,7 +70,8 @@ def lib():
         for name in ("orc_kog_sweep_f64", "orc_kog_sweep_f32"):
             fn = getattr(L, name)
             fn.restype = i32
-            fn.argtypes = [i32, p, p, p, i32, d, i32, ctypes.POINTER(i32)]
+            fn.argtypes = [i32, p, p, p, i32, d, i32, i32, ctypes.POINTER(i32)]
+        L.orc_step_pairs.argtypes = [i32, i32, i32, p]
         _lib = L
     return _lib
 
@@ -181,11 +182,13 @@ def full_uv(out):
     return res[0], res[1]
 
 
-def kog_sweep(G, max_sweeps: int = 30, tol_factor: float = 1.0, U=None, V=None):
-    """Two-sided Kogbetliantz iteration on one n x n matrix (round-robin parallel
-    ordering).  G is taken column-major (pass a Fortran-ordered or transposed
-    array); returns (G_out, U, V, status, sweeps) with the arrays column-major.
-    tol_factor < 0 disables the stopping test (exactly max_sweeps sweeps)."""
+def kog_sweep(G, max_sweeps: int = 30, tol_factor: float = 1.0, U=None, V=None,
+              ordering: int = 0):
+    """Two-sided Kogbetliantz iteration on one n x n matrix (parallel ordering 0 =
+    round-robin, 1 = modified modulus).  G is taken column-major (pass a
+    Fortran-ordered or transposed array); returns (G_out, U, V, status, sweeps) with
+    the arrays column-major.  tol_factor < 0 disables the stopping test (exactly
+    max_sweeps sweeps)."""
     G = np.array(G, order="F", copy=True)
     n = G.shape[0]
     dt = G.dtype
@@ -195,8 +198,15 @@ def kog_sweep(G, max_sweeps: int = 30, tol_factor: float = 1.0, U=None, V=None):
     sw = ctypes.c_int()
     fn = getattr(lib(), "orc_kog_sweep_" + _dt(dt))
     st = fn(n, _ptr(G), _ptr(U), _ptr(V), int(max_sweeps), float(tol_factor), int(acc),
-            ctypes.byref(sw))
+            int(ordering), ctypes.byref(sw))
     return G, U, V, st, sw.value
+
+
+def step_pairs(ordering: int, n: int, k: int):
+    """The n/2 pivot pairs (i < j) of step k of a sweep, as an int array [n/2, 2]."""
+    out = np.empty((n // 2, 2), np.int32)
+    lib().orc_step_pairs(int(ordering), int(n), int(k), _ptr(out))
+    return out
 
 
 def svd2_backward(U, S, V, dS=None, dU=None, dV=None, tau: float = 0.0):

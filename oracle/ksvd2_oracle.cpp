@@ -982,12 +982,44 @@ static int rr_player(int n, int k, int q) {
   return 1 + (q - 1 + k) % (n - 1);
 }
 
+/* The pivot pairs (i < j) of step k of a sweep, n/2 of them, in pi, pj.
+   ordering 0: the round-robin pairs above, slot by slot.
+   ordering 1: the modified modulus strategy (Sect. 4 names it for the order-n
+   iteration), read as the modulus strategy for the odd order m = n - 1 -- step
+   k pairs the indices i < j < m with i + j = k (mod m) and leaves idle the
+   index c with 2c = k (mod m) -- with the idle index paired with m. */
+static void step_pairs(int ordering, int n, int k, int *pi, int *pj) {
+  int np = n / 2, t = 0;
+  if (ordering == 0) {
+    for (int q = 0; q < np; ++q) {
+      int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
+      pi[q] = std::min(a, b);
+      pj[q] = std::max(a, b);
+    }
+    return;
+  }
+  int m = n - 1;
+  for (int c = 0; c < m; ++c)
+    if ((2 * c) % m == k) {
+      pi[t] = c;
+      pj[t] = m;
+      ++t;
+    }
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j)
+      if ((i + j) % m == k) {
+        pi[t] = i;
+        pj[t] = j;
+        ++t;
+      }
+}
+
 /* one element pair of a rotation: x' = a x + b y as fma(a, x, b*y) */
 template <class R> static R rot_lin(R a, R x, R b, R y) { return std::fma(a, x, b * y); }
 
 template <class R>
 static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor, int accumulate,
-                     int *sweeps_done) {
+                     int ordering, int *sweeps_done) {
   if (!accumulate) {
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
@@ -1025,11 +1057,9 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
   int sw = 0;
   for (sw = 0; sw < max_sweeps; ++sw) {
     for (int k = 0; k < n - 1; ++k) {
+      step_pairs(ordering, n, k, pi, pj);
       for (int q = 0; q < np; ++q) {
-        int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
-        int i = std::min(a, b), j = std::max(a, b);
-        pi[q] = i;
-        pj[q] = j;
+        int i = pi[q], j = pj[q];
         R gii = G[i + (int64_t)i * n], gji = G[j + (int64_t)i * n];
         R gij = G[i + (int64_t)j * n], gjj = G[j + (int64_t)j * n];
         Res<R> r = ksvd2<R>(gii, gji, gij, gjj);
@@ -1262,13 +1292,28 @@ int orc_ksvd2_fast_f32(int64_t n, const float *g11, const float *g21, const floa
 /* One n x n matrix (column-major, in place): returns 0 when converged,
    1 when max_sweeps ran out; tol_factor < 0 disables the stopping test. */
 int orc_kog_sweep_f64(int n, double *G, double *U, double *V, int max_sweeps, double tol_factor,
-                      int accumulate, int *sweeps_done) {
-  return sweep_one<double>(n, G, U, V, max_sweeps, tol_factor, accumulate, sweeps_done);
+                      int accumulate, int ordering, int *sweeps_done) {
+  return sweep_one<double>(n, G, U, V, max_sweeps, tol_factor, accumulate, ordering,
+                           sweeps_done);
 }
 
 int orc_kog_sweep_f32(int n, float *G, float *U, float *V, int max_sweeps, double tol_factor,
-                      int accumulate, int *sweeps_done) {
-  return sweep_one<float>(n, G, U, V, max_sweeps, tol_factor, accumulate, sweeps_done);
+                      int accumulate, int ordering, int *sweeps_done) {
+  return sweep_one<float>(n, G, U, V, max_sweeps, tol_factor, accumulate, ordering,
+                          sweeps_done);
+}
+
+/* the pivot pairs of step k (for the ordering pins): 2 * (n/2) ints, i then j */
+void orc_step_pairs(int ordering, int n, int k, int *out) {
+  int np = n / 2;
+  int *pi = new int[np], *pj = new int[np];
+  step_pairs(ordering, n, k, pi, pj);
+  for (int q = 0; q < np; ++q) {
+    out[2 * q] = pi[q];
+    out[2 * q + 1] = pj[q];
+  }
+  delete[] pi;
+  delete[] pj;
 }
 
 }  // extern "C"

@@ -3,7 +3,9 @@
 Sweep: converged results are checked against LAPACK's singular values (numpy.linalg.svd,
 run as a library), the stopping test (off-diagonal norm <= n eps ||G||_F), orthogonality of
 U and V and the reconstruction G = U Sigma V^T, also for entries near the overflow
-threshold (the global power-of-two scaling).
+threshold (the global power-of-two scaling), for both parallel orderings; each ordering's
+steps are checked by brute force to be perfect matchings of the indices that together meet
+every pair exactly once per sweep.
 
 Adjoint: central finite differences of the oracle's own forward map (an independent
 numerical derivative) on general, near-degenerate (gauge-invariant polar-factor loss) and
@@ -22,12 +24,37 @@ def _eps(dtype):
     return 2.0 ** (-53 if np.dtype(dtype) == np.float64 else -24)
 
 
+@pytest.mark.parametrize("ordering", [0, 1], ids=["round-robin", "modulus"])
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 12, 18, 34, 64])
+def test_ordering_is_a_parallel_sweep(orc, ordering, n):
+    """Each of the n - 1 steps pairs every index exactly once (n/2 disjoint pivots), and
+    over the sweep every one of the n(n-1)/2 pairs i < j meets exactly once."""
+    seen = np.zeros((n, n), np.int32)
+    for k in range(n - 1):
+        P = orc.step_pairs(ordering, n, k)
+        assert P.shape == (n // 2, 2)
+        assert np.all(P[:, 0] < P[:, 1])
+        assert sorted(P.ravel().tolist()) == list(range(n))
+        seen[P[:, 0], P[:, 1]] += 1
+    iu = np.triu_indices(n, 1)
+    assert np.all(seen[iu] == 1)
+
+
+def test_orderings_differ_in_step_order(orc):
+    """The two orderings visit the same pairs per sweep, in a different step order."""
+    a = [sorted(map(tuple, orc.step_pairs(0, 8, k).tolist())) for k in range(7)]
+    b = [sorted(map(tuple, orc.step_pairs(1, 8, k).tolist())) for k in range(7)]
+    assert a != b
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", [2, 4, 6, 10, 16, 32])
-def test_sweep_converges_to_svd(orc, dtype, n):
+@pytest.mark.parametrize("ordering", [0, 1], ids=["round-robin", "modulus"])
+def test_sweep_converges_to_svd(orc, dtype, n, ordering):
     rng = np.random.default_rng(100 + n)
     G0 = (rng.standard_normal((n, n)) * np.exp2(rng.integers(-3, 4, (n, n)))).astype(dtype)
-    G, U, V, st, sw = orc.kog_sweep(np.asfortranarray(G0), max_sweeps=30, tol_factor=1.0)
+    G, U, V, st, sw = orc.kog_sweep(np.asfortranarray(G0), max_sweeps=30, tol_factor=1.0,
+                                    ordering=ordering)
     assert st == 0 and 1 <= sw <= 15, (st, sw)
     eps = _eps(dtype)
     G0d = G0.astype(np.float64)
