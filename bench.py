@@ -184,6 +184,23 @@ def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=6
                      "eff_GBs": bytes_ / times[-1] / 1e9,
                      "matrices_per_s": len(mats) / times[-1]}
         log(f"[bench] sweep {mode}: {res[mode]}")
+    if "persistent" in modes:
+        # the same solve with the modified modulus ordering (persistent mode)
+        p.G.copy_(G0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o2 = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode="persistent",
+                                workspace=ws, sort=True, ordering="modulus")
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        s2 = np.abs(o2["sweeps"].cpu().numpy()).astype(np.int64)
+        res["persistent_modulus_ordering"] = {
+            "seconds": t, "sweeps_mean": float(s2.mean()), "sweeps_max": int(s2.max()),
+            "converged": bool(np.all(o2["sweeps"].cpu().numpy() > 0))}
+        log(f"[bench] sweep persistent, modified modulus: {res['persistent_modulus_ordering']}")
+        p.G.copy_(G0)
+        out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode="persistent",
+                                 workspace=ws, sort=True)
     # the sigma gradient dG = U diag(dsigma) V^T of the last solve: 2 n^3 flops per matrix
     ds = torch.from_numpy(np.random.default_rng(17).standard_normal(int(p.n.sum())).astype(dtype)).cuda()
     fl = float(np.sum(2.0 * p.n.astype(np.float64) ** 3))

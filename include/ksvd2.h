@@ -167,8 +167,8 @@ int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, v
 /*
  * kog_sweep_batch -- the two-sided Kogbetliantz iteration (Sect. 1, eq. SVD) on
  * `nmat` independent square matrices of even orders n_k (2 <= n_k <= 8192, at
- * most 65535 matrices): in each parallel step the n_k/2 disjoint pivots of a
- * round-robin ordering are diagonalised by the 2x2 SVD above (U_p, sigma,
+ * most 65535 matrices): in each parallel step the n_k/2 disjoint pivots of the
+ * chosen ordering are diagonalised by the 2x2 SVD above (U_p, sigma,
  * V_p; sigma rounded once to W), U_p^T is applied to the pivot rows of G, then
  * V_p to the pivot columns (each element pair as fma(a, x, b*y)), the pivot
  * block is set to diag(sigma_1, sigma_2), and U <- U U_p, V <- V V_p on the
@@ -196,16 +196,26 @@ int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, v
  *           return KSVD2_EINVAL naming mode 0, which takes every order;
  *       2 = mode 1 captured into a hipGraph on first use and replayed on later
  *           calls with identical arguments (needs a non-null stream).
+ * ordering: 0 = round-robin (circle method: index 0 fixed, 1..n-1 rotate by one
+ *           position per step, positions s and n-1-s meet);
+ *           1 = modified modulus (the strategy Sect. 4 names for the order-n
+ *           iteration): with m = n-1, step k pairs the indices below m whose sum
+ *           is k mod m, and the index c with 2c = k mod m with m.
+ *           Both visit every pair once per sweep, in different step orders.
  * All modes perform the same arithmetic in the same order: bitwise identical.
  * workspace: device memory of at least kog_sweep_workspace_size() bytes,
  * 256-byte aligned, owned by the caller, used only during the call's work.
- * Inputs must keep ||G||_F well below the overflow threshold (the iteration
- * itself does not rescale G).
+ * Overflow: G is first multiplied by 2^s_G with s_G = e_nu - 2 - e_G - ceil(lg n)
+ * when that is negative (e_G the largest exponent of its entries, e_nu that of
+ * the largest finite value), so no two-sided update can overflow, and scaled
+ * back on exit; the stopping test takes its norms of G 2^-t (t the largest
+ * exponent after the scaling).  Status codes as above; an invalid mode or
+ * ordering is KSVD2_EINVAL.
  */
 int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
                     void *G, void *U, void *V, void *sigma, int32_t *sweeps_out,
                     int32_t max_sweeps, double tol_factor, int accumulate, int mode,
-                    void *workspace, size_t ws_bytes, void *stream);
+                    int ordering, void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * kog_sweep_sort -- the delivered singular values in the usual order: for each

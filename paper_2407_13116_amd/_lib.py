@@ -46,7 +46,7 @@ def lib():
             fn.argtypes = [i32, i64, p, p, p, p]
         if hasattr(L, "kog_sweep_batch"):
             L.kog_sweep_batch.restype = i32
-            L.kog_sweep_batch.argtypes = [i32, i64, p, p, p, p, p, p, p, i32, d, i32, i32, p,
+            L.kog_sweep_batch.argtypes = [i32, i64, p, p, p, p, p, p, p, i32, d, i32, i32, i32, p,
                                           ctypes.c_size_t, p]
             L.kog_sweep_workspace_size.restype = ctypes.c_size_t
             L.kog_sweep_workspace_size.argtypes = [i32, i64, p]

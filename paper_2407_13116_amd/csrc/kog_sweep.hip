@@ -63,6 +63,7 @@ struct SweepDesc {
   int32_t *done;         // converged flag
   int32_t *scale;        // s_G of matrix m (0: not scaled)
   int32_t *nexp;         // t of matrix m: the norms are taken of G 2^-t
+  int ord;               // pivot ordering: 0 round-robin, 1 modified modulus
 };
 
 // Slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
@@ -75,10 +76,32 @@ __device__ inline int rr_player(int n, int k, int s) {
   return 1 + (x >= n - 1 ? x - (n - 1) : x);
 }
 
-__device__ inline void rr_pair(int n, int k, int q, int &i, int &j) {
-  int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
+// Slot q of step k in the modified modulus ordering (the parallel strategy
+// Sect. 4 names for the order-n iteration): with m = n - 1 odd, step k pairs the
+// indices below m whose sum is k modulo m, and the one index c with 2c = k
+// (mod m), which the modulus strategy for odd orders leaves idle, with m.  Slot
+// 0 holds (c, m), slot q >= 1 the pair c -+ q (mod m).  Every pair meets once in
+// the m steps of a sweep.
+__device__ inline void mm_pair(int n, int k, int q, int &i, int &j) {
+  const int m = n - 1;
+  const int c = (k & 1) ? (k + m) >> 1 : k >> 1;  // 2c = k (mod m)
+  int a = c - q, b = c + q;
+  a = a < 0 ? a + m : a;
+  b = b >= m ? b - m : b;
+  b = q == 0 ? m : b;
   i = a < b ? a : b;
   j = a < b ? b : a;
+}
+
+// the pivot pair of slot q in step k of the ordering `ord`, i < j
+__device__ inline void piv_pair(int ord, int n, int k, int q, int &i, int &j) {
+  if (ord == 1) {
+    mm_pair(n, k, q, i, j);
+  } else {
+    int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
+    i = a < b ? a : b;
+    j = a < b ? b : a;
+  }
 }
 
 template <class R> struct Piv {
@@ -258,7 +281,8 @@ template <class R, int D = 8> __device__ void tile_store(const R *T, R *M, int n
 // last pivot rotates the padding column n of the tile (never copied back), so
 // the loop body has no branches
 template <class R, int NG>
-__device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv) {
+__device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv,
+                               int ord) {
   const int ldt = n + 1;
   const int np = n >> 1;
   const int lane = threadIdx.x & 63;
@@ -274,7 +298,7 @@ __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab
         bool ok = q < np;
         int qs = ok ? q : 0;
         int i, j;
-        rr_pair(n, k, qs, i, j);
+        piv_pair(ord, n, k, qs, i, j);
         ii[u] = ok ? i : n;
         jj[u] = ok ? j : n;
         e1[u] = S[qs];           // u11 or v11
@@ -305,13 +329,13 @@ __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab
 }
 
 template <class R>
-__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv) {
+__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv, int ord) {
   if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
   const int np = n >> 1;
   if (np <= 64)
-    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv);
+    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord);
   else
-    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv);
+    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv, ord);
 }
 
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
@@ -452,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, R
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= np || k >= n - 1 || d.done[m]) return;
   int i, j;
-  rr_pair(n, k, q, i, j);
+  piv_pair(d.ord, n, k, q, i, j);
   int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
   pairs[2 * (slot + q)] = (int16_t)i;
   pairs[2 * (slot + q) + 1] = (int16_t)j;
@@ -505,7 +529,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   R *M = (blockIdx.y ? V : U) + d.off[m];
   tile_load(T, M, n, r0, nr);
   __syncthreads();
-  tile_rotate(T, n, nr, k0, k1, par + kChunk * d.poff[m] * kPivComp, blockIdx.y != 0);
+  tile_rotate(T, n, nr, k0, k1, par + kChunk * d.poff[m] * kPivComp, blockIdx.y != 0, d.ord);
   __syncthreads();
   tile_store(T, M, n, r0, nr);
 }
@@ -574,7 +598,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
       R *slot = tab + (size_t)(k % kChunk) * kPivComp * np;
       for (int q = threadIdx.x; q < np; q += BS) {
         int i, j;
-        rr_pair(n, k, q, i, j);
+        piv_pair(d.ord, n, k, q, i, j);
         spair[2 * q] = (int16_t)i;
         spair[2 * q + 1] = (int16_t)j;
         Piv<R> P = pivot_svd(Gm, n, i, j);
@@ -594,7 +618,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
             int nr = min(rows, n - r0);
             tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
-            tile_rotate(T, n, nr, k0, k, tab, side != 0);
+            tile_rotate(T, n, nr, k0, k, tab, side != 0, d.ord);
             __syncthreads();
             tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
@@ -879,7 +903,7 @@ static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int co
 }
 
 struct GraphKey {
-  int dtype, mode;
+  int dtype, mode, ordering;
   int64_t nmat;
   const void *G, *U, *V, *sigma, *sweeps, *ws;
   int max_sweeps, accumulate;
@@ -889,9 +913,9 @@ struct GraphKey {
   std::vector<int64_t> off;
   int tune_hash;
   bool operator<(const GraphKey &o) const {
-    return std::tie(dtype, mode, nmat, G, U, V, sigma, sweeps, ws, max_sweeps, accumulate, tolf,
+    return std::tie(dtype, mode, ordering, nmat, G, U, V, sigma, sweeps, ws, max_sweeps, accumulate, tolf,
                     st, n, off, tune_hash) <
-           std::tie(o.dtype, o.mode, o.nmat, o.G, o.U, o.V, o.sigma, o.sweeps, o.ws, o.max_sweeps,
+           std::tie(o.dtype, o.mode, o.ordering, o.nmat, o.G, o.U, o.V, o.sigma, o.sweeps, o.ws, o.max_sweeps,
                     o.accumulate, o.tolf, o.st, o.n, o.off, o.tune_hash);
   }
 };
@@ -900,13 +924,15 @@ static std::map<GraphKey, hipGraphExec_t> g_graphs;
 template <class R>
 static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
                       R *G, R *U, R *V, R *sigma, int32_t *sweeps_out, int max_sweeps,
-                      double tolf, int accumulate, int mode, void *ws, size_t ws_bytes,
-                      hipStream_t st) {
+                      double tolf, int accumulate, int mode, int ordering, void *ws,
+                      size_t ws_bytes, hipStream_t st) {
   if (nmat < 0) return fail(KSVD2_EINVAL, "nmat < 0");
   if (nmat == 0) return KSVD2_OK;
   if (!n_host || !off_host) return fail(KSVD2_EINVAL, "n_host and off_host are required");
   if (max_sweeps < 0) return fail(KSVD2_EINVAL, "max_sweeps < 0");
   if (mode < 0 || mode > 2) return fail(KSVD2_EINVAL, "mode must be 0, 1 or 2");
+  if (ordering != 0 && ordering != 1)
+    return fail(KSVD2_EINVAL, "ordering must be 0 (round-robin) or 1 (modified modulus)");
   if (nmat > 65535) return fail(KSVD2_EINVAL, "at most 65535 matrices per call");
   if (mode == 2 && st == nullptr)
     return fail(KSVD2_EINVAL, "mode 2 (hipGraph) needs a non-null stream");
@@ -956,6 +982,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.done = reinterpret_cast<int32_t *>(wsb + L.done);
   d.scale = reinterpret_cast<int32_t *>(wsb + L.scale);
   d.nexp = reinterpret_cast<int32_t *>(wsb + L.nexp);
+  d.ord = ordering;
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
   R *par = reinterpret_cast<R *>(wsb + L.par);
@@ -1045,7 +1072,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   if (mode == 1) return launch_all();
 
   // mode 2: capture the launches once per argument set, then replay
-  GraphKey key{dtype, mode, nmat, G, U, V, sigma, sweeps_out, ws, max_sweeps, accumulate,
+  GraphKey key{dtype, mode, ordering, nmat, G, U, V, sigma, sweeps_out, ws, max_sweeps, accumulate,
                tolf, st, std::vector<int32_t>(n_host, n_host + nmat),
                std::vector<int64_t>(off_host, off_host + nmat), 0};
   for (int b = 0; b < 5; ++b) key.tune_hash = key.tune_hash * 31 + tune.block[di][b];
@@ -1187,16 +1214,16 @@ size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host) 
 int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
                     void *G, void *U, void *V, void *sigma, int32_t *sweeps_out,
                     int32_t max_sweeps, double tol_factor, int accumulate, int mode,
-                    void *workspace, size_t ws_bytes, void *stream) {
+                    int ordering, void *workspace, size_t ws_bytes, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (dtype == 1)
     return sweep_impl<double>(1, nmat, n_host, off_host, (double *)G, (double *)U, (double *)V,
                               (double *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate,
-                              mode, workspace, ws_bytes, st);
+                              mode, ordering, workspace, ws_bytes, st);
   if (dtype == 0)
     return sweep_impl<float>(0, nmat, n_host, off_host, (float *)G, (float *)U, (float *)V,
                              (float *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate, mode,
-                             workspace, ws_bytes, st);
+                             ordering, workspace, ws_bytes, st);
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
 }
 

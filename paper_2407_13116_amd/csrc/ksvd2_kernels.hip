@@ -265,7 +265,7 @@ using namespace ksvd2;
 
 extern "C" {
 
-int ksvd2_version(void) { return 2; }
+int ksvd2_version(void) { return 3; }
 
 const char *ksvd2_last_error(void) { return last_error_ref().c_str(); }
 

@@ -16,6 +16,7 @@ from . import _lib
 
 _DT = {torch.float32: 0, torch.float64: 1}
 MODES = {"plain": 0, "persistent": 1, "graph": 2}
+ORDERINGS = {"round-robin": 0, "modulus": 1}
 
 
 class Packed:
@@ -50,14 +51,16 @@ def workspace_bytes(dtype, n):
 
 def kog_sweep_batch(packed: Packed, max_sweeps: int = 30, tol_factor: float = 1.0,
                     mode: str | int = "persistent", U=None, V=None, workspace=None,
-                    sort: bool = False):
+                    sort: bool = False, ordering: str | int = "round-robin"):
     """Run the sweep in place on packed.G.  Returns dict(G, U, V, sigma, sweeps).
 
+    ``ordering``: "round-robin" (0) or "modulus" (1, the modified modulus strategy).
     ``U``/``V`` given => accumulate (continue from them).  ``sort`` => sigma in
     descending order with the columns of U and V permuted to match (kog_sweep_sort);
     G stays the iterate, so resume only from unsorted U and V."""
     L = _lib.lib()
     mode = MODES.get(mode, mode)
+    ordering = ORDERINGS.get(ordering, ordering)
     G = packed.G
     dt = _DT[G.dtype]
     acc = U is not None
@@ -84,7 +87,7 @@ def kog_sweep_batch(packed: Packed, max_sweeps: int = 30, tol_factor: float = 1.
         rc = L.kog_sweep_batch(dt, len(n), n.ctypes.data_as(ctypes.c_void_p),
                                off.ctypes.data_as(ctypes.c_void_p), G.data_ptr(), U.data_ptr(),
                                V.data_ptr(), sigma.data_ptr(), sweeps.data_ptr(), int(max_sweeps),
-                               float(tol_factor), int(acc), int(mode), wsp + pad,
+                               float(tol_factor), int(acc), int(mode), int(ordering), wsp + pad,
                                workspace.numel() - pad, stream.cuda_stream or None)
     _lib.check(rc, "kog_sweep_batch")
     if sort:

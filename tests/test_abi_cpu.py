@@ -76,9 +76,10 @@ def test_sweep_arguments_rejected(L):
     n = np.array([4, 5], dtype=np.int32)          # odd order
     off = np.array([0, 16], dtype=np.int64)
     p = ctypes.c_void_p(256)
-    args = lambda nn, mode, ws_bytes: (1, 2, nn.ctypes.data_as(ctypes.c_void_p),
-                                       off.ctypes.data_as(ctypes.c_void_p), p, p, p, None, None,
-                                       3, 1.0, 0, mode, p, ws_bytes, None)
+    args = lambda nn, mode, ws_bytes, ordering=0: (1, 2, nn.ctypes.data_as(ctypes.c_void_p),
+                                                   off.ctypes.data_as(ctypes.c_void_p), p, p, p,
+                                                   None, None, 3, 1.0, 0, mode, ordering, p,
+                                                   ws_bytes, None)
     assert L.kog_sweep_batch(*args(n, 1, 1 << 20)) == -1
     assert b"even" in L.ksvd2_last_error()
     n2 = np.array([4, 6], dtype=np.int32)
@@ -87,4 +88,6 @@ def test_sweep_arguments_rejected(L):
     assert need > 0
     assert L.kog_sweep_batch(*args(n2, 2, need)) == -1                # graph mode, null stream
     assert L.kog_sweep_batch(*args(n2, 7, need)) == -1                # bad mode
+    assert L.kog_sweep_batch(*args(n2, 1, need, 2)) == -1             # bad ordering
+    assert b"ordering" in L.ksvd2_last_error()
     assert L.kog_sweep_tune(1, 9, 256) == -1 and L.kog_sweep_tune(1, 0, 300) == -1
