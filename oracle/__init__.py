@@ -72,6 +72,8 @@ def lib():
             fn.restype = i32
             fn.argtypes = [i32, p, p, p, i32, d, i32, i32, ctypes.POINTER(i32)]
         L.orc_step_pairs.argtypes = [i32, i32, i32, p]
+        for name in ("orc_ksvd2c_f64", "orc_ksvd2c_f32"):
+            getattr(L, name).argtypes = [i64, p, p, p, p, p, p, p, i32]
         _lib = L
     return _lib
 
@@ -200,6 +202,29 @@ def kog_sweep(G, max_sweeps: int = 30, tol_factor: float = 1.0, U=None, V=None,
     st = fn(n, _ptr(G), _ptr(U), _ptr(V), int(max_sweeps), float(tol_factor), int(acc),
             int(ordering), ctypes.byref(sw))
     return G, U, V, st, sw.value
+
+
+def ksvd2c(G, nthreads: int = 0):
+    """Complex 2x2 SVD (Sect. 3.4) of G [B,2,2] (complex128 or complex64): returns dict
+    U, V [B,2,2] complex (G = U diag(S) V^H), S [B,2] real, f [B,2], e [B,2] (sigma =
+    f 2^e), info [B]."""
+    G = np.ascontiguousarray(G)
+    if G.dtype == np.complex128:
+        rt = np.float64
+    elif G.dtype == np.complex64:
+        rt = np.float32
+    else:
+        raise TypeError(f"unsupported dtype {G.dtype}")
+    B = G.shape[0]
+    U = np.empty((B, 2, 2), G.dtype)
+    V = np.empty((B, 2, 2), G.dtype)
+    S = np.empty((B, 2), rt)
+    f = np.empty((B, 2), rt)
+    e = np.empty((B, 2), np.int32)
+    info = np.empty(B, np.int32)
+    fn = getattr(lib(), "orc_ksvd2c_" + _dt(rt))
+    fn(B, _ptr(G), _ptr(U), _ptr(S), _ptr(V), _ptr(f), _ptr(e), _ptr(info), int(nthreads))
+    return {"U": U, "V": V, "S": S, "f": f, "e": e, "info": info}
 
 
 def step_pairs(ordering: int, n: int, k: int):

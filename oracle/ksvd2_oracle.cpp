@@ -22,6 +22,7 @@
  *      classes (Sect. 3.1), the URV factorisation (Sect. 3.2), the SVD of
  *      the triangular factor (Sect. 3.3.1, Algorithms tf/tp) and the
  *      assembly with the left-vector heuristic (Sect. 3.3.2)
+ *   4b. the complex 2x2 SVD (Sect. 3.4)
  *   5. the Kogbetliantz sweep over an n x n matrix (Sect. 1, eq. (SVD))
  *   6. extern "C" batch drivers (OpenMP) for the test-suite
  */
@@ -963,6 +964,320 @@ static int batch_fwd(int64_t n, const R *g11, const R *g21, const R *g12, const 
 }
 
 /* ------------------------------------------------------------------------ */
+/* 4b. The complex 2x2 SVD (Sect. 3.4): G = U diag(sigma) V^H.              */
+/*    A real G is the real method; a purely imaginary G = i Im(G) is the    */
+/*    real method on Im(G) with U multiplied by i.  Otherwise every element */
+/*    made real and non-negative goes through a unit phase e^{i alpha} =    */
+/*    g/|g| into a diagonal phase matrix (the complex "sign matrix") and is */
+/*    replaced by |g|; the scale type is s_C = s + 1 (class 9 included, its */
+/*    |g| could overflow); e_G takes the real and imaginary parts; U_+ is   */
+/*    formed explicitly and multiplied by the real factors of the SVD of R; */
+/*    no wider datatype (no eq. EXT), no merging of rotations.              */
+/* ------------------------------------------------------------------------ */
+template <class R> struct Cx {
+  R re, im;
+};
+template <class R> static Cx<R> cx(R re, R im) { return Cx<R>{re, im}; }
+template <class R> static Cx<R> c_conj(Cx<R> a) { return Cx<R>{a.re, -a.im}; }
+/* (a + ib)(c + id) = (ac - bd) + i(ad + bc), each part one fma after one product */
+template <class R> static Cx<R> c_mul(Cx<R> a, Cx<R> b) {
+  return Cx<R>{std::fma(a.re, b.re, -(a.im * b.im)), std::fma(a.re, b.im, a.im * b.re)};
+}
+template <class R> static Cx<R> c_scale(Cx<R> a, R r) { return Cx<R>{a.re * r, a.im * r}; }
+/* |g| (the correctly rounded hypot of the parts) and the phase g/|g| of a
+   non-zero g, taken of g 2^-k with k the exponent of its larger part (exact),
+   so that a subnormal g, whose modulus rounds coarsely, still has a phase of
+   modulus one to working accuracy */
+template <class R> static R c_abs(Cx<R> a) { return cr_hypot(a.re, a.im); }
+template <class R> static Cx<R> c_phase(Cx<R> a) {
+  int k = std::ilogb(std::max(std::fabs(a.re), std::fabs(a.im)));
+  Cx<R> b = {std::scalbn(a.re, -k), std::scalbn(a.im, -k)};
+  R m = cr_hypot(b.re, b.im);
+  return Cx<R>{b.re / m, b.im / m};
+}
+
+template <class R> struct CM2 {
+  Cx<R> a[2][2];
+};
+/* complex 2x2 times real 2x2: each entry is c_i0 r_0j + c_i1 r_1j, per part as
+   fma(c_i0, r_0j, c_i1 r_1j) */
+template <class R> static CM2<R> cm_mul_real(const CM2<R> &C, const M2<R> &B) {
+  CM2<R> o;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      o.a[i][j].re = std::fma(C.a[i][0].re, B.a[0][j], C.a[i][1].re * B.a[1][j]);
+      o.a[i][j].im = std::fma(C.a[i][0].im, B.a[0][j], C.a[i][1].im * B.a[1][j]);
+    }
+  return o;
+}
+/* diag(d1, d2) times a real matrix (row i scaled by d_i): every entry is a
+   phase times a real, one rounding per part */
+template <class R> static CM2<R> cm_diag_real(Cx<R> d1, Cx<R> d2, const M2<R> &B) {
+  CM2<R> o;
+  Cx<R> d[2] = {d1, d2};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) o.a[i][j] = c_scale(d[i], B.a[i][j]);
+  return o;
+}
+/* a real matrix times a complex one, entry by entry as for cm_mul_real */
+template <class R> static CM2<R> real_mul_cm(const M2<R> &A, const CM2<R> &C) {
+  CM2<R> o;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      o.a[i][j].re = std::fma(A.a[i][0], C.a[0][j].re, A.a[i][1] * C.a[1][j].re);
+      o.a[i][j].im = std::fma(A.a[i][0], C.a[0][j].im, A.a[i][1] * C.a[1][j].im);
+    }
+  return o;
+}
+template <class R> static CM2<R> cm_of_real(const M2<R> &A) {
+  CM2<R> o;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) o.a[i][j] = Cx<R>{A.a[i][j], (R)0};
+  return o;
+}
+
+template <class R> struct CRes {
+  CM2<R> U, V;
+  EF<R> s1, s2;
+  uint32_t info;
+};
+
+/* the real factors of the SVD of R = [a b; 0 d] (a, b, d >= 0, b > 0, d > 0),
+   with the swap of eq. RT when a < d: R = Ub diag(s1, s2) Vb^T, P_sigma
+   included (Sect. 3.3; as in the real method's phase 3 without the heuristic) */
+template <class R> struct TriUV {
+  M2<R> Ub, Vb;
+  EF<R> s1, s2;
+  uint32_t flags;
+};
+template <class R> static TriUV<R> tri_uv(R a, R b, R d) {
+  TriUV<R> o;
+  o.flags = 0;
+  bool swapped = a < d;
+  if (swapped) o.flags |= INFO_RSWAP;
+  Tri<R> tr = swapped ? tri_svd<true>(d, b, a) : tri_svd<true>(a, b, d);
+  if (tr.ovf) o.flags |= INFO_TPSI_OVF;
+  if (tr.psig) o.flags |= INFO_PSIG;
+  M2<R> S2 = swapped ? m_diag((R)1, (R)-1) : m_id<R>();
+  M2<R> Ubphi = swapped ? m_mul(m_rot(tr.spsi, tr.cpsi), S2) : m_rot(tr.cphi, tr.sphi);
+  M2<R> Vbpsi = swapped ? m_mul(m_rot(tr.sphi, tr.cphi), S2) : m_rot(tr.cpsi, tr.spsi);
+  M2<R> Psig = tr.psig ? m_x<R>() : m_id<R>();
+  o.Ub = m_mul(Ubphi, Psig);
+  o.Vb = m_mul(Vbpsi, Psig);
+  o.s1 = tr.s1;
+  o.s2 = tr.s2;
+  return o;
+}
+
+template <class R> static CRes<R> ksvd2c(const Cx<R> g[4]) {
+  /* g in the order g11, g21, g12, g22 */
+  CRes<R> res;
+  bool finite = true, all_re = true, all_im = true;
+  for (int k = 0; k < 4; ++k) {
+    finite = finite && std::isfinite(g[k].re) && std::isfinite(g[k].im);
+    all_re = all_re && g[k].im == 0;
+    all_im = all_im && g[k].re == 0;
+  }
+  int t = 0;
+  for (int k = 0; k < 4; ++k) t |= (g[k].re != 0 || g[k].im != 0) << k;
+  if (!finite) {
+    R nan = (R)NAN;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) res.U.a[i][j] = res.V.a[i][j] = Cx<R>{nan, nan};
+    res.s1.e = res.s2.e = 0;
+    res.s1.f = res.s2.f = nan;
+    res.info = (uint32_t)t | INFO_NONFINITE;
+    return res;
+  }
+  if (all_re || all_im) {
+    /* a real matrix, or i times one */
+    Res<R> r = all_re ? ksvd2<R>(g[0].re, g[1].re, g[2].re, g[3].re)
+                      : ksvd2<R>(g[0].im, g[1].im, g[2].im, g[3].im);
+    res.V = cm_of_real(r.V);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        res.U.a[i][j] = all_re ? Cx<R>{r.U.a[i][j], (R)0} : Cx<R>{(R)0, r.U.a[i][j]};
+    res.s1 = r.s1;
+    res.s2 = r.s2;
+    res.info = r.info;
+    bool nu, nv;
+    R c, sn;
+    compact(r.U, c, sn, nu);
+    compact(r.V, c, sn, nv);
+    if (nu) res.info |= INFO_DET_U;
+    if (nv) res.info |= INFO_DET_V;
+    return res;
+  }
+  /* prescaling (eqs. eG, s) with s_C = s + 1 over all real and imaginary parts */
+  Cls c = cls_of(t);
+  int eG = INT_MIN;
+  for (int k = 0; k < 4; ++k) {
+    if (g[k].re != 0) eG = std::max(eG, std::ilogb(g[k].re));
+    if (g[k].im != 0) eG = std::max(eG, std::ilogb(g[k].im));
+  }
+  int s = Fmt<R>::e_nu - eG - (scale_type(c) + 1);
+  Cx<R> h[4];
+  for (int k = 0; k < 4; ++k) h[k] = Cx<R>{std::scalbn(g[k].re, s), std::scalbn(g[k].im, s)};
+  int t1 = 0;
+  for (int k = 0; k < 4; ++k) t1 |= (h[k].re != 0 || h[k].im != 0) << k;
+  Cls c1 = cls_of(t1);
+  uint32_t info = (uint32_t)t | ((uint32_t)t1 << 4);
+  R m[4];
+  Cx<R> ph[4];
+  for (int k = 0; k < 4; ++k) {
+    m[k] = c_abs(h[k]);
+    ph[k] = (m[k] != 0) ? c_phase(h[k]) : Cx<R>{(R)1, (R)0};
+  }
+  const Cx<R> one = {(R)1, (R)0};
+  M2<R> Mg = {{{m[0], m[2]}, {m[1], m[3]}}}; /* |G'| */
+  EF<R> s1, s2;
+  if (c1 == Z9 || c1 == Z3) {
+    /* row phases: the phase of the row's non-zero element (the non-zero
+       column's element for class 3), 1 for a zero row */
+    Cx<R> d1 = (m[0] != 0) ? ph[0] : (m[2] != 0) ? ph[2] : one;
+    Cx<R> d2 = (m[1] != 0) ? ph[1] : (m[3] != 0) ? ph[3] : one;
+    Part<R> p = (c1 == Z9) ? svd_z9(Mg, t1) : svd_z3<true>(Mg, t1);
+    res.U = cm_diag_real(d1, d2, p.U);
+    res.V = cm_of_real(p.V);
+    s1 = p.s1;
+    s2 = p.s2;
+  } else if (c1 == Z5) {
+    /* column phases conj(phase) of the non-zero row's elements go into V */
+    Cx<R> d1 = c_conj((m[0] != 0) ? ph[0] : ph[1]);
+    Cx<R> d2 = c_conj((m[2] != 0) ? ph[2] : ph[3]);
+    Part<R> p = svd_z5<true>(Mg, t1);
+    res.U = cm_of_real(p.U);
+    res.V = cm_diag_real(d1, d2, p.V);
+    s1 = p.s1;
+    s2 = p.s2;
+  } else if (c1 == Z13) {
+    /* permute into [x y; 0 z] (types 7: columns, 14: rows, 11: both), then
+       P_U^T G P_V = D_U [|x| |y|; 0 |z|] D_V^H with D_U = diag(px, pz b2),
+       D_V = diag(1, b2), b2 = px conj(py) */
+    M2<R> PU = m_id<R>(), PV = m_id<R>();
+    if (t1 == 7) PV = m_x<R>();
+    if (t1 == 14) PU = m_x<R>();
+    if (t1 == 11) {
+      PU = m_x<R>();
+      PV = m_x<R>();
+    }
+    /* the positions (row, column) of x, y, z in G' */
+    int rx = (PU.a[0][0] != 0) ? 0 : 1, ry = rx, rz = 1 - rx;
+    int cx_ = (PV.a[0][0] != 0) ? 0 : 1, cy = 1 - cx_, cz = cy;
+    int kx = rx + 2 * cx_, ky = ry + 2 * cy, kz = rz + 2 * cz;
+    Cx<R> b2 = c_mul(ph[kx], c_conj(ph[ky]));
+    Cx<R> a2 = c_mul(ph[kz], b2);
+    TriUV<R> tu = tri_uv(m[kx], m[ky], m[kz]);
+    info |= tu.flags;
+    res.U = real_mul_cm(PU, cm_diag_real(ph[kx], a2, tu.Ub));
+    res.V = real_mul_cm(PV, cm_diag_real(one, b2, tu.Vb));
+    s1 = tu.s1;
+    s2 = tu.s2;
+  } else {
+    /* class 15: column pivoting by the column norms, row phases making the
+       first column real and non-negative, row pivoting, one real rotation by
+       tan(theta) = |g21|/|g11|; T = [w1 r12; 0 r22] with complex r12, r22,
+       T = D_a [w1 |r12|; 0 |r22|] D_b^H, D_a = diag(1, p22 conj(p12)),
+       D_b = diag(1, conj(p12)) */
+    R w1 = cr_hypot(m[0], m[1]), w2 = cr_hypot(m[2], m[3]);
+    bool cswap = w1 < w2;
+    if (cswap) std::swap(w1, w2);
+    int k11 = cswap ? 2 : 0, k21 = cswap ? 3 : 1, k12 = cswap ? 0 : 2, k22 = cswap ? 1 : 3;
+    /* row phases of the first column, applied to the second */
+    Cx<R> q12 = c_mul(c_conj(ph[k11]), h[k12]);
+    Cx<R> q22 = c_mul(c_conj(ph[k21]), h[k22]);
+    R a = m[k11], b = m[k21];
+    bool rswap = a < b;
+    Cx<R> p1 = ph[k11], p2 = ph[k21]; /* D1 = diag(p1, p2) */
+    if (rswap) {
+      std::swap(a, b);
+      std::swap(q12, q22);
+    }
+    R tan_t = b / a;
+    R sec_t = cr_hypot(tan_t, (R)1);
+    Cx<R> r12 = {std::fma(q22.re, tan_t, q12.re) / sec_t, std::fma(q22.im, tan_t, q12.im) / sec_t};
+    Cx<R> r22 = {std::fma(-q12.re, tan_t, q22.re) / sec_t, std::fma(-q12.im, tan_t, q22.im) / sec_t};
+    R m12 = c_abs(r12), m22 = c_abs(r22);
+    Cx<R> p12 = (m12 != 0) ? c_phase(r12) : one;
+    Cx<R> p22 = (m22 != 0) ? c_phase(r22) : one;
+    Cx<R> beta2 = c_conj(p12);
+    Cx<R> alpha2 = (m12 != 0) ? c_mul(p22, beta2) : p22;
+    /* U_+ = D1 P_U U_theta D_a, formed explicitly */
+    M2<R> PU = rswap ? m_x<R>() : m_id<R>();
+    M2<R> W = m_mul(PU, givens<true>(tan_t)); /* P_U U_theta, exact */
+    CM2<R> Up;
+    Cx<R> d[2] = {p1, p2};
+    for (int i = 0; i < 2; ++i) {
+      Up.a[i][0] = c_scale(d[i], W.a[i][0]);
+      Up.a[i][1] = c_mul(c_scale(d[i], W.a[i][1]), alpha2);
+    }
+    M2<R> PV = cswap ? m_x<R>() : m_id<R>();
+    M2<R> Ub, Vb;
+    if (m12 == 0 || m22 == 0) {
+      /* a zero appeared: finished as in Sect. 3.1 */
+      info |= INFO_DEGEN;
+      M2<R> Rpp = {{{w1, m12}, {(R)0, m22}}};
+      int t2 = type_of(Rpp);
+      Part<R> sub = (cls_of(t2) == Z5) ? svd_z5<true>(Rpp, t2) : svd_z9(Rpp, t2);
+      Ub = sub.U;
+      Vb = sub.V;
+      s1 = sub.s1;
+      s2 = sub.s2;
+    } else {
+      TriUV<R> tu = tri_uv(w1, m12, m22);
+      info |= tu.flags;
+      Ub = tu.Ub;
+      Vb = tu.Vb;
+      s1 = tu.s1;
+      s2 = tu.s2;
+    }
+    res.U = cm_mul_real(Up, Ub);
+    res.V = real_mul_cm(PV, cm_diag_real(one, beta2, Vb));
+  }
+  /* backscale (Sect. 3.3.2) */
+  res.s1 = ef_pow2(-s, s1);
+  res.s2 = ef_pow2(-s, s2);
+  res.info = info | ((uint32_t)(uint16_t)(int16_t)s << 16);
+  return res;
+}
+
+/* batch driver: G, U, V are [n][2][2] complex (re, im interleaved, row-major
+   2x2); S [n][2] plain sigma; f [n][2], e [n][2] the (e,f) pairs */
+template <class R>
+static void batch_c(int64_t n, const R *G, R *U, R *S, R *V, R *f, int32_t *e, int32_t *info,
+                    int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t b = 0; b < n; ++b) {
+    const R *x = G + 8 * b;
+    /* row-major (i, j) -> 2 (2 i + j); order g11, g21, g12, g22 */
+    Cx<R> g[4] = {{x[0], x[1]}, {x[4], x[5]}, {x[2], x[3]}, {x[6], x[7]}};
+    CRes<R> r = ksvd2c<R>(g);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        int o = 8 * b + 2 * (2 * i + j);
+        U[o] = r.U.a[i][j].re;
+        U[o + 1] = r.U.a[i][j].im;
+        V[o] = r.V.a[i][j].re;
+        V[o + 1] = r.V.a[i][j].im;
+      }
+    S[2 * b] = ef_fl(r.s1);
+    S[2 * b + 1] = ef_fl(r.s2);
+    if (f) {
+      f[2 * b] = r.s1.f;
+      f[2 * b + 1] = r.s2.f;
+    }
+    if (e) {
+      e[2 * b] = r.s1.e;
+      e[2 * b + 1] = r.s2.e;
+    }
+    if (info) info[b] = (int32_t)r.info;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* 5. Two-sided Kogbetliantz iteration over one n x n matrix (Sect. 1, eq.  */
 /*    (SVD)): in each parallel step the n/2 disjoint pivot submatrices of a  */
 /*    round-robin ordering are diagonalised by the 2x2 SVD above; the        */
@@ -1301,6 +1616,17 @@ int orc_kog_sweep_f32(int n, float *G, float *U, float *V, int max_sweeps, doubl
                       int accumulate, int ordering, int *sweeps_done) {
   return sweep_one<float>(n, G, U, V, max_sweeps, tol_factor, accumulate, ordering,
                           sweeps_done);
+}
+
+/* the complex 2x2 SVD (Sect. 3.4), layouts as batch_c */
+void orc_ksvd2c_f64(int64_t n, const double *G, double *U, double *S, double *V, double *f,
+                    int32_t *e, int32_t *info, int nthreads) {
+  batch_c<double>(n, G, U, S, V, f, e, info, nthreads);
+}
+
+void orc_ksvd2c_f32(int64_t n, const float *G, float *U, float *S, float *V, float *f,
+                    int32_t *e, int32_t *info, int nthreads) {
+  batch_c<float>(n, G, U, S, V, f, e, info, nthreads);
 }
 
 /* the pivot pairs of step k (for the ordering pins): 2 * (n/2) ints, i then j */

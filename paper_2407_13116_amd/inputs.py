@@ -213,3 +213,70 @@ def special_set(dtype=np.float64, seed: int = 11, per_type: int = 4096):
     G = np.concatenate(out)
     # plane order: g11, g21, g12, g22 <-> bits 0, 1, 2, 3 of t
     return tuple(np.ascontiguousarray(G[:, k]) for k in range(4))
+
+
+def complex_batch(dtype=np.complex128, seed: int = 8, B: int = 1 << 22, emax=None):
+    """Complex 2x2 matrices [B,2,2]: real and imaginary parts each +-m 2^e with e
+    uniform in [-emax, emax] (default 20) and m on the p-bit grid; 10% upper
+    triangular, 5% with one zero part per element (purely real or imaginary elements),
+    2% of each single-column / single-row / diagonal pattern, 1% purely real and 1%
+    purely imaginary matrices."""
+    rt = np.float64 if np.dtype(dtype) == np.complex128 else np.float32
+    rng = np.random.default_rng(seed)
+    if emax is None:
+        emax = 20
+    re = signed_pow2_entries(rng, (B, 2, 2), -emax, emax, rt)
+    im = signed_pow2_entries(rng, (B, 2, 2), -emax, emax, rt)
+    u = rng.random(B)
+    tri = u < 0.10
+    re[tri, 1, 0] = 0
+    im[tri, 1, 0] = 0
+    mixed = (u >= 0.10) & (u < 0.15)
+    zr = mixed[:, None, None] & (rng.random((B, 2, 2)) < 0.5)
+    re[zr] = 0
+    zi = mixed[:, None, None] & ~zr
+    im[zi] = 0
+    col = (u >= 0.15) & (u < 0.17)
+    re[col, :, 1] = 0
+    im[col, :, 1] = 0
+    row = (u >= 0.17) & (u < 0.19)
+    re[row, 1, :] = 0
+    im[row, 1, :] = 0
+    dia = (u >= 0.19) & (u < 0.21)
+    re[dia, 0, 1] = re[dia, 1, 0] = 0
+    im[dia, 0, 1] = im[dia, 1, 0] = 0
+    im[(u >= 0.21) & (u < 0.22)] = 0
+    re[(u >= 0.22) & (u < 0.23)] = 0
+    G = np.empty((B, 2, 2), dtype)
+    G.real = re
+    G.imag = im
+    return G
+
+
+def complex_special_set(dtype=np.complex128, seed: int = 12, per_type: int = 1024):
+    """Every zero pattern of the complex elements x the edge magnitudes of the real special
+    set in either part (the other part zero, an edge value or a random value)."""
+    rt = np.float64 if np.dtype(dtype) == np.complex128 else np.float32
+    rng = np.random.default_rng(seed)
+    mags = _edge_magnitudes(rt)
+    out = []
+    for t in range(16):
+        G = np.zeros((per_type, 2, 2), dtype)
+        for k, (i, j) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+            if not (t >> k) & 1:
+                continue
+            parts = []
+            for _ in range(2):
+                pick = rng.integers(0, len(mags) + 3, per_type)
+                vals = np.where(pick < len(mags), mags[np.minimum(pick, len(mags) - 1)],
+                                signed_pow2_entries(rng, per_type, -30, 30, rt))
+                vals = np.where(pick == len(mags) + 2, 0, vals)
+                sgn = np.where(rng.random(per_type) < 0.5, -1, 1)
+                parts.append((sgn * vals).astype(rt))
+            re, im = parts
+            both0 = (re == 0) & (im == 0)
+            re = np.where(both0, mags[0], re).astype(rt)
+            G[:, i, j].real = re
+            G[:, i, j].imag = im
+        out.append(G)
+    return np.concatenate(out)
