@@ -98,6 +98,25 @@ def fwd_case(dtype, steps, warmup, fast=False):
     return res, g, host
 
 
+def complex_case(cdt, steps, warmup):
+    """The complex 2x2 SVD (Sect. 3.4) of the 2^22-matrix complex recipe: U, S, V out
+    (144 / 72 algorithmic bytes per matrix in complex128 / complex64)."""
+    import torch
+
+    from paper_2407_13116_amd import api, inputs
+
+    G = torch.from_numpy(inputs.complex_batch(cdt)).cuda()
+    ms_wall, ms_ev = timed_loop(lambda: api.ksvd2c(G), steps, warmup)
+    B = G.shape[0]
+    per = 144 if cdt == np.complex128 else 72
+    out = {"B": B, "rate": B / (ms_wall * 1e-3), "ms_per_launch": ms_ev,
+           "GBs": B * per / (ms_ev * 1e-3) / 1e9}
+    out["hbm_frac"] = out["GBs"] / HBM_PEAK_GBS
+    del G
+    torch.cuda.empty_cache()
+    return out
+
+
 def fwdbwd_case(dtype, steps, warmup):
     import torch
 
@@ -326,6 +345,9 @@ def main():
                            "GBs": ff["GBs"], "hbm_frac": ff["GBs"] / HBM_PEAK_GBS}
             fast_err[name] = sigma2_error_sample(gf, hf, dt)
             del gf, hf
+        for cdt, name in ((np.complex128, "complex_c128"), (np.complex64, "complex_c64")):
+            log(f"[bench] {name}: complex 2x2 SVD, 2^22 matrices")
+            extra[name] = complex_case(cdt, args.steps, args.warmup)
         for dt, name in ((np.float64, "fwdbwd_f64"), (np.float32, "fwdbwd_f32")):
             log(f"[bench] {name}, 2^22 matrices")
             fb = fwdbwd_case(dt, args.steps, args.warmup)

@@ -115,6 +115,34 @@ int ksvd2_batch_fast_f32(int64_t batch, const float *g11, const float *g21, cons
                          float *s2_plain, void *stream);
 
 /*
+ * ksvd2c_batch -- the complex 2x2 SVD (Sect. 3.4): G = U diag(sigma) V^H for
+ * `batch` complex matrices.  A real G takes the real method above (U, V real);
+ * a purely imaginary G the real method on Im(G), with U multiplied by i.
+ * Otherwise every element that is made real goes through its unit phase g/|g|
+ * into a diagonal phase matrix (the complex counterpart of the sign matrices)
+ * and is replaced by its correctly rounded modulus; the prescaling uses s + 1
+ * for the scale type of every class and the exponents of both parts; the
+ * triangular factor is the real [|r11| |r12|; 0 |r22|] handled by Algorithms
+ * tf and tp; U_+ is formed explicitly; no wider datatype is used (no eq. EXT),
+ * so sigma_2 of a general complex matrix is accurate relative to sigma_1, not
+ * to itself.
+ * Layout: G, U, V are [batch][2][2] complex row-major arrays with the real and
+ * imaginary parts interleaved (element (i,j) of matrix k at 8k + 2(2i + j)),
+ * as complex64 / complex128 tensors store them; S is [batch][2] plain sigma
+ * (sigma_1 >= sigma_2 >= 0, rounded once; may overflow where the (e,f) pair
+ * does not); f, e (nullable) [batch][2] the pairs sigma = f 2^e, f in [1,2);
+ * info (nullable) [batch]: bits 0-3 the type t of the complex zero pattern,
+ * 4-7 t', bits 11-15 as for ksvd2_batch_*, bits 16-31 the prescaling exponent
+ * s (real and imaginary inputs: the real method's info word).  Entries of U and
+ * V that are zero are +0.  Non-finite input: NaN outputs, bit 15, status 0.
+ * dtype: 0 = complex64 (float parts), 1 = complex128 (double parts).  All
+ * pointers are caller-owned device memory aligned to the part type (4 or 8
+ * bytes); status codes as for ksvd2_batch_*.
+ */
+int ksvd2c_batch(int dtype, int64_t batch, const void *G, void *U, void *S, void *V, void *f,
+                 int32_t *e, int32_t *info, void *stream);
+
+/*
  * ksvd2_svd2x2 -- the same SVD in the layout of an autograd graph: G, U, V are
  * [batch,2,2] row-major arrays (element (i,j) of matrix k at 4k + 2i + j), S is
  * [batch,2] with the plain singular values (rounded once to the working

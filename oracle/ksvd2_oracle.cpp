@@ -1258,10 +1258,11 @@ static void batch_c(int64_t n, const R *G, R *U, R *S, R *V, R *f, int32_t *e, i
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j) {
         int o = 8 * b + 2 * (2 * i + j);
-        U[o] = r.U.a[i][j].re;
-        U[o + 1] = r.U.a[i][j].im;
-        V[o] = r.V.a[i][j].re;
-        V[o + 1] = r.V.a[i][j].im;
+        /* canonical zeros: -0 becomes +0 */
+        U[o] = r.U.a[i][j].re + (R)0;
+        U[o + 1] = r.U.a[i][j].im + (R)0;
+        V[o] = r.V.a[i][j].re + (R)0;
+        V[o + 1] = r.V.a[i][j].im + (R)0;
       }
     S[2 * b] = ef_fl(r.s1);
     S[2 * b + 1] = ef_fl(r.s2);

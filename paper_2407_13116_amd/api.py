@@ -115,6 +115,33 @@ def hypot(x, y, fast: bool = False):
     return out
 
 
+def ksvd2c(G, with_pairs: bool = False):
+    """Complex 2x2 SVD (Sect. 3.4): G [B,2,2] complex64/complex128 on the GPU ->
+    (U [B,2,2], S [B,2] real, V [B,2,2]) with G = U diag(S) V^H; with ``with_pairs``
+    also (f [B,2], e [B,2] int32, info [B] int32), sigma = f 2^e.  See ksvd2c_batch."""
+    if not isinstance(G, torch.Tensor) or not G.is_cuda:
+        raise _lib.KSVD2Error("ksvd2c: G must be a CUDA tensor (no CPU fallback)")
+    if G.dtype not in (torch.complex64, torch.complex128):
+        raise _lib.KSVD2Error("ksvd2c: G must be complex64 or complex128")
+    if G.dim() != 3 or G.shape[1:] != (2, 2):
+        raise _lib.KSVD2Error("ksvd2c: G must have shape [B,2,2]")
+    G = G.contiguous()
+    rt = torch.float64 if G.dtype == torch.complex128 else torch.float32
+    B = G.shape[0]
+    U = torch.empty_like(G)
+    V = torch.empty_like(G)
+    S = torch.empty((B, 2), dtype=rt, device=G.device)
+    f = e = info = None
+    if with_pairs:
+        f = torch.empty((B, 2), dtype=rt, device=G.device)
+        e = torch.empty((B, 2), dtype=torch.int32, device=G.device)
+        info = torch.empty(B, dtype=torch.int32, device=G.device)
+    rc = _lib.lib().ksvd2c_batch(1 if rt == torch.float64 else 0, B, _ptr(G), _ptr(U), _ptr(S),
+                                 _ptr(V), _ptr(f), _ptr(e), _ptr(info), _stream())
+    _lib.check(rc, "ksvd2c_batch")
+    return (U, S, V, f, e, info) if with_pairs else (U, S, V)
+
+
 class SVD2x2(torch.autograd.Function):
     """G [B,2,2] -> (U, S, V) with G = U diag(S) V^T; backward by the adjoint kernel.
 

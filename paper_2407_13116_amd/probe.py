@@ -10,6 +10,7 @@ python -m paper_2407_13116_amd.probe --workload NAME [--reps K]
                     in [-20,20]): no lane divergence between classes, so the per-wave VALU
                     instruction count is the per-matrix path length of that class
   bwd64 / bwd32     the 2^22-matrix backward (k_bwd)
+  cplx128 / cplx64  the 2^22-matrix complex 2x2 SVD (k_fwd_c)
   copy              a plain 1 GiB device-to-device copy (counter calibration: FETCH_SIZE
                     and WRITE_SIZE should each read 1 GiB)
   sweep4            one persistent sweep of the 256 x (n=256) FP64 workload
@@ -64,6 +65,11 @@ def main(argv=None):
         U, S, V = api.svd2x2_raw(t[0])
         for _ in range(reps):
             api.svd2x2_backward(U, S, V, t[1], t[2], t[3])
+    elif w in ("cplx128", "cplx64"):
+        G = torch.from_numpy(inputs.complex_batch(np.complex128 if w == "cplx128"
+                                                  else np.complex64)).cuda()
+        for _ in range(reps + 1):
+            api.ksvd2c(G)
     elif w == "copy":
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
