@@ -168,7 +168,8 @@ def sigma2_error_sample(g, host, dtype, n=1500):
 
 
 def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=60, tune=True):
-    """Time one converged solve of a batch of square matrices per execution mode (the
+    """Time one converged solve of a batch of square matrices per execution mode, with the
+    modified modulus ordering, and once with the round-robin ordering (the
     matrices are re-uploaded untimed before every run).  Effective bytes: every step reads
     and writes G, U and V once, 6 n^2 w per matrix per step."""
     import torch
@@ -204,19 +205,19 @@ def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=6
                      "matrices_per_s": len(mats) / times[-1]}
         log(f"[bench] sweep {mode}: {res[mode]}")
     if "persistent" in modes:
-        # the same solve with the modified modulus ordering (persistent mode)
+        # the same solve with the round-robin ordering (persistent mode)
         p.G.copy_(G0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         o2 = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode="persistent",
-                                workspace=ws, sort=True, ordering="modulus")
+                                workspace=ws, sort=True, ordering="round-robin")
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         s2 = np.abs(o2["sweeps"].cpu().numpy()).astype(np.int64)
-        res["persistent_modulus_ordering"] = {
+        res["persistent_round_robin_ordering"] = {
             "seconds": t, "sweeps_mean": float(s2.mean()), "sweeps_max": int(s2.max()),
             "converged": bool(np.all(o2["sweeps"].cpu().numpy() > 0))}
-        log(f"[bench] sweep persistent, modified modulus: {res['persistent_modulus_ordering']}")
+        log(f"[bench] sweep persistent, round-robin: {res['persistent_round_robin_ordering']}")
         p.G.copy_(G0)
         out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode="persistent",
                                  workspace=ws, sort=True)

@@ -185,9 +185,9 @@ def full_uv(out):
 
 
 def kog_sweep(G, max_sweeps: int = 30, tol_factor: float = 1.0, U=None, V=None,
-              ordering: int = 0):
-    """Two-sided Kogbetliantz iteration on one n x n matrix (parallel ordering 0 =
-    round-robin, 1 = modified modulus).  G is taken column-major (pass a
+              ordering: int = 1):
+    """Two-sided Kogbetliantz iteration on one n x n matrix (parallel ordering 1 =
+    modified modulus, the default, or 0 = round-robin).  G is taken column-major (pass a
     Fortran-ordered or transposed array); returns (G_out, U, V, status, sweeps) with
     the arrays column-major.  tol_factor < 0 disables the stopping test (exactly
     max_sweeps sweeps)."""

@@ -51,10 +51,11 @@ def workspace_bytes(dtype, n):
 
 def kog_sweep_batch(packed: Packed, max_sweeps: int = 30, tol_factor: float = 1.0,
                     mode: str | int = "persistent", U=None, V=None, workspace=None,
-                    sort: bool = False, ordering: str | int = "round-robin"):
+                    sort: bool = False, ordering: str | int = "modulus"):
     """Run the sweep in place on packed.G.  Returns dict(G, U, V, sigma, sweeps).
 
-    ``ordering``: "round-robin" (0) or "modulus" (1, the modified modulus strategy).
+    ``ordering``: "modulus" (1, the modified modulus strategy; the default: on the
+    benchmark batches it needs 2 to 2.5 times fewer sweeps) or "round-robin" (0).
     ``U``/``V`` given => accumulate (continue from them).  ``sort`` => sigma in
     descending order with the columns of U and V permuted to match (kog_sweep_sort);
     G stays the iterate, so resume only from unsorted U and V."""

@@ -13,9 +13,10 @@
   differences of sorted sigma through the GPU sweep.
 * Resuming (accumulate): 1 + 1 sweeps equal 2 sweeps bitwise; edge cases (order 2,
   diagonal and zero matrices).
-* The modified modulus ordering: bit for bit against the oracle's sweep with the same
-  ordering, every mode, orders 2 .. 260 (several U/V tiles); converged runs of both
-  orderings reach LAPACK's singular values.
+* Orderings: every case above runs the default modified modulus ordering; the
+  round-robin ordering bit for bit against the oracle's sweep with that ordering, every
+  mode, orders 2 .. 260 (several U/V tiles); converged runs of both orderings reach
+  LAPACK's singular values.
 """
 import numpy as np
 import pytest
@@ -33,7 +34,7 @@ def _mats(rng, ns, dtype, emax=3):
             for n in ns]
 
 
-def _run(mats, dtype, mode, max_sweeps, tolf, ordering="round-robin"):
+def _run(mats, dtype, mode, max_sweeps, tolf, ordering="modulus"):
     import torch
 
     from paper_2407_13116_amd import sweep as sw
@@ -335,14 +336,14 @@ def test_global_scaling_bitwise_vs_oracle(orc, dtype, mode):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("mode", MODES)
-def test_modulus_ordering_bitwise_vs_oracle(orc, dtype, mode):
+def test_round_robin_ordering_bitwise_vs_oracle(orc, dtype, mode):
     rng = np.random.default_rng(24)
     ns = [2, 4, 6, 10, 16, 34, 66, 8, 130, 260]
     mats = _mats(rng, ns, dtype)
-    p, got = _run(mats, dtype, mode, max_sweeps=2, tolf=-1.0, ordering="modulus")
+    p, got = _run(mats, dtype, mode, max_sweeps=2, tolf=-1.0, ordering="round-robin")
     assert list(got["sweeps"]) == [-2] * len(ns)
     for k, G0 in enumerate(mats):
-        G, U, V, st, swp = orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0, ordering=1)
+        G, U, V, st, swp = orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0, ordering=0)
         assert (st, swp) == (1, 2)
         assert _same(got["G"][k], G), (mode, k, ns[k], "G")
         assert _same(got["U"][k], U), (mode, k, ns[k], "U")
