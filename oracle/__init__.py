@@ -72,6 +72,9 @@ def lib():
             fn.restype = i32
             fn.argtypes = [i32, p, p, p, i32, d, i32, i32, ctypes.POINTER(i32)]
         L.orc_step_pairs.argtypes = [i32, i32, i32, p]
+        for t in ("f64", "f32"):
+            getattr(L, "orc_qrcp_" + t).argtypes = [i32, i32, p, p, p, p]
+            getattr(L, "orc_qapply_" + t).argtypes = [i32, i32, p, p, p, p, p, p, p]
         for name in ("orc_ksvd2c_f64", "orc_ksvd2c_f32"):
             getattr(L, name).argtypes = [i64, p, p, p, p, p, p, p, i32]
         _lib = L
@@ -225,6 +228,44 @@ def ksvd2c(G, nthreads: int = 0):
     fn = getattr(lib(), "orc_ksvd2c_" + _dt(rt))
     fn(B, _ptr(G), _ptr(U), _ptr(S), _ptr(V), _ptr(f), _ptr(e), _ptr(info), int(nthreads))
     return {"U": U, "V": V, "S": S, "f": f, "e": e, "info": info}
+
+
+def qrcp(G):
+    """QR with column pivoting of an m x n matrix (m >= n), Householder form:
+    returns (A, tau, perm, R) with A holding the reflectors below the diagonal and R on
+    and above (column-major), G[:, perm] = Q R, R the n x n triangular factor."""
+    A = np.array(G, order="F", copy=True)
+    m, n = A.shape
+    tau = np.empty(n, A.dtype)
+    perm = np.empty(n, np.int32)
+    Rsq = np.empty((n, n), A.dtype, order="F")
+    getattr(lib(), "orc_qrcp_" + _dt(A.dtype))(m, n, _ptr(A), _ptr(tau), _ptr(perm), _ptr(Rsq))
+    return A, tau, perm, Rsq
+
+
+def qapply(A, tau, perm, UR, VR):
+    """U = Q [U_R; 0] (m x n) and V = P V_R from qrcp's output and the SVD of R."""
+    m, n = A.shape
+    A = np.asfortranarray(A)
+    UR = np.asfortranarray(UR, dtype=A.dtype)
+    VR = np.asfortranarray(VR, dtype=A.dtype)
+    U = np.empty((m, n), A.dtype, order="F")
+    V = np.empty((n, n), A.dtype, order="F")
+    getattr(lib(), "orc_qapply_" + _dt(A.dtype))(m, n, _ptr(A), _ptr(np.ascontiguousarray(tau)),
+                                                _ptr(np.ascontiguousarray(perm, np.int32)),
+                                                _ptr(UR), _ptr(VR), _ptr(U), _ptr(V))
+    return U, V
+
+
+def svd_rect(G, max_sweeps: int = 40, tol_factor: float = 1.0, ordering: int = 1):
+    """SVD of an m x n matrix (m >= n, n even): QR with column pivoting, the sweep on
+    R, then U = Q [U_R; 0], V = P V_R.  Returns (U, sigma, V, sweeps), sigma unsorted
+    as the sweep leaves it."""
+    A, tau, perm, Rsq = qrcp(G)
+    Gk, UR, VR, st, sw = kog_sweep(Rsq, max_sweeps=max_sweeps, tol_factor=tol_factor,
+                                   ordering=ordering)
+    U, V = qapply(A, tau, perm, UR, VR)
+    return U, np.diag(Gk).copy(), V, (sw if st == 0 else -sw)
 
 
 def step_pairs(ordering: int, n: int, k: int):

@@ -24,6 +24,7 @@
  *      assembly with the left-vector heuristic (Sect. 3.3.2)
  *   4b. the complex 2x2 SVD (Sect. 3.4)
  *   5. the Kogbetliantz sweep over an n x n matrix (Sect. 1, eq. (SVD))
+ *   5b. rectangular inputs: QR with column pivoting before, Q after the sweep
  *   6. extern "C" batch drivers (OpenMP) for the test-suite
  */
 #include <algorithm>
@@ -1467,6 +1468,84 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
 }  // namespace
 
 /* ------------------------------------------------------------------------ */
+/* 5b. Rectangular m x n inputs, m >= n (Sect. 1: preprocessed to a square  */
+/*    triangular G_0 = U_0^T G V_0 by a URV-type factorization, the QR      */
+/*    factorization with column pivoting).  Householder reflections         */
+/*    H_k = I - tau_k v_k v_k^T (v_k(k) = 1), the pivot the trailing column */
+/*    of largest norm (the first such on ties), the norms recomputed at     */
+/*    every step.  G P = Q R; after the sweep R = U_R Sigma V_R^T,          */
+/*    U = Q [U_R; 0] and V = P V_R.  Column-major arrays.                   */
+/* ------------------------------------------------------------------------ */
+template <class R>
+static void qrcp_one(int m, int n, R *A, R *tau, int32_t *perm, R *Rsq) {
+  auto a = [&](int i, int j) -> R & { return A[i + (int64_t)j * m]; };
+  for (int j = 0; j < n; ++j) perm[j] = j;
+  for (int k = 0; k < n; ++k) {
+    /* pivot: the largest squared norm of the trailing columns (rows k..m-1) */
+    int p = k;
+    R best = (R)-1;
+    for (int j = k; j < n; ++j) {
+      R s = 0;
+      for (int i = k; i < m; ++i) s += a(i, j) * a(i, j);
+      if (s > best) {
+        best = s;
+        p = j;
+      }
+    }
+    if (p != k) {
+      for (int i = 0; i < m; ++i) std::swap(a(i, k), a(i, p));
+      std::swap(perm[k], perm[p]);
+    }
+    /* the reflection that maps column k (rows k..m-1) onto beta e_k */
+    R x0 = a(k, k), s = 0;
+    for (int i = k + 1; i < m; ++i) s += a(i, k) * a(i, k);
+    if (s == 0) {
+      tau[k] = 0;
+      continue;
+    }
+    R nrm = std::sqrt(x0 * x0 + s);
+    R beta = x0 >= 0 ? -nrm : nrm;
+    tau[k] = (beta - x0) / beta;
+    R scal = (R)1 / (x0 - beta);
+    for (int i = k + 1; i < m; ++i) a(i, k) *= scal;
+    a(k, k) = beta;
+    /* H_k on the trailing columns */
+    for (int j = k + 1; j < n; ++j) {
+      R w = a(k, j);
+      for (int i = k + 1; i < m; ++i) w += a(i, k) * a(i, j);
+      R tw = tau[k] * w;
+      a(k, j) -= tw;
+      for (int i = k + 1; i < m; ++i) a(i, j) -= tw * a(i, k);
+    }
+  }
+  /* the n x n triangular factor, zeros below the diagonal */
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) Rsq[i + (int64_t)j * n] = (i <= j) ? a(i, j) : (R)0;
+}
+
+/* U = H_0 ... H_{n-1} [U_R; 0] (m x n) and V = P V_R (n x n) */
+template <class R>
+static void qapply_one(int m, int n, const R *A, const R *tau, const int32_t *perm, const R *UR,
+                       const R *VR, R *U, R *V) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < m; ++i) U[i + (int64_t)j * m] = (i < n) ? UR[i + (int64_t)j * n] : (R)0;
+  for (int k = n - 1; k >= 0; --k) {
+    if (tau[k] == 0) continue;
+    for (int j = 0; j < n; ++j) {
+      R *u = U + (int64_t)j * m;
+      const R *v = A + (int64_t)k * m;
+      R w = u[k];
+      for (int i = k + 1; i < m; ++i) w += v[i] * u[i];
+      R tw = tau[k] * w;
+      u[k] -= tw;
+      for (int i = k + 1; i < m; ++i) u[i] -= tw * v[i];
+    }
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) V[perm[i] + (int64_t)j * n] = VR[i + (int64_t)j * n];
+}
+
+/* ------------------------------------------------------------------------ */
 /* 6. extern "C" entry points used by the test-suite (via ctypes).           */
 /* ------------------------------------------------------------------------ */
 extern "C" {
@@ -1617,6 +1696,24 @@ int orc_kog_sweep_f32(int n, float *G, float *U, float *V, int max_sweeps, doubl
                       int accumulate, int ordering, int *sweeps_done) {
   return sweep_one<float>(n, G, U, V, max_sweeps, tol_factor, accumulate, ordering,
                           sweeps_done);
+}
+
+/* QR with column pivoting of one m x n column-major matrix (in place:
+   reflectors below the diagonal, R on and above), tau[n], perm[n], and the
+   n x n triangular factor */
+void orc_qrcp_f64(int m, int n, double *A, double *tau, int32_t *perm, double *Rsq) {
+  qrcp_one<double>(m, n, A, tau, perm, Rsq);
+}
+void orc_qrcp_f32(int m, int n, float *A, float *tau, int32_t *perm, float *Rsq) {
+  qrcp_one<float>(m, n, A, tau, perm, Rsq);
+}
+void orc_qapply_f64(int m, int n, const double *A, const double *tau, const int32_t *perm,
+                    const double *UR, const double *VR, double *U, double *V) {
+  qapply_one<double>(m, n, A, tau, perm, UR, VR, U, V);
+}
+void orc_qapply_f32(int m, int n, const float *A, const float *tau, const int32_t *perm,
+                    const float *UR, const float *VR, float *U, float *V) {
+  qapply_one<float>(m, n, A, tau, perm, UR, VR, U, V);
 }
 
 /* the complex 2x2 SVD (Sect. 3.4), layouts as batch_c */
