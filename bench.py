@@ -117,6 +117,32 @@ def complex_case(cdt, steps, warmup):
     return out
 
 
+def rect_case(dtype):
+    """Rectangular inputs (Sect. 1): 256 tall 512 x 256 matrices, QR with column pivoting,
+    the converged sweep on the triangular factors (persistent, modified modulus ordering,
+    sorted), then U = Q [U_R; 0] and V = P V_R; one timed run after an untimed one."""
+    import torch
+
+    from paper_2407_13116_amd import inputs
+    from paper_2407_13116_amd import sweep as sw
+
+    pr = sw.PackedRect(inputs.rect_batch(dtype=dtype), dtype=dtype)
+    sw.svd_rect_device(pr)
+    pr.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = sw.svd_rect_device(pr)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s = np.abs(out["sweeps"].cpu().numpy())
+    res = {"matrices": len(pr.m), "shape": [int(pr.m[0]), int(pr.n[0])], "seconds": t,
+           "matrices_per_s": len(pr.m) / t, "sweeps_mean": float(s.mean()),
+           "converged": bool(np.all(out["sweeps"].cpu().numpy() > 0))}
+    del pr, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def fwdbwd_case(dtype, steps, warmup):
     import torch
 
@@ -361,6 +387,9 @@ def main():
         for dt, name in ((np.float64, "sweep_uneven_f64"), (np.float32, "sweep_uneven_f32")):
             log(f"[bench] sweep: 1,000 uneven orders, {name}")
             extra[name] = sweep_case(_inp.sweep_uneven(dtype=dt), dt)
+        log("[bench] rectangular: 256 x (512 x 256) FP64")
+        extra["rect_f64"] = rect_case(np.float64)
+        log(f"[bench] rect: {extra['rect_f64']}")
         log("[bench] sigma_2 accuracy sample")
         extra["max_rel_err_sigma2_ulp"] = {"f64": sigma2_error_sample(g64, h64, np.float64),
                                            "f32": sigma2_error_sample(g32, h32, np.float32),

@@ -261,6 +261,45 @@ int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_
 int kog_sweep_sort(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
                    void *U, void *V, void *sigma, void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Rectangular inputs (Sect. 1): an m x n matrix with m >= n is reduced to a
+ * square triangular one by the QR factorization with column pivoting, G P =
+ * Q R; kog_sweep_batch then takes R (n even) and kog_qrcp_apply forms the
+ * factors of G, U = Q [U_R; 0] (m x n, orthonormal columns) and V = P V_R.
+ * (For m < n, factor G^T.)
+ *
+ * kog_qrcp_batch -- in place on A (matrix k column-major m_k x n_k at element
+ * offset aoff_host[k]; 1 <= n_k <= 4096, m_k >= n_k): Householder reflections
+ * H_j = I - tau_j v_j v_j^T with v_j(j) = 1, v_j stored below the diagonal of
+ * column j and R on and above it (the layout of LAPACK's geqp3).  At step j
+ * the trailing column of largest norm (rows j..m-1, recomputed at every step;
+ * the first one on ties) is exchanged into place; the reflector maps it onto
+ * beta e_j with beta = -sign(x_j) ||x||.  tau and perm are packed by matrix
+ * at n_0 + ... + n_{k-1}; perm[j] is the column of G that became column j of
+ * G P.  Rsq receives the n_k x n_k triangular factor, zeros below the diagonal,
+ * column-major at element offset roff_host[k] (ready for kog_sweep_batch).
+ * Entries must keep the squared column norms finite.
+ *
+ * kog_qrcp_apply -- from kog_qrcp_batch's A, tau, perm and the SVD factors
+ * U_R, V_R of R (n_k x n_k at roff_host[k], e.g. from kog_sweep_batch and
+ * kog_sweep_sort), writes U = H_0 ... H_{n-1} [U_R; 0] (m_k x n_k at
+ * aoff_host[k] of U) and V = P V_R (n_k x n_k at roff_host[k] of V).  perm must
+ * be the one kog_qrcp_batch wrote.
+ *
+ * Both: m_host, n_host, aoff_host, roff_host are host arrays of nmat entries
+ * (at most 65535 matrices); every other pointer is caller-owned device memory;
+ * workspace: at least kog_rect_workspace_size(nmat) bytes, 256-byte aligned;
+ * stream-ordered; status codes as above.
+ */
+size_t kog_rect_workspace_size(int64_t nmat);
+int kog_qrcp_batch(int dtype, int64_t nmat, const int32_t *m_host, const int32_t *n_host,
+                   const int64_t *aoff_host, const int64_t *roff_host, void *A, void *tau,
+                   int32_t *perm, void *Rsq, void *workspace, size_t ws_bytes, void *stream);
+int kog_qrcp_apply(int dtype, int64_t nmat, const int32_t *m_host, const int32_t *n_host,
+                   const int64_t *aoff_host, const int64_t *roff_host, const void *A,
+                   const void *tau, const int32_t *perm, const void *UR, const void *VR, void *U,
+                   void *V, void *workspace, size_t ws_bytes, void *stream);
+
 /* Bytes of workspace kog_sweep_batch and kog_sigma_grad need for this batch
    (0 for invalid arguments). */
 size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);

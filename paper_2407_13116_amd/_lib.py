@@ -56,6 +56,13 @@ def lib():
             L.kog_sigma_grad.argtypes = [i32, i64, p, p, p, p, p, p, p, ctypes.c_size_t, p]
             L.kog_sweep_sort.restype = i32
             L.kog_sweep_sort.argtypes = [i32, i64, p, p, p, p, p, p, ctypes.c_size_t, p]
+            L.kog_rect_workspace_size.restype = ctypes.c_size_t
+            L.kog_rect_workspace_size.argtypes = [i64]
+            L.kog_qrcp_batch.restype = i32
+            L.kog_qrcp_batch.argtypes = [i32, i64, p, p, p, p, p, p, p, p, p, ctypes.c_size_t, p]
+            L.kog_qrcp_apply.restype = i32
+            L.kog_qrcp_apply.argtypes = [i32, i64, p, p, p, p, p, p, p, p, p, p, p, p,
+                                         ctypes.c_size_t, p]
             L.kog_sweep_tune.restype = i32
             L.kog_sweep_tune.argtypes = [i32, i32, i32]
         _lib = L

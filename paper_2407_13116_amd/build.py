@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libksvd2.so")
-SOURCES = ["ksvd2_kernels.hip", "kog_sweep.hip", "ksvd2c.hip"]
+SOURCES = ["ksvd2_kernels.hip", "kog_sweep.hip", "ksvd2c.hip", "kog_rect.hip"]
 ARCH = os.environ.get("KSVD2_ARCH", "gfx950")
 
 FLAGS = [

@@ -11,6 +11,7 @@ python -m paper_2407_13116_amd.probe --workload NAME [--reps K]
                     instruction count is the per-matrix path length of that class
   bwd64 / bwd32     the 2^22-matrix backward (k_bwd)
   cplx128 / cplx64  the 2^22-matrix complex 2x2 SVD (k_fwd_c)
+  rect64            256 tall 512 x 256 FP64 matrices: k_qrcp, the sweep, k_qapply
   copy              a plain 1 GiB device-to-device copy (counter calibration: FETCH_SIZE
                     and WRITE_SIZE should each read 1 GiB)
   sweep4            one persistent sweep of the 256 x (n=256) FP64 workload
@@ -70,6 +71,13 @@ def main(argv=None):
                                                   else np.complex64)).cuda()
         for _ in range(reps + 1):
             api.ksvd2c(G)
+    elif w == "rect64":
+        from . import sweep as sw
+
+        pr = sw.PackedRect(inputs.rect_batch(), dtype=np.float64)
+        for _ in range(reps):
+            pr.reset()
+            sw.svd_rect_device(pr)
     elif w == "copy":
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -135,5 +135,74 @@ def sigma_grad(packed: Packed, U, V, dsigma, workspace=None):
     return dG
 
 
+class PackedRect:
+    """m x n matrices (m >= n) packed column-major into one flat device tensor, with the
+    n x n buffers (offsets roff) their triangular factors and V use."""
+
+    def __init__(self, mats, dtype=None, device="cuda"):
+        mats = [np.asarray(x) for x in mats]
+        dtype = dtype or mats[0].dtype
+        self.m = np.array([x.shape[0] for x in mats], dtype=np.int32)
+        self.n = np.array([x.shape[1] for x in mats], dtype=np.int32)
+        self.aoff = np.concatenate([[0], np.cumsum(self.m.astype(np.int64) * self.n)[:-1]]
+                                   ).astype(np.int64)
+        self.A = torch.from_numpy(np.concatenate([np.asarray(x, dtype=dtype).ravel(order="F")
+                                                  for x in mats])).to(device)
+        self.R = Packed([np.zeros((k, k), dtype) for k in self.n], dtype=dtype, device=device)
+        self.roff = self.R.off
+        self.A0 = self.A.clone()
+
+    def reset(self):
+        self.A.copy_(self.A0)
+
+
+def svd_rect_device(pr: PackedRect, max_sweeps: int = 40, tol_factor: float = 1.0,
+                    mode="persistent", ordering="modulus", sort: bool = True):
+    """kog_qrcp_batch, the sweep on the triangular factors (kog_sweep_sort when ``sort``)
+    and kog_qrcp_apply on a PackedRect (its A is overwritten by the reflectors).
+    Returns dict(U, V, sigma, sweeps) of device tensors (U in A's layout, V in R's)."""
+    L = _lib.lib()
+    dev = pr.A.device
+    ntot = int(pr.n.sum())
+    tau = torch.empty(ntot, dtype=pr.A.dtype, device=dev)
+    perm = torch.empty(ntot, dtype=torch.int32, device=dev)
+    wsz = int(L.kog_rect_workspace_size(len(pr.m)))
+    ws = torch.empty(wsz + 256, dtype=torch.uint8, device=dev)
+    pad = (-ws.data_ptr()) % 256
+    st = torch.cuda.current_stream().cuda_stream or None
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    dt = _DT[pr.A.dtype]
+    m, n, aoff, roff = (np.ascontiguousarray(x) for x in (pr.m, pr.n, pr.aoff, pr.roff))
+    rc = L.kog_qrcp_batch(dt, len(m), ptr(m), ptr(n), ptr(aoff), ptr(roff), pr.A.data_ptr(),
+                          tau.data_ptr(), perm.data_ptr(), pr.R.G.data_ptr(),
+                          ws.data_ptr() + pad, wsz, st)
+    _lib.check(rc, "kog_qrcp_batch")
+    out = kog_sweep_batch(pr.R, max_sweeps=max_sweeps, tol_factor=tol_factor, mode=mode,
+                          sort=sort, ordering=ordering)
+    U = torch.empty_like(pr.A)
+    V = torch.empty_like(pr.R.G)
+    rc = L.kog_qrcp_apply(dt, len(m), ptr(m), ptr(n), ptr(aoff), ptr(roff), pr.A.data_ptr(),
+                          tau.data_ptr(), perm.data_ptr(), out["U"].data_ptr(),
+                          out["V"].data_ptr(), U.data_ptr(), V.data_ptr(), ws.data_ptr() + pad,
+                          wsz, st)
+    _lib.check(rc, "kog_qrcp_apply")
+    return {"U": U, "V": V, "sigma": out["sigma"], "sweeps": out["sweeps"]}
+
+
+def svd_rect(mats, max_sweeps: int = 40, tol_factor: float = 1.0, mode="persistent",
+             ordering="modulus", sort: bool = True, dtype=None, device="cuda"):
+    """SVD of m x n matrices (m >= n, n even; Sect. 1) through svd_rect_device.
+    Returns a list of (U [m,n], sigma [n], V [n,n]) numpy triples and the sweep counts.
+    For m < n pass the transposes."""
+    pr = PackedRect(mats, dtype=dtype, device=device)
+    out = svd_rect_device(pr, max_sweeps, tol_factor, mode, ordering, sort)
+    Uh = out["U"].cpu().numpy()
+    Vs = pr.R.unpack(out["V"])
+    sig = pr.R.unpack_sigma(out["sigma"])
+    res = [(Uh[o:o + mm * nn].reshape((mm, nn), order="F"), sig[k], Vs[k])
+           for k, (o, mm, nn) in enumerate(zip(pr.aoff, pr.m, pr.n))]
+    return res, out["sweeps"].cpu().numpy()
+
+
 def set_tuning(dtype, bucket: int, block: int):
     _lib.check(_lib.lib().kog_sweep_tune(_DT[dtype], bucket, block), "kog_sweep_tune")

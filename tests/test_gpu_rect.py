@@ -1,0 +1,114 @@
+"""GPU rectangular path (Sect. 1): QR with column pivoting, the sweep on R, U = Q [U_R; 0],
+V = P V_R, against the oracle and LAPACK.
+
+The device reduces over rows with a lane tree and the oracle sequentially, so the
+factorization is compared within a rounding tolerance, not bit for bit: the same pivot
+order, R and the reflectors within c m eps ||G||.  The whole SVD is checked through
+properties that hold at any size: LAPACK's singular values (sorted, descending),
+orthonormal columns of U, orthogonal V, G = U Sigma V^T.  Shapes: square and tall, odd
+and even m, n from 2 to 256 in one uneven batch, both precisions; argument errors.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+DT = [np.float64, np.float32]
+
+
+def _eps(dt):
+    return 2.0 ** (-53 if dt == np.float64 else -24)
+
+
+def _batch(dt, seed=3):
+    rng = np.random.default_rng(seed)
+    shapes = [(2, 2), (5, 2), (40, 10), (64, 64), (100, 64), (129, 128), (300, 256), (17, 16)]
+    return [(rng.standard_normal(s) * np.exp2(rng.integers(-3, 4, s[1]))).astype(dt)
+            for s in shapes]
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_qrcp_vs_oracle(orc, dt):
+    import ctypes
+
+    import torch
+
+    from paper_2407_13116_amd import _lib
+    from paper_2407_13116_amd import sweep as sw
+
+    mats = _batch(dt)
+    L = _lib.lib()
+    m = np.array([x.shape[0] for x in mats], np.int32)
+    n = np.array([x.shape[1] for x in mats], np.int32)
+    aoff = np.concatenate([[0], np.cumsum(m.astype(np.int64) * n)[:-1]]).astype(np.int64)
+    A = torch.from_numpy(np.concatenate([x.ravel(order="F") for x in mats])).cuda()
+    R = sw.Packed([np.zeros((k, k), dt) for k in n], dtype=dt)
+    tau = torch.empty(int(n.sum()), dtype=A.dtype, device="cuda")
+    perm = torch.empty(int(n.sum()), dtype=torch.int32, device="cuda")
+    wsz = int(L.kog_rect_workspace_size(len(m)))
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = L.kog_qrcp_batch(1 if dt == np.float64 else 0, len(m), ptr(m), ptr(n), ptr(aoff),
+                          ptr(R.off), A.data_ptr(), tau.data_ptr(), perm.data_ptr(),
+                          R.G.data_ptr(), ws.data_ptr(), wsz, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    Ah, th, ph = A.cpu().numpy(), tau.cpu().numpy(), perm.cpu().numpy()
+    Rs = R.unpack(R.G)
+    t0 = 0
+    for k, G in enumerate(mats):
+        mm, nn = G.shape
+        Ao, to, po, Ro = orc.qrcp(G)
+        Ag = Ah[aoff[k]:aoff[k] + mm * nn].reshape((mm, nn), order="F")
+        tol = 16 * mm * _eps(dt) * float(np.linalg.norm(G.astype(np.float64)))
+        assert np.array_equal(ph[t0:t0 + nn], po), k
+        assert np.abs(Rs[k].astype(np.float64) - Ro).max() <= tol, k
+        # reflectors (unit-scaled entries) and tau
+        assert np.abs(np.tril(Ag, -1) - np.tril(Ao, -1)).max() <= 16 * mm * _eps(dt) * 64, k
+        assert np.abs(th[t0:t0 + nn] - to).max() <= 16 * mm * _eps(dt), k
+        t0 += nn
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("mode", ["persistent", "plain"])
+def test_rect_svd_properties(dt, mode):
+    from paper_2407_13116_amd import sweep as sw
+
+    mats = _batch(dt, seed=4)
+    res, sweeps = sw.svd_rect(mats, mode=mode)
+    assert np.all(sweeps > 0)
+    e = _eps(dt)
+    for G, (U, s, V) in zip(mats, res):
+        mm, nn = G.shape
+        Gd = G.astype(np.float64)
+        ref = np.linalg.svd(Gd, compute_uv=False)
+        sd = s.astype(np.float64)
+        assert np.all(sd[:-1] >= sd[1:])
+        assert np.abs(sd - ref).max() <= 40 * mm * e * ref[0]
+        Ud, Vd = U.astype(np.float64), V.astype(np.float64)
+        assert np.abs(Ud.T @ Ud - np.eye(nn)).max() <= 40 * mm * e
+        assert np.abs(Vd.T @ Vd - np.eye(nn)).max() <= 40 * nn * e
+        assert np.abs(Ud @ np.diag(sd) @ Vd.T - Gd).max() <= 40 * mm * e * np.linalg.norm(Gd)
+
+
+def test_rect_arguments_rejected():
+    import ctypes
+
+    import torch
+
+    from paper_2407_13116_amd import _lib
+
+    L = _lib.lib()
+    m = np.array([3], np.int32)
+    n = np.array([4], np.int32)                      # m < n
+    off = np.zeros(1, np.int64)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    buf = torch.empty(64, dtype=torch.float64, device="cuda")
+    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    p = buf.data_ptr()
+    rc = L.kog_qrcp_batch(1, 1, ptr(m), ptr(n), ptr(off), ptr(off), p, p, p, p, ws.data_ptr(),
+                          4096, None)
+    assert rc == -1 and b"m >= n" in L.ksvd2_last_error()
+    m2 = np.array([8], np.int32)
+    rc = L.kog_qrcp_batch(1, 1, ptr(m2), ptr(n), ptr(off), ptr(off), p, p, p, p, ws.data_ptr(),
+                          16, None)
+    assert rc == -4
