@@ -7,10 +7,10 @@
 //
 // One workgroup per matrix factorizes it in place (Householder reflections
 // H_k = I - tau_k v_k v_k^T, v_k(k) = 1, stored below the diagonal as LAPACK's
-// geqp3 does): per column the trailing column norms, the pivot (largest norm,
-// the first on ties), the column exchange, the reflector, and its application
-// to the trailing columns, each wave taking whole columns and reducing over the
-// rows with a fixed lane tree.  Q is applied to [U_R; 0] column by column, one
+// geqp3 does): per column the pivot (largest trailing norm, the first on ties),
+// the column exchange, the reflector, and its application to the trailing
+// columns, which also yields their norms for the next pivot; waves take whole
+// columns and reduce over the rows with a fixed lane tree.  Q is applied to [U_R; 0] column by column, one
 // wave per column through all n reflectors (columns are independent, so no
 // workgroup barrier is needed there).
 #include <hip/hip_runtime.h>
@@ -51,16 +51,18 @@ __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, i
   int32_t *pm = perm + d.toff[mat];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int j = threadIdx.x; j < n; j += blockDim.x) pm[j] = j;
+  // squared column norms over all rows; later steps take them from the update
+  // pass of the step before (the same rows, summed by the same lanes in the same
+  // order as a separate pass would)
+  for (int j = wv; j < n; j += nw) {
+    const R *c = a + (int64_t)j * m;
+    R s = 0;
+    for (int i = lane; i < m; i += 64) s += c[i] * c[i];
+    s = wave_sum(s);
+    if (lane == 0) s_nrm[j] = s;
+  }
+  __syncthreads();
   for (int k = 0; k < n; ++k) {
-    // squared norms of the trailing columns, rows k..m-1
-    for (int j = k + wv; j < n; j += nw) {
-      const R *c = a + (int64_t)j * m;
-      R s = 0;
-      for (int i = k + lane; i < m; i += 64) s += c[i] * c[i];
-      s = wave_sum(s);
-      if (lane == 0) s_nrm[j] = s;
-    }
-    __syncthreads();
     // the pivot: the largest squared norm, the smallest index on ties
     if (wv == 0) {
       R best = (R)-1;
@@ -126,7 +128,8 @@ __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, i
       for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) ck[i] *= scal;
       __syncthreads();
       if (threadIdx.x == 0) ck[k] = s_beta;
-      // H_k on the trailing columns
+      // H_k on the trailing columns, and their squared norms over rows k+1..m-1
+      // for the next pivot
       for (int j = k + 1 + wv; j < n; j += nw) {
         R *cj = a + (int64_t)j * m;
         R w = 0;
@@ -134,7 +137,22 @@ __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, i
         w = wave_sum(w) + cj[k];
         R tw = tk * w;
         if (lane == 0) cj[k] -= tw;
-        for (int i = k + 1 + lane; i < m; i += 64) cj[i] -= tw * ck[i];
+        R s = 0;
+        for (int i = k + 1 + lane; i < m; i += 64) {
+          R x = cj[i] - tw * ck[i];
+          cj[i] = x;
+          s += x * x;
+        }
+        s = wave_sum(s);
+        if (lane == 0) s_nrm[j] = s;
+      }
+    } else {
+      for (int j = k + 1 + wv; j < n; j += nw) {
+        const R *cj = a + (int64_t)j * m;
+        R s = 0;
+        for (int i = k + 1 + lane; i < m; i += 64) s += cj[i] * cj[i];
+        s = wave_sum(s);
+        if (lane == 0) s_nrm[j] = s;
       }
     }
     __syncthreads();
