@@ -24,8 +24,9 @@
 namespace ksvd2 {
 
 constexpr int kRectMaxN = 4096;  // the column norms of a matrix live in LDS
-constexpr int kQrcpBlock = 512;
+constexpr int kQrcpBlock = 1024;
 constexpr int kQapplyBlock = 256;
+constexpr size_t kQapplyLds = 64 * 1024;  // the U columns of a workgroup, when they fit
 
 struct RectDesc {
   const int32_t *m, *n;
@@ -165,21 +166,31 @@ __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, i
   }
 }
 
-// U = H_0 ... H_{n-1} [U_R; 0]: one wave per column of U; V = P V_R by rows
-template <class R>
+// U = H_0 ... H_{n-1} [U_R; 0]: one wave per column of U; V = P V_R by rows.
+// kLds: the wave's column lives in LDS while the reflectors are applied (the
+// reflectors stream from L2/HBM); otherwise it is updated in place in U.  Both
+// perform the same operations in the same order.
+template <class R, bool kLds>
 __global__ __launch_bounds__(kQapplyBlock) void k_qapply(RectDesc d, const R *A, const R *tau,
                                                          const int32_t *perm, const R *UR,
-                                                         const R *VR, R *U, R *V) {
+                                                         const R *VR, R *U, R *V, int ldsm) {
+  extern __shared__ unsigned char s_raw[];
   const int mat = blockIdx.y;
   const int m = d.m[mat], n = d.n[mat];
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (kQapplyBlock >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.x * (kQapplyBlock >> 6) + wv;
   if (j >= n) return;  // whole waves leave; no barrier below
   const R *a = A + d.aoff[mat];
   const R *tu = tau + d.toff[mat];
   const R *ur = UR + d.roff[mat] + (int64_t)j * n;
-  R *u = U + d.aoff[mat] + (int64_t)j * m;
+  R *ug = U + d.aoff[mat] + (int64_t)j * m;
+  R *u = kLds ? reinterpret_cast<R *>(s_raw) + (size_t)wv * ldsm : ug;
   for (int i = lane; i < m; i += 64) u[i] = (i < n) ? ur[i] : (R)0;
+  if (kLds) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   for (int k = n - 1; k >= 0; --k) {
     const R tk = tu[k];
     if (tk == (R)0) continue;
@@ -188,9 +199,20 @@ __global__ __launch_bounds__(kQapplyBlock) void k_qapply(RectDesc d, const R *A,
     for (int i = k + 1 + lane; i < m; i += 64) w += v[i] * u[i];
     w = wave_sum(w) + u[k];
     R tw = tk * w;
+    if (kLds) {
+      // every lane has read u[k] before lane 0 rewrites it
+      __builtin_amdgcn_wave_barrier();
+    }
     if (lane == 0) u[k] -= tw;
     for (int i = k + 1 + lane; i < m; i += 64) u[i] -= tw * v[i];
+    if (kLds) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
+  if (kLds)
+    for (int i = lane; i < m; i += 64) ug[i] = u[i];
   const int32_t *pm = perm + d.toff[mat];
   const R *vr = VR + d.roff[mat] + (int64_t)j * n;
   R *vo = V + d.roff[mat] + (int64_t)j * n;
@@ -288,8 +310,16 @@ static int qapply_impl(int64_t nmat, const int32_t *m_host, const int32_t *n_hos
   int rc = rect_setup(nmat, m_host, n_host, aoff_host, roff_host, ws, ws_bytes, st, d, maxn);
   if (rc) return rc;
   const int cols = kQapplyBlock >> 6;
-  hipLaunchKernelGGL(k_qapply<R>, dim3((unsigned)((maxn + cols - 1) / cols), (unsigned)nmat),
-                     dim3(kQapplyBlock), 0, st, d, A, tau, perm, UR, VR, U, V);
+  int maxm = 0;
+  for (int64_t k = 0; k < nmat; ++k) maxm = m_host[k] > maxm ? m_host[k] : maxm;
+  const size_t lds = (size_t)cols * maxm * sizeof(R);
+  dim3 grid((unsigned)((maxn + cols - 1) / cols), (unsigned)nmat);
+  if (lds <= kQapplyLds)
+    hipLaunchKernelGGL((k_qapply<R, true>), grid, dim3(kQapplyBlock), lds, st, d, A, tau, perm,
+                       UR, VR, U, V, maxm);
+  else
+    hipLaunchKernelGGL((k_qapply<R, false>), grid, dim3(kQapplyBlock), 0, st, d, A, tau, perm,
+                       UR, VR, U, V, 0);
   return launch_status("kog_qrcp_apply launch");
 }
 

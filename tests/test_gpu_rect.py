@@ -6,7 +6,8 @@ factorization is compared within a rounding tolerance, not bit for bit: the same
 order, R and the reflectors within c m eps ||G||.  The whole SVD is checked through
 properties that hold at any size: LAPACK's singular values (sorted, descending),
 orthonormal columns of U, orthogonal V, G = U Sigma V^T.  Shapes: square and tall, odd
-and even m, n from 2 to 256 in one uneven batch, both precisions; argument errors.
+and even m, n from 2 to 256 in one uneven batch (U columns held in LDS), and a batch of
+columns over 4,000 rows (U updated in global memory), both precisions; argument errors.
 """
 import numpy as np
 import pytest
@@ -19,15 +20,20 @@ def _eps(dt):
     return 2.0 ** (-53 if dt == np.float64 else -24)
 
 
-def _batch(dt, seed=3):
+SHAPES = [(2, 2), (5, 2), (40, 10), (64, 64), (100, 64), (129, 128), (300, 256), (17, 16)]
+# columns of more than 64 KB per workgroup of four: U is updated in place in global memory
+TALL = [(4200, 4), (5000, 2), (4100, 8)]
+
+
+def _batch(dt, seed=3, shapes=SHAPES):
     rng = np.random.default_rng(seed)
-    shapes = [(2, 2), (5, 2), (40, 10), (64, 64), (100, 64), (129, 128), (300, 256), (17, 16)]
     return [(rng.standard_normal(s) * np.exp2(rng.integers(-3, 4, s[1]))).astype(dt)
             for s in shapes]
 
 
 @pytest.mark.parametrize("dt", DT)
-def test_qrcp_vs_oracle(orc, dt):
+@pytest.mark.parametrize("shapes", [SHAPES, TALL], ids=["mixed", "tall"])
+def test_qrcp_vs_oracle(orc, dt, shapes):
     import ctypes
 
     import torch
@@ -35,7 +41,7 @@ def test_qrcp_vs_oracle(orc, dt):
     from paper_2407_13116_amd import _lib
     from paper_2407_13116_amd import sweep as sw
 
-    mats = _batch(dt)
+    mats = _batch(dt, shapes=shapes)
     L = _lib.lib()
     m = np.array([x.shape[0] for x in mats], np.int32)
     n = np.array([x.shape[1] for x in mats], np.int32)
@@ -69,11 +75,13 @@ def test_qrcp_vs_oracle(orc, dt):
 
 
 @pytest.mark.parametrize("dt", DT)
-@pytest.mark.parametrize("mode", ["persistent", "plain"])
-def test_rect_svd_properties(dt, mode):
+@pytest.mark.parametrize("mode,shapes", [("persistent", SHAPES), ("plain", SHAPES),
+                                         ("persistent", TALL)], ids=["persistent", "plain",
+                                                                     "tall"])
+def test_rect_svd_properties(dt, mode, shapes):
     from paper_2407_13116_amd import sweep as sw
 
-    mats = _batch(dt, seed=4)
+    mats = _batch(dt, seed=4, shapes=shapes)
     res, sweeps = sw.svd_rect(mats, mode=mode)
     assert np.all(sweeps > 0)
     e = _eps(dt)
