@@ -238,40 +238,52 @@ template <class R> __device__ __attribute__((always_inline)) Svd2c<R> svd2c(cons
     ph[k] = (m[k] != (R)0) ? c_phase(h[k]) : one;
   }
   M2<R> Mg = {m[0], m[2], m[1], m[3]};  // |G'|, row-major [a b; c d]
+  // Each class prepares the operands of one of two shared bodies -- the simple
+  // classes of Sect. 3.1 (part9 / part35) or the triangular SVD (tri_uv) -- and
+  // the phase factors around it, so that lanes of one wave in different classes
+  // run each body once:
+  //   kind 0 (classes 9, 3): U = diag(d1, d2) Ub, V = Vb;
+  //   kind 1 (class 5):      U = Ub, V = diag(d1, d2) Vb;
+  //   kind 2 (classes 13, 15): U = Up Ub, V = rows exchanged if vsw of diag(1, vph) Vb.
+  int kind = 2;
+  bool use_tri = false;
+  M2<R> Ms = Mg;
+  int ts = t1;
+  R ra = 0, rb = 0, rd = 0;  // the triangular factor [ra rb; 0 rd]
   EF<R> s1, s2;
+  Cx<R> d1 = one, d2 = one, vph = one;
+  bool vsw = false;
+  CM<R> Up;
   if (tb1 & (CL9 | CL3)) {
     // row phases: the phase of the row's non-zero element, 1 for a zero row
-    Cx<R> d1 = (m[0] != (R)0) ? ph[0] : (m[2] != (R)0) ? ph[2] : one;
-    Cx<R> d2 = (m[1] != (R)0) ? ph[1] : (m[3] != (R)0) ? ph[3] : one;
-    Part<R> p = (tb1 & CL9) ? part9(Mg, t1) : part35<R, true>(Mg, t1);
-    out.U = cm_diag_real(d1, d2, rm_of(p.U));
-    out.V = cm_real(rm_of(p.V));
-    s1 = p.s1;
-    s2 = p.s2;
+    kind = 0;
+    d1 = (m[0] != (R)0) ? ph[0] : (m[2] != (R)0) ? ph[2] : one;
+    d2 = (m[1] != (R)0) ? ph[1] : (m[3] != (R)0) ? ph[3] : one;
   } else if (tb1 & CL5) {
     // column phases: conj of the phases of the non-zero row's elements, into V
-    Cx<R> d1 = c_conj((m[0] != (R)0) ? ph[0] : ph[1]);
-    Cx<R> d2 = c_conj((m[2] != (R)0) ? ph[2] : ph[3]);
-    Part<R> p = part35<R, true>(Mg, t1);
-    out.U = cm_real(rm_of(p.U));
-    out.V = cm_diag_real(d1, d2, rm_of(p.V));
-    s1 = p.s1;
-    s2 = p.s2;
+    kind = 1;
+    d1 = c_conj((m[0] != (R)0) ? ph[0] : ph[1]);
+    d2 = c_conj((m[2] != (R)0) ? ph[2] : ph[3]);
   } else if (tb1 & CL13) {
     // permute into [x y; 0 z] (types 7: columns, 14: rows, 11: both); then
     // P_U^T G' P_V = D_U [|x| |y|; 0 |z|] D_V^H with D_U = diag(px, pz b2),
-    // D_V = diag(1, b2), b2 = px conj(py)
+    // D_V = diag(1, b2), b2 = px conj(py); Up = P_U D_U
     bool pu = (t1 == 14 || t1 == 11), pv = (t1 == 7 || t1 == 11);
     int rx = pu ? 1 : 0, cx = pv ? 1 : 0;
     int kx = rx + 2 * cx, ky = rx + 2 * (1 - cx), kz = (1 - rx) + 2 * (1 - cx);
     Cx<R> b2 = c_mul(ph[kx], c_conj(ph[ky]));
     Cx<R> a2 = c_mul(ph[kz], b2);
-    TriUV<R> tu = tri_uv(m[kx], m[ky], m[kz]);
-    info |= tu.flags;
-    out.U = cm_swaprows(cm_diag_real(ph[kx], a2, tu.Ub), pu);
-    out.V = cm_swaprows(cm_diag_real(one, b2, tu.Vb), pv);
-    s1 = tu.s1;
-    s2 = tu.s2;
+    const Cx<R> zero = {(R)0, (R)0};
+    Up.a[0][0] = pu ? zero : ph[kx];
+    Up.a[0][1] = pu ? a2 : zero;
+    Up.a[1][0] = pu ? ph[kx] : zero;
+    Up.a[1][1] = pu ? zero : a2;
+    vph = b2;
+    vsw = pv;
+    ra = m[kx];
+    rb = m[ky];
+    rd = m[kz];
+    use_tri = true;
   } else {
     // class 15: column pivoting by the column norms, row phases making the
     // first column real and non-negative, row pivoting, one real rotation by
@@ -307,32 +319,48 @@ template <class R> __device__ __attribute__((always_inline)) Svd2c<R> svd2c(cons
     Cx<R> alpha2 = (m12 != (R)0) ? c_mul(p22, beta2) : p22;
     // U_+ = D1 P_U U_theta D_a, formed explicitly
     RM<R> W = rm_swaprows(rm_rot(ct, st), rswap);
-    CM<R> Up;
     Up.a[0][0] = c_scale(p1, W.a[0][0]);
     Up.a[1][0] = c_scale(p2, W.a[1][0]);
     Up.a[0][1] = c_mul(c_scale(p1, W.a[0][1]), alpha2);
     Up.a[1][1] = c_mul(c_scale(p2, W.a[1][1]), alpha2);
-    RM<R> Ub, Vb;
+    vph = beta2;
+    vsw = cswap;
     if (m12 == (R)0 || m22 == (R)0) {
       // a zero appeared: finished as in Sect. 3.1
       info |= I_DEGEN;
-      M2<R> Rpp = {w1, m12, (R)0, m22};
-      int t2 = ztype(Rpp.a, Rpp.c, Rpp.b, Rpp.d);
-      Part<R> sub = ((1u << t2) & CL5) ? part35<R, true>(Rpp, t2) : part9(Rpp, t2);
-      Ub = rm_of(sub.U);
-      Vb = rm_of(sub.V);
-      s1 = sub.s1;
-      s2 = sub.s2;
+      Ms = M2<R>{w1, m12, (R)0, m22};
+      ts = ztype(Ms.a, Ms.c, Ms.b, Ms.d);
     } else {
-      TriUV<R> tu = tri_uv(w1, m12, m22);
-      info |= tu.flags;
-      Ub = tu.Ub;
-      Vb = tu.Vb;
-      s1 = tu.s1;
-      s2 = tu.s2;
+      ra = w1;
+      rb = m12;
+      rd = m22;
+      use_tri = true;
     }
+  }
+  RM<R> Ub, Vb;
+  if (use_tri) {
+    TriUV<R> tu = tri_uv(ra, rb, rd);
+    info |= tu.flags;
+    Ub = tu.Ub;
+    Vb = tu.Vb;
+    s1 = tu.s1;
+    s2 = tu.s2;
+  } else {
+    Part<R> p = ((1u << ts) & CL9) ? part9(Ms, ts) : part35<R, true>(Ms, ts);
+    Ub = rm_of(p.U);
+    Vb = rm_of(p.V);
+    s1 = p.s1;
+    s2 = p.s2;
+  }
+  if (kind == 0) {
+    out.U = cm_diag_real(d1, d2, Ub);
+    out.V = cm_real(Vb);
+  } else if (kind == 1) {
+    out.U = cm_real(Ub);
+    out.V = cm_diag_real(d1, d2, Vb);
+  } else {
     out.U = cm_mul_real(Up, Ub);
-    out.V = cm_swaprows(cm_diag_real(one, beta2, Vb), cswap);
+    out.V = cm_swaprows(cm_diag_real(one, vph, Vb), vsw);
   }
   // backscale (Sect. 3.3.2); frexp form -> the paper's (e, f), f in [1, 2)
   out.f1 = s1.f * (R)2;
@@ -345,8 +373,10 @@ template <class R> __device__ __attribute__((always_inline)) Svd2c<R> svd2c(cons
 
 // one matrix per lane; G, U, V are [n][2][2] complex (real and imaginary part
 // interleaved), S [n][2] plain sigma, f [n][2] and e [n][2] the (e,f) pairs
+// at most 128 registers (4 waves per SIMD): the shared bodies keep the phase
+// factors of every class live across them
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_fwd_c(int64_t n, const R *__restrict__ G,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fwd_c(int64_t n, const R *__restrict__ G,
                                                   R *__restrict__ U, R *__restrict__ S,
                                                   R *__restrict__ V, R *__restrict__ f,
                                                   int32_t *__restrict__ e,
