@@ -309,6 +309,43 @@ def cpu_baseline(seconds):
                       f"({done} SVDs in {dt:.1f} s), OpenMP static schedule"}
 
 
+def oracle_beside(kind, seconds=2.0):
+    """The oracle timed on a bounded sample of the same workload as a widened row's
+    GPU case (host cores, OpenMP where the oracle has it)."""
+    import oracle
+    from paper_2407_13116_amd import inputs
+
+    oracle.build(force=False)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if kind == "fast":
+        g = [p[:1 << 20] for p in inputs.forward_sweep(np.float64, B=1 << 20)]
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            oracle.ksvd2(*g, nthreads=nthreads, plain=False, fast=True)
+            done += g[0].size
+        unit, sample = "2x2 SVDs/s", "2^20 matrices of the FP64 forward workload, repeated"
+    elif kind == "complex":
+        G = inputs.complex_batch(np.complex128, B=1 << 20)
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            oracle.ksvd2c(G, nthreads=nthreads)
+            done += len(G)
+        unit, sample = "complex 2x2 SVDs/s", "2^20 matrices of the complex128 recipe, repeated"
+    else:
+        mats = inputs.rect_batch(nmat=4)
+        done, t0 = 0, time.perf_counter()
+        for G in mats:
+            oracle.svd_rect(G)
+            done += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        unit, sample = "matrices/s", f"{done} of the 512 x 256 FP64 matrices, one thread"
+        nthreads = 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": unit, "cores": nthreads, "kind": "oracle",
+            "sample": sample}
+
+
 def roofline(f64):
     """The FP64 forward kernel is bound by VALU issue (its algorithmic bytes need only a
     quarter of HBM bandwidth at the measured rate): achieved = algorithmic FP work per
@@ -372,9 +409,13 @@ def main():
                            "GBs": ff["GBs"], "hbm_frac": ff["GBs"] / HBM_PEAK_GBS}
             fast_err[name] = sigma2_error_sample(gf, hf, dt)
             del gf, hf
+        if not args.no_cpu:
+            extra["fwd_fast_f64"]["cpu_baseline"] = oracle_beside("fast")
         for cdt, name in ((np.complex128, "complex_c128"), (np.complex64, "complex_c64")):
             log(f"[bench] {name}: complex 2x2 SVD, 2^22 matrices")
             extra[name] = complex_case(cdt, args.steps, args.warmup)
+        if not args.no_cpu:
+            extra["complex_c128"]["cpu_baseline"] = oracle_beside("complex")
         for dt, name in ((np.float64, "fwdbwd_f64"), (np.float32, "fwdbwd_f32")):
             log(f"[bench] {name}, 2^22 matrices")
             fb = fwdbwd_case(dt, args.steps, args.warmup)
@@ -389,6 +430,8 @@ def main():
             extra[name] = sweep_case(_inp.sweep_uneven(dtype=dt), dt)
         log("[bench] rectangular: 256 x (512 x 256) FP64")
         extra["rect_f64"] = rect_case(np.float64)
+        if not args.no_cpu:
+            extra["rect_f64"]["cpu_baseline"] = oracle_beside("rect", seconds=5.0)
         log(f"[bench] rect: {extra['rect_f64']}")
         log("[bench] sigma_2 accuracy sample")
         extra["max_rel_err_sigma2_ulp"] = {"f64": sigma2_error_sample(g64, h64, np.float64),
