@@ -191,9 +191,13 @@ def svd_rect_device(pr: PackedRect, max_sweeps: int = 40, tol_factor: float = 1.
 
 def svd_rect(mats, max_sweeps: int = 40, tol_factor: float = 1.0, mode="persistent",
              ordering="modulus", sort: bool = True, dtype=None, device="cuda"):
-    """SVD of m x n matrices (m >= n, n even; Sect. 1) through svd_rect_device.
-    Returns a list of (U [m,n], sigma [n], V [n,n]) numpy triples and the sweep counts.
-    For m < n pass the transposes."""
+    """SVD of m x n matrices (Sect. 1) through svd_rect_device: G = U diag(sigma) V^T
+    with U [m,k], V [n,k], k = min(m, n), which must be even.  A matrix with m < n is
+    factored as G^T (the paper's advice) and its U and V exchanged.  Returns a list of
+    (U, sigma, V) numpy triples and the sweep counts."""
+    mats = [np.asarray(x) for x in mats]
+    wide = [x.shape[0] < x.shape[1] for x in mats]
+    mats = [x.T if w else x for x, w in zip(mats, wide)]
     pr = PackedRect(mats, dtype=dtype, device=device)
     out = svd_rect_device(pr, max_sweeps, tol_factor, mode, ordering, sort)
     Uh = out["U"].cpu().numpy()
@@ -201,6 +205,7 @@ def svd_rect(mats, max_sweeps: int = 40, tol_factor: float = 1.0, mode="persiste
     sig = pr.R.unpack_sigma(out["sigma"])
     res = [(Uh[o:o + mm * nn].reshape((mm, nn), order="F"), sig[k], Vs[k])
            for k, (o, mm, nn) in enumerate(zip(pr.aoff, pr.m, pr.n))]
+    res = [(V, s_, U) if w else (U, s_, V) for (U, s_, V), w in zip(res, wide)]
     return res, out["sweeps"].cpu().numpy()
 
 

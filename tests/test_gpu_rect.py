@@ -120,3 +120,25 @@ def test_rect_arguments_rejected():
     rc = L.kog_qrcp_batch(1, 1, ptr(m2), ptr(n), ptr(off), ptr(off), p, p, p, p, ws.data_ptr(),
                           16, None)
     assert rc == -4
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_rect_wide_matrices_through_the_transpose(dt):
+    """m < n: the Python side factors G^T and exchanges U and V (Sect. 1)."""
+    from paper_2407_13116_amd import sweep as sw
+
+    rng = np.random.default_rng(12)
+    mats = [rng.standard_normal(s).astype(dt) for s in ((4, 10), (32, 100), (64, 64))]
+    res, sweeps = sw.svd_rect(mats)
+    assert np.all(sweeps > 0)
+    e = _eps(dt)
+    for G, (U, s, V) in zip(mats, res):
+        m, n = G.shape
+        k = min(m, n)
+        assert U.shape == (m, k) and V.shape == (n, k)
+        Gd = G.astype(np.float64)
+        R = U.astype(np.float64) @ np.diag(s.astype(np.float64)) @ V.astype(np.float64).T
+        assert np.abs(R - Gd).max() <= 40 * max(m, n) * e * np.linalg.norm(Gd)
+        ref = np.linalg.svd(Gd, compute_uv=False)
+        assert np.abs(s.astype(np.float64) - ref).max() <= 40 * max(m, n) * e * ref[0]
+
