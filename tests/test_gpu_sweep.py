@@ -6,9 +6,10 @@
   520 whose deferred U/V update spans several LDS row tiles and pivot passes.
 * Converged runs: the three modes bitwise identical to each other; sigma against LAPACK,
   orthogonality of U and V, reconstruction, the off-diagonal stopping test.
-* The uniform-size workload at full size (256 matrices of order 256, FP64) in the
-  launch configuration the benchmark times; two sampled matrices recomputed by the oracle
-  with the same number of sweeps, bit for bit.
+* The uniform-size workload at full size (256 matrices of order 256, FP64) and the uneven
+  one (1,000 orders 16..512, FP64 and FP32) in the launch configuration the benchmark
+  times; sampled matrices recomputed by the oracle with the same number of sweeps, bit for
+  bit.
 * The sigma gradient dG = U diag(dsigma) V^T: against float64 numpy, and against central
   differences of sorted sigma through the GPU sweep.
 * Resuming (accumulate): 1 + 1 sweeps equal 2 sweeps bitwise; edge cases (order 2,
@@ -144,6 +145,30 @@ def test_uniform_workload_full_size_sampled(orc):
         n = mats[k].shape[0]
         # LAPACK's singular values are accurate to n eps sigma_max (absolute) only
         assert np.max(np.abs(sig - ref)) <= 10 * n * 2.0 ** -53 * ref[0]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_uneven_workload_full_size_sampled(orc, dtype):
+    """1,000 matrices of uneven order 16..512, persistent mode as benchmarked; three sampled
+    matrices (the smallest, a middle and a large order) recomputed by the oracle with the
+    same number of sweeps, bit for bit."""
+    import torch
+
+    from paper_2407_13116_amd import sweep as sw
+
+    mats = inputs.sweep_uneven(dtype=dtype)
+    p = sw.Packed(mats, dtype=dtype)
+    out = sw.kog_sweep_batch(p, max_sweeps=60, tol_factor=1.0, mode="persistent")
+    torch.cuda.synchronize()
+    sweeps = out["sweeps"].cpu().numpy()
+    assert np.all(sweeps > 0), sweeps
+    Gs, Us, Vs = p.unpack(out["G"]), p.unpack(out["U"]), p.unpack(out["V"])
+    ns = np.array([m.shape[0] for m in mats])
+    order = np.argsort(ns, kind="stable")
+    picks = [int(order[0]), int(order[len(order) // 2]), int(order[int(0.7 * len(order))])]
+    for k in picks:
+        G, U, V, st, swp = orc.kog_sweep(mats[k], max_sweeps=int(sweeps[k]), tol_factor=-1.0)
+        assert _same(Gs[k], G) and _same(Us[k], U) and _same(Vs[k], V), (k, ns[k])
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
