@@ -21,35 +21,43 @@ std::string &last_error_ref() {
   return s;
 }
 
+// element at byte offset `bo` of a plane: a 32-bit offset from the plane's base
+// lets every load and store take the scalar-base addressing form instead of a
+// 64-bit address per plane and lane (launches are split so that offsets fit)
+template <class T> __device__ inline T &at(T *base, uint32_t bo) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + bo);
+}
+template <class T> __device__ inline const T &at(const T *base, uint32_t bo) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + bo);
+}
+constexpr int64_t kMaxLaunch = int64_t(1) << 28;  // elements per launch: offsets < 2^31
+
 // 6 waves per SIMD (at most 80 registers): the straight-line SVD code issues
 // back-to-back dependent FP64 instructions, and one more resident wave hides
 // more of their latency than the few registers given up cost (measured).
 // CR: the correctly rounded hypot (the method as analysed) or the fast variant.
 template <class R, bool CR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_soa(int64_t n, const R *__restrict__ g11,
-                                                    const R *__restrict__ g21,
-                                                    const R *__restrict__ g12,
-                                                    const R *__restrict__ g22, R *__restrict__ cu,
-                                                    R *__restrict__ su, R *__restrict__ cv,
-                                                    R *__restrict__ sv, R *__restrict__ f1,
-                                                    R *__restrict__ f2, int32_t *__restrict__ e1,
-                                                    int32_t *__restrict__ e2,
-                                                    int32_t *__restrict__ info,
-                                                    R *__restrict__ s1, R *__restrict__ s2) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_soa(
+    uint32_t n, const R *__restrict__ g11, const R *__restrict__ g21, const R *__restrict__ g12,
+    const R *__restrict__ g22, R *__restrict__ cu, R *__restrict__ su, R *__restrict__ cv,
+    R *__restrict__ sv, R *__restrict__ f1, R *__restrict__ f2, int32_t *__restrict__ e1,
+    int32_t *__restrict__ e2, int32_t *__restrict__ info, R *__restrict__ s1,
+    R *__restrict__ s2) {
+  const uint32_t i = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
   if (i >= n) return;
-  Svd2<R> r = svd2<R, CR>(g11[i], g21[i], g12[i], g22[i]);
-  cu[i] = r.cu;
-  su[i] = r.su;
-  cv[i] = r.cv;
-  sv[i] = r.sv;
-  f1[i] = r.f1;
-  f2[i] = r.f2;
-  e1[i] = r.e1;
-  e2[i] = r.e2;
-  info[i] = (int32_t)r.info;
-  if (s1) s1[i] = scale2(r.f1, r.e1);
-  if (s2) s2[i] = scale2(r.f2, r.e2);
+  const uint32_t bw = i * (uint32_t)sizeof(R), b4 = i * 4u;
+  Svd2<R> r = svd2<R, CR>(at(g11, bw), at(g21, bw), at(g12, bw), at(g22, bw));
+  at(cu, bw) = r.cu;
+  at(su, bw) = r.su;
+  at(cv, bw) = r.cv;
+  at(sv, bw) = r.sv;
+  at(f1, bw) = r.f1;
+  at(f2, bw) = r.f2;
+  at(e1, b4) = r.e1;
+  at(e2, b4) = r.e2;
+  at(info, b4) = (int32_t)r.info;
+  if (s1) at(s1, bw) = scale2(r.f1, r.e1);
+  if (s2) at(s2, bw) = scale2(r.f2, r.e2);
 }
 
 // [B,2,2] blocks (4 consecutive values) and [B,2] pairs, moved as 16-byte
@@ -199,8 +207,13 @@ static int fwd_soa(int64_t n, const R *g11, const R *g21, const R *g12, const R 
   KSVD2_REQ(cu, w); KSVD2_REQ(su, w); KSVD2_REQ(cv, w); KSVD2_REQ(sv, w);
   KSVD2_REQ(f1, w); KSVD2_REQ(f2, w); KSVD2_REQ(e1, 4); KSVD2_REQ(e2, 4); KSVD2_REQ(info, 4);
   KSVD2_OPT(s1, w); KSVD2_OPT(s2, w);
-  hipLaunchKernelGGL((k_fwd_soa<R, CR>), dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
-                     g11, g21, g12, g22, cu, su, cv, sv, f1, f2, e1, e2, info, s1, s2);
+  for (int64_t o = 0; o < n; o += kMaxLaunch) {
+    const uint32_t c = (uint32_t)(n - o < kMaxLaunch ? n - o : kMaxLaunch);
+    R *s1o = s1 ? s1 + o : nullptr, *s2o = s2 ? s2 + o : nullptr;
+    hipLaunchKernelGGL((k_fwd_soa<R, CR>), dim3(grid_for(c)), dim3(kBlock), 0,
+                       (hipStream_t)stream, c, g11 + o, g21 + o, g12 + o, g22 + o, cu + o, su + o,
+                       cv + o, sv + o, f1 + o, f2 + o, e1 + o, e2 + o, info + o, s1o, s2o);
+  }
   return launch_status("ksvd2 forward launch");
 }
 
