@@ -164,16 +164,56 @@ template <class R> struct Svd2c {
   uint32_t info;
 };
 
-// g in the order g11, g21, g12, g22
+// a finite G whose elements are all real, or all imaginary
+template <class R> __device__ inline bool real_or_imag(const Cx<R> g[4], bool &all_re) {
+  bool re = true, im = true, fin = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    fin = fin && isfinite(g[k].re) && isfinite(g[k].im);
+    re = re && g[k].im == (R)0;
+    im = im && g[k].re == (R)0;
+  }
+  all_re = re;
+  return fin && (re || im);
+}
+
+// a real matrix, or i times one: the real method (U multiplied by i for the latter)
+template <class R>
+__device__ __attribute__((always_inline)) Svd2c<R> svd2c_real(const Cx<R> g[4], bool all_re) {
+  Svd2c<R> out;
+  Svd2<R> r = all_re ? svd2<R>(g[0].re, g[1].re, g[2].re, g[3].re)
+                     : svd2<R>(g[0].im, g[1].im, g[2].im, g[3].im);
+  R du = (r.info & I_DETU) ? (R)-1 : (R)1, dv = (r.info & I_DETV) ? (R)-1 : (R)1;
+  RM<R> Ur, Vr;
+  Ur.a[0][0] = r.cu;
+  Ur.a[0][1] = -du * r.su;
+  Ur.a[1][0] = r.su;
+  Ur.a[1][1] = du * r.cu;
+  Vr.a[0][0] = r.cv;
+  Vr.a[0][1] = -dv * r.sv;
+  Vr.a[1][0] = r.sv;
+  Vr.a[1][1] = dv * r.cv;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      out.U.a[i][j] = all_re ? Cx<R>{Ur.a[i][j], (R)0} : Cx<R>{(R)0, Ur.a[i][j]};
+  out.V = cm_real(Vr);
+  out.f1 = r.f1;
+  out.f2 = r.f2;
+  out.e1 = r.e1;
+  out.e2 = r.e2;
+  out.info = r.info;
+  return out;
+}
+
+// g in the order g11, g21, g12, g22; a non-finite G or one with a complex
+// element (real and purely imaginary matrices take svd2c_real)
 template <class R> __device__ __attribute__((always_inline)) Svd2c<R> svd2c(const Cx<R> g[4]) {
   Svd2c<R> out;
-  bool finite = true, all_re = true, all_im = true;
+  bool finite = true;
   int t = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     finite = finite && isfinite(g[k].re) && isfinite(g[k].im);
-    all_re = all_re && g[k].im == (R)0;
-    all_im = all_im && g[k].re == (R)0;
     t |= (g[k].re != (R)0 || g[k].im != (R)0) << k;
   }
   if (!finite) {
@@ -183,31 +223,6 @@ template <class R> __device__ __attribute__((always_inline)) Svd2c<R> svd2c(cons
     out.f1 = out.f2 = nan;
     out.e1 = out.e2 = 0;
     out.info = (uint32_t)t | I_NONFINITE;
-    return out;
-  }
-  if (all_re || all_im) {
-    // a real matrix, or i times one: the real method
-    Svd2<R> r = all_re ? svd2<R>(g[0].re, g[1].re, g[2].re, g[3].re)
-                       : svd2<R>(g[0].im, g[1].im, g[2].im, g[3].im);
-    R du = (r.info & I_DETU) ? (R)-1 : (R)1, dv = (r.info & I_DETV) ? (R)-1 : (R)1;
-    RM<R> Ur, Vr;
-    Ur.a[0][0] = r.cu;
-    Ur.a[0][1] = -du * r.su;
-    Ur.a[1][0] = r.su;
-    Ur.a[1][1] = du * r.cu;
-    Vr.a[0][0] = r.cv;
-    Vr.a[0][1] = -dv * r.sv;
-    Vr.a[1][0] = r.sv;
-    Vr.a[1][1] = dv * r.cv;
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j)
-        out.U.a[i][j] = all_re ? Cx<R>{Ur.a[i][j], (R)0} : Cx<R>{(R)0, Ur.a[i][j]};
-    out.V = cm_real(Vr);
-    out.f1 = r.f1;
-    out.f2 = r.f2;
-    out.e1 = r.e1;
-    out.e2 = r.e2;
-    out.info = r.info;
     return out;
   }
   // prescaling with s_C = s + 1 over all real and imaginary parts
@@ -371,22 +386,9 @@ template <class R> __device__ __attribute__((always_inline)) Svd2c<R> svd2c(cons
   return out;
 }
 
-// one matrix per lane; G, U, V are [n][2][2] complex (real and imaginary part
-// interleaved), S [n][2] plain sigma, f [n][2] and e [n][2] the (e,f) pairs
-// at most 128 registers (4 waves per SIMD): the shared bodies keep the phase
-// factors of every class live across them
 template <class R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fwd_c(int64_t n, const R *__restrict__ G,
-                                                  R *__restrict__ U, R *__restrict__ S,
-                                                  R *__restrict__ V, R *__restrict__ f,
-                                                  int32_t *__restrict__ e,
-                                                  int32_t *__restrict__ info) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const R *x = G + 8 * i;
-  // row-major (r, c) at 2 (2 r + c); order g11, g21, g12, g22
-  Cx<R> g[4] = {{x[0], x[1]}, {x[4], x[5]}, {x[2], x[3]}, {x[6], x[7]}};
-  Svd2c<R> r = svd2c<R>(g);
+__device__ inline void store_c(int64_t i, const Svd2c<R> &r, R *U, R *S, R *V, R *f, int32_t *e,
+                               int32_t *info) {
   R *u = U + 8 * i, *v = V + 8 * i;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -409,6 +411,53 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     e[2 * i + 1] = r.e2;
   }
   if (info) info[i] = (int32_t)r.info;
+}
+
+template <class R> __device__ inline void load_c(const R *G, int64_t i, Cx<R> g[4]) {
+  const R *x = G + 8 * i;
+  // row-major (r, c) at 2 (2 r + c); order g11, g21, g12, g22
+  g[0] = Cx<R>{x[0], x[1]};
+  g[1] = Cx<R>{x[4], x[5]};
+  g[2] = Cx<R>{x[2], x[3]};
+  g[3] = Cx<R>{x[6], x[7]};
+}
+
+// One matrix per lane; G, U, V are [n][2][2] complex (real and imaginary part
+// interleaved), S [n][2] plain sigma, f [n][2] and e [n][2] the (e,f) pairs.
+// Real and purely imaginary matrices are rare but would make every wave that
+// holds one run the whole real method beside the complex path, so a workgroup
+// collects them in LDS and its first lanes run the real method on them after
+// the complex lanes are done (each matrix's result does not depend on which
+// lane computes it).  At most 128 registers (4 waves per SIMD).
+template <class R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fwd_c(
+    int64_t n, const R *__restrict__ G, R *__restrict__ U, R *__restrict__ S,
+    R *__restrict__ V, R *__restrict__ f, int32_t *__restrict__ e, int32_t *__restrict__ info) {
+  __shared__ int s_cnt;
+  __shared__ int s_list[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kBlock;
+  const int64_t i = base + threadIdx.x;
+  const bool valid = i < n;
+  Cx<R> g[4];
+  bool all_re = false, rl = false;
+  if (valid) {
+    load_c(G, i, g);
+    rl = real_or_imag(g, all_re);
+  }
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  if (rl) s_list[atomicAdd(&s_cnt, 1)] = threadIdx.x;
+  __syncthreads();
+  if (valid && !rl) store_c(i, svd2c<R>(g), U, S, V, f, e, info);
+  const int cnt = s_cnt;
+  if ((int)threadIdx.x < cnt) {
+    const int64_t j = base + s_list[threadIdx.x];
+    Cx<R> h[4];
+    load_c(G, j, h);
+    bool hre;
+    (void)real_or_imag(h, hre);
+    store_c(j, svd2c_real<R>(h, hre), U, S, V, f, e, info);
+  }
 }
 
 template <class R>
