@@ -277,8 +277,11 @@ __device__ __attribute__((always_inline)) inline float hypot1_le1(float t) {
 // special operands.  Where the operands are known to need no scaling (normal
 // operands and quotient, numerator above 2^-960, divisor below 2^1020) the
 // bracket does nothing and is left out; one reciprocal then also serves two
-// numerators.  The results are the IEEE quotients, bit for bit.  binary32 keeps
-// the plain (correctly rounded) division.
+// numerators.  The results are the IEEE quotients, bit for bit.  The binary32
+// sequence (reciprocal estimate, one Newton step, a product, two residual
+// corrections) is bracketed the same way and needs no scaling for normal
+// operands and quotient, a numerator above 2^-100 and a divisor below 2^124;
+// it is used unguarded for the (e,f) mantissa quotients, which always qualify.
 // ---------------------------------------------------------------------------
 __device__ inline double rcp_refined(double b) {
   double y = __builtin_amdgcn_rcp(b);
@@ -295,11 +298,25 @@ __device__ inline double div_with(double a, double b, double y) {
 
 // a / b for a, b in [1/2, 1) (mantissas in frexp form)
 __device__ inline double div_unit(double a, double b) { return div_with(a, b, rcp_refined(b)); }
-__device__ inline float div_unit(float a, float b) { return a / b; }
+__device__ inline float rcp_refined(float b) {
+  float y = __builtin_amdgcn_rcpf(b);
+  float e = fmaf(-b, y, 1.0f);
+  return fmaf(e, y, y);
+}
+__device__ inline float div_with(float a, float b, float y) {
+  float q = a * y;
+  float r = fmaf(-b, q, a);
+  q = fmaf(r, y, q);
+  r = fmaf(-b, q, a);
+  return fmaf(r, y, q);
+}
+__device__ inline float div_unit(float a, float b) { return div_with(a, b, rcp_refined(b)); }
 
 // c = 1 / sec and s = t / sec, where sec = sqrt(1 + t^2) rounded (the secant of
 // the angle with tangent t): the quotients are normal whenever t is 0 or
-// |t| >= 2^-960, so only a huge secant or a tiny tangent takes the plain route.
+// |t| >= 2^-960, so only a huge secant (above 2^1020) or a tiny tangent takes
+// the plain route.  In binary32 the guards cost more than the division steps
+// they save (measured), so binary32 divides plainly here.
 __device__ inline void cos_sin(double t, double sec, double &c, double &s) {
   if (sec <= 0x1p1020 && (t == 0.0 || fabs(t) >= 0x1p-960)) {
     double y = rcp_refined(sec);
@@ -317,7 +334,7 @@ __device__ inline void cos_sin(float t, float sec, float &c, float &s) {
 
 // a1 / sec and a2 / sec for sec in [1, 2): one reciprocal serves both wherever
 // 2^-960 <= |a_i| <= 2^1020 (normal quotients, exact residuals); zero and
-// extreme numerators take the plain division.
+// extreme numerators take the plain division (binary32: always, as above).
 __device__ inline void div_by_sec(double a1, double a2, double sec, double &q1, double &q2) {
   bool f1 = fabs(a1) >= 0x1p-960 && fabs(a1) <= 0x1p1020;
   bool f2 = fabs(a2) >= 0x1p-960 && fabs(a2) <= 0x1p1020;
