@@ -304,9 +304,26 @@ def cpu_baseline(seconds):
         oracle.ksvd2(*g, nthreads=nthreads, plain=False)
         done += g[0].size
     dt = time.perf_counter() - t0
+    # one thread on the first 2^18 matrices, ~2 s
+    g1 = [p[:1 << 18] for p in g]
+    d1, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < 2.0:
+        oracle.ksvd2(*g1, nthreads=1, plain=False)
+        d1 += g1[0].size
+    st = d1 / (time.perf_counter() - t1)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": done / dt, "unit": "2x2 SVDs/s", "cores": nthreads, "kind": "oracle",
             "sample": f"first 2^22 matrices of the FP64 2^24 workload, repeated for ~{seconds:.0f} s "
-                      f"({done} SVDs in {dt:.1f} s), OpenMP static schedule"}
+                      f"({done} SVDs in {dt:.1f} s), OpenMP static schedule",
+            "single_thread_value": st, "cpu_model": model, "nproc": os.cpu_count()}
 
 
 def oracle_beside(kind, seconds=2.0):
