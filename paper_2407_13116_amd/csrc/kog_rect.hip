@@ -10,9 +10,9 @@
 // geqp3 does): per column the pivot (largest trailing norm, the first on ties),
 // the column exchange, the reflector, and its application to the trailing
 // columns, which also yields their norms for the next pivot; waves take whole
-// columns and reduce over the rows with a fixed lane tree.  Q is applied to [U_R; 0] column by column, one
-// wave per column through all n reflectors (columns are independent, so no
-// workgroup barrier is needed there).
+// columns and reduce over the rows with a fixed lane tree.  Q is applied to
+// [U_R; 0] column by column, one wave per column through all n reflectors
+// (columns are independent, so no workgroup barrier is needed there).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
