@@ -2,7 +2,8 @@
 // matrices of possibly different even orders, built on the 2x2 SVD of
 // ksvd2_device.hpp.
 //
-// One parallel step k of a sweep (round-robin ordering, n/2 disjoint pivots):
+// One parallel step k of a sweep (n/2 disjoint pivots from the round-robin or
+// the modified modulus ordering):
 //   1. every pivot (i, j) of step k is diagonalised by the 2x2 SVD of
 //      [g_ii g_ij; g_ji g_jj] (U_p, sigma, V_p; sigma rounded to W);
 //   2. rows i, j of G are rotated by U_p^T, then columns i, j by V_p:
