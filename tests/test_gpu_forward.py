@@ -58,6 +58,17 @@ def test_full_size_sampled_bitwise(orc, dtype):
     assert np.all(((f2 >= 1) & (f2 < 2)) | ((f2 == 0) & (got["e2"] == 0)))
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("seed", [101, 202, 303])
+def test_more_seeds_bitwise(orc, dtype, seed):
+    """The accuracy/throughput recipe with other seeds, 2^19 + 11 matrices each, and its
+    exponent range narrowed to a quarter (fewer exponent-gap exits, more full hypots)."""
+    g = inputs.forward_sweep(dtype, seed=seed, B=(1 << 19) + 11)
+    assert_bitwise(gpu_ksvd2(g), orc.ksvd2(*g), label=f"seed {seed} {dtype.__name__}")
+    q = tuple(np.ldexp(m, e // 4).astype(dtype) for m, e in (np.frexp(p) for p in g))
+    assert_bitwise(gpu_ksvd2(q), orc.ksvd2(*q), label=f"seed {seed} narrow {dtype.__name__}")
+
+
 @pytest.mark.parametrize("n", [1, 2, 255, 256, 257])
 def test_small_batches(orc, n):
     g = inputs.forward_sweep(np.float64, B=n, seed=5)
