@@ -382,8 +382,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the batched 2x2 "
-              "SVD shards by matrix with no communication, and multi-GPU runs are not part "
-              "of this build.", file=sys.stderr)
+              "SVD shards by matrix with no communication, and runs on several GPUs are not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
 
