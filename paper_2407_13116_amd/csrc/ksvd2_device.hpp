@@ -239,6 +239,22 @@ __device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y
   float f = (float)r;
   double fd = isinf(f) ? 0x1p128 : (double)f;  // +inf stands for 2^128 here
   if (fd == r) return f;
+  // f is the correctly rounded root unless sqrt(x^2 + y^2) lies beyond one of
+  // the two rounding boundaries around f.  With d = sqrt(S) - r, S - r^2 =
+  // d (2 r + d) and 2 r + d > r, so |d| < |S - r^2| / r; the residual comes from
+  // one fma, and the rounding of S itself moves the root by at most r 2^-54.  So
+  // f is certified when |r - f| + r 2^-52 + |S - r^2| / r stays below the
+  // smaller distance from f to a rounding boundary (half the spacing of binary32
+  // numbers at f; the spacing below a power of two is half as wide), tested
+  // without a division; only the rare uncertified lanes take the exact test.
+  if (f != 0.0f && !isinf(f)) {
+    int ef = max(ilog2(fd), -126);
+    double side = ldexp(1.0, ef - 24);
+    if ((__float_as_uint(f) & 0x7fffffu) == 0u && ef > -126) side *= 0.5;
+    double slack = side - fabs(r - fd) - r * 0x1p-52;
+    double rho = fma(-r, r, S);
+    if (slack > 0.0 && fabs(rho) < r * slack * 0.5) return f;
+  }
   bool above = r > fd;
   float g;
   double gd;
