@@ -31,9 +31,9 @@ def _batch(dt, seed=3, shapes=SHAPES):
             for s in shapes]
 
 
-@pytest.mark.parametrize("dt", DT)
-@pytest.mark.parametrize("shapes", [SHAPES, TALL], ids=["mixed", "tall"])
-def test_qrcp_vs_oracle(orc, dt, shapes):
+def _qrcp_gpu(mats, dt):
+    """Runs kog_qrcp_batch on the packed batch; returns the reflectors, tau, the
+    pivots and R per matrix."""
     import ctypes
 
     import torch
@@ -41,7 +41,6 @@ def test_qrcp_vs_oracle(orc, dt, shapes):
     from paper_2407_13116_amd import _lib
     from paper_2407_13116_amd import sweep as sw
 
-    mats = _batch(dt, shapes=shapes)
     L = _lib.lib()
     m = np.array([x.shape[0] for x in mats], np.int32)
     n = np.array([x.shape[1] for x in mats], np.int32)
@@ -60,18 +59,28 @@ def test_qrcp_vs_oracle(orc, dt, shapes):
     torch.cuda.synchronize()
     Ah, th, ph = A.cpu().numpy(), tau.cpu().numpy(), perm.cpu().numpy()
     Rs = R.unpack(R.G)
-    t0 = 0
+    out, t0 = [], 0
     for k, G in enumerate(mats):
         mm, nn = G.shape
+        out.append((Ah[aoff[k]:aoff[k] + mm * nn].reshape((mm, nn), order="F"),
+                    th[t0:t0 + nn], ph[t0:t0 + nn], Rs[k]))
+        t0 += nn
+    return out
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shapes", [SHAPES, TALL], ids=["mixed", "tall"])
+def test_qrcp_vs_oracle(orc, dt, shapes):
+    mats = _batch(dt, shapes=shapes)
+    for k, (G, (Ag, tg, pg, Rg)) in enumerate(zip(mats, _qrcp_gpu(mats, dt))):
+        mm, nn = G.shape
         Ao, to, po, Ro = orc.qrcp(G)
-        Ag = Ah[aoff[k]:aoff[k] + mm * nn].reshape((mm, nn), order="F")
         tol = 16 * mm * _eps(dt) * float(np.linalg.norm(G.astype(np.float64)))
-        assert np.array_equal(ph[t0:t0 + nn], po), k
-        assert np.abs(Rs[k].astype(np.float64) - Ro).max() <= tol, k
+        assert np.array_equal(pg, po), k
+        assert np.abs(Rg.astype(np.float64) - Ro).max() <= tol, k
         # reflectors (unit-scaled entries) and tau
         assert np.abs(np.tril(Ag, -1) - np.tril(Ao, -1)).max() <= 16 * mm * _eps(dt) * 64, k
-        assert np.abs(th[t0:t0 + nn] - to).max() <= 16 * mm * _eps(dt), k
-        t0 += nn
+        assert np.abs(tg - to).max() <= 16 * mm * _eps(dt), k
 
 
 @pytest.mark.parametrize("dt", DT)
@@ -142,3 +151,56 @@ def test_rect_wide_matrices_through_the_transpose(dt):
         ref = np.linalg.svd(Gd, compute_uv=False)
         assert np.abs(s.astype(np.float64) - ref).max() <= 40 * max(m, n) * e * ref[0]
 
+
+def _deficient(dt):
+    """A zero column, exactly repeated and scaled columns, a rank-one matrix; with
+    their ranks."""
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((30, 8))
+    A[:, 3] = 0.0
+    B = rng.standard_normal((20, 6))
+    B[:, 4] = B[:, 1]
+    B[:, 5] = -2.0 * B[:, 0]
+    C = np.outer(rng.standard_normal(12), rng.standard_normal(4))
+    return [x.astype(dt) for x in (A, B, C)], [7, 4, 1]
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_qrcp_rank_deficient_vs_oracle(orc, dt):
+    """Beyond the numerical rank the remaining columns are rounding noise, so their
+    order is not fixed by the method: the pivots up to the rank and those columns of R
+    match the oracle; the zero column's reflector is the identity (tau = 0 exactly) and
+    it is pivoted last."""
+    mats, ranks = _deficient(dt)
+    for k, (G, r, (Ag, tg, pg, Rg)) in enumerate(zip(mats, ranks, _qrcp_gpu(mats, dt))):
+        mm, nn = G.shape
+        Ao, to, po, Ro = orc.qrcp(G)
+        tol = 16 * mm * _eps(dt) * float(np.linalg.norm(G.astype(np.float64)))
+        assert np.array_equal(pg[:r], po[:r]), k
+        assert sorted(pg) == list(range(nn)), k
+        assert np.abs(Rg[:, :r].astype(np.float64) - Ro[:, :r]).max() <= tol, k
+        assert np.all(np.isfinite(Rg)) and np.all(np.isfinite(tg)), k
+        assert np.abs(np.triu(Rg.astype(np.float64), 0)[r:, r:]).max() <= tol, k
+    assert tg.dtype == mats[0].dtype
+    _, tA, pA, _ = _qrcp_gpu(mats[:1], dt)[0]
+    assert pA[-1] == 3 and tA[-1] == 0
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_rect_rank_deficient_and_zero_columns(dt):
+    """The same matrices through the whole path: LAPACK's singular values (the zeros
+    within the tolerance) and G = U Sigma V^T."""
+    from paper_2407_13116_amd import sweep as sw
+
+    mats, _ = _deficient(dt)
+    res, sweeps = sw.svd_rect(mats)
+    assert np.all(sweeps > 0)
+    e = _eps(dt)
+    for G, (U, s, V) in zip(mats, res):
+        m, n = G.shape
+        Gd = G.astype(np.float64)
+        ref = np.linalg.svd(Gd, compute_uv=False)
+        sd = s.astype(np.float64)
+        assert np.abs(sd - ref).max() <= 40 * m * e * ref[0]
+        R = U.astype(np.float64) @ np.diag(sd) @ V.astype(np.float64).T
+        assert np.abs(R - Gd).max() <= 40 * m * e * np.linalg.norm(Gd)

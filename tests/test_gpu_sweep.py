@@ -387,3 +387,33 @@ def test_orderings_converge_to_lapack(ordering):
         sig = np.sort(np.abs(got["sigma"][k]))[::-1]
         assert np.max(np.abs(sig - ref)) <= 40 * ns[k] * 2.0 ** -53 * ref[0]
 
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_sparse_and_structured_bitwise(orc, dtype, mode):
+    """Matrices with many exact zeros (every zero pattern of the 2x2 pivots occurs),
+    rank-one and rank-deficient ones, wide exponent ranges, and signed zeros: two sweeps
+    bit for bit against the oracle."""
+    rng = np.random.default_rng(31)
+    mats = []
+    for n in (8, 16, 30, 64):
+        A = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.3)
+        mats.append(A)
+        u, v = rng.standard_normal(n), rng.standard_normal(n)
+        mats.append(np.outer(u, v))
+        B = rng.standard_normal((n, n))
+        B[:, n // 2:] = B[:, : n - n // 2] * 2.0          # rank n/2 exactly
+        mats.append(B)
+        C = rng.standard_normal((n, n)) * np.exp2(rng.integers(-60, 61, (n, n)))
+        mats.append(C)
+        D = np.where(rng.random((n, n)) < 0.5, -0.0, 0.0)
+        D[np.arange(n), np.arange(n)] = rng.standard_normal(n)
+        mats.append(D)
+    mats = [np.asfortranarray(m.astype(dtype)) for m in mats]
+    p, got = _run(mats, dtype, mode, max_sweeps=2, tolf=-1.0)
+    for k, G0 in enumerate(mats):
+        G, U, V, st, swp = orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0)
+        assert _same(got["G"][k], G), (mode, k, "G")
+        assert _same(got["U"][k], U), (mode, k, "U")
+        assert _same(got["V"][k], V), (mode, k, "V")
+
