@@ -232,7 +232,10 @@ int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, v
  *           Both visit every pair once per sweep, in different step orders.
  * All modes perform the same arithmetic in the same order: bitwise identical.
  * workspace: device memory of at least kog_sweep_workspace_size() bytes,
- * 256-byte aligned, owned by the caller, used only during the call's work.
+ * 256-byte aligned, owned by the caller, used only during the call's work
+ * (it includes a second buffer of G's size, sum of n^2 elements, through which
+ * the persistent modes update G two steps at a time under the modified modulus
+ * ordering).
  * Overflow: G is first multiplied by 2^s_G with s_G = e_nu - 2 - e_G - ceil(lg n)
  * when that is negative (e_G the largest exponent of its entries, e_nu that of
  * the largest finite value), so no two-sided update can overflow, and scaled

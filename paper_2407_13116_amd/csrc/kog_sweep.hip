@@ -21,7 +21,10 @@
 // kChunk consecutive steps are kept in a table, and U and V are brought up to
 // date once per chunk, a tile of rows at a time in LDS.  Each row of U or V
 // receives exactly the same rotations in the same order as with per-step
-// updates; deferring changes the memory traffic, not a single bit.
+// updates; deferring changes the memory traffic, not a single bit.  Under the
+// modified modulus ordering the persistent modes also update G two steps per
+// pass (the pairs of consecutive steps interlock; see g_fused_pair), again with
+// the same operations on every element.
 //
 // Executions of exactly the same arithmetic:
 //   mode 0  plain per-step launches: a pivot kernel and a G kernel per step,
@@ -65,6 +68,8 @@ struct SweepDesc {
   int32_t *scale;        // s_G of matrix m (0: not scaled)
   int32_t *nexp;         // t of matrix m: the norms are taken of G 2^-t
   int ord;               // pivot ordering: 0 round-robin, 1 modified modulus
+  const int64_t *aoff;   // offset of matrix m in galt
+  void *galt;            // a second buffer of G's size (the two-step G updates)
 };
 
 // Slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
@@ -109,9 +114,7 @@ template <class R> struct Piv {
   R u11, u21, u12, u22, v11, v21, v12, v22, s1, s2;
 };
 
-template <class R> __device__ inline Piv<R> pivot_svd(const R *G, int n, int i, int j) {
-  R gii = G[i + (int64_t)i * n], gji = G[j + (int64_t)i * n];
-  R gij = G[i + (int64_t)j * n], gjj = G[j + (int64_t)j * n];
+template <class R> __device__ inline Piv<R> pivot_svd_of(R gii, R gji, R gij, R gjj) {
   Svd2<R> r = svd2<R>(gii, gji, gij, gjj);
   R du = (r.info & I_DETU) ? (R)-1 : (R)1, dv = (r.info & I_DETV) ? (R)-1 : (R)1;
   Piv<R> p;
@@ -126,6 +129,11 @@ template <class R> __device__ inline Piv<R> pivot_svd(const R *G, int n, int i, 
   p.s1 = scale2(r.f1, r.e1);
   p.s2 = scale2(r.f2, r.e2);
   return p;
+}
+
+template <class R> __device__ inline Piv<R> pivot_svd(const R *G, int n, int i, int j) {
+  return pivot_svd_of(G[i + (int64_t)i * n], G[j + (int64_t)i * n], G[i + (int64_t)j * n],
+                      G[j + (int64_t)j * n]);
 }
 
 template <class R> __device__ inline R lin(R a, R x, R b, R y) { return fma(a, x, b * y); }
@@ -156,20 +164,38 @@ template <class R> __device__ inline void piv_store(R *slot, int np, int q, cons
 // columns (col_i' = col_i v11 + col_j v21, col_j' = col_i v12 + col_j v22);
 // the diagonal blocks become diag(sigma_1, sigma_2).
 
+// the four elements of a block, by row (i_p or j_p) and column (i_q or j_q)
+template <class R> struct Blk {
+  R ii, ji, ij, jj;
+};
+
+// block (p, q) of a step rotated: a = g(i_p, i_q), b = g(j_p, i_q), c = g(i_p, j_q),
+// d = g(j_p, j_q) before it
 template <class R>
-__device__ inline void g_block_store(R *G, int n, int ip, int jp, int iq, int jq, const R *S,
-                                     int np, int p, int q, R a, R b, R c, R d) {
+__device__ inline Blk<R> blk_rotate(const R *S, int np, int p, int q, R a, R b, R c, R d) {
   R u11 = S[C_U11 * np + p], u21 = S[C_U21 * np + p];
   R u12 = S[C_U12 * np + p], u22 = S[C_U22 * np + p];
   R v11 = S[C_V11 * np + q], v21 = S[C_V21 * np + q];
   R v12 = S[C_V12 * np + q], v22 = S[C_V22 * np + q];
   R a1 = lin(u11, a, u21, b), b1 = lin(u12, a, u22, b);
   R c1 = lin(u11, c, u21, d), d1 = lin(u12, c, u22, d);
+  Blk<R> o;
+  o.ii = lin(v11, a1, v21, c1);
+  o.ij = lin(v12, a1, v22, c1);
+  o.ji = lin(v11, b1, v21, d1);
+  o.jj = lin(v12, b1, v22, d1);
+  return o;
+}
+
+template <class R>
+__device__ inline void g_block_store(R *G, int n, int ip, int jp, int iq, int jq, const R *S,
+                                     int np, int p, int q, R a, R b, R c, R d) {
+  Blk<R> o = blk_rotate(S, np, p, q, a, b, c, d);
   R *ci = G + (int64_t)iq * n, *cj = G + (int64_t)jq * n;
-  ci[ip] = lin(v11, a1, v21, c1);
-  cj[ip] = lin(v12, a1, v22, c1);
-  ci[jp] = lin(v11, b1, v21, d1);
-  cj[jp] = lin(v12, b1, v22, d1);
+  ci[ip] = o.ii;
+  cj[ip] = o.ij;
+  ci[jp] = o.ji;
+  cj[jp] = o.jj;
 }
 
 template <class R>
@@ -182,9 +208,11 @@ __device__ inline void g_diag_store(R *G, int n, int i, int j, const R *S, int n
 
 // all np^2 blocks of one step by one workgroup of BS lanes, D blocks per lane
 // in flight: the loads are issued without branches (a lane past the end reads
-// block (0, 0) and stores nothing), so none of them waits for another
+// block (0, 0) and stores nothing), so none of them waits for another.  Reads
+// Gin and writes G (the same buffer, or another one of the same layout: every
+// element is written).
 template <class R, int BS, int D>
-__device__ void g_step_block(R *G, int n, const R *S, const int16_t *pr) {
+__device__ void g_step_block(const R *Gin, R *G, int n, const R *S, const int16_t *pr) {
   const int np = n >> 1;
   const int dp = BS % np, dq = BS / np;
   // block w = p + q np, walked with stride BS by carries
@@ -202,7 +230,7 @@ __device__ void g_step_block(R *G, int n, const R *S, const int16_t *pr) {
       jp[u] = pr[2 * ps + 1];
       iq[u] = pr[2 * qs];
       jq[u] = pr[2 * qs + 1];
-      const R *ci = G + (int64_t)iq[u] * n, *cj = G + (int64_t)jq[u] * n;
+      const R *ci = Gin + (int64_t)iq[u] * n, *cj = Gin + (int64_t)jq[u] * n;
       a[u] = ci[ip[u]];
       b[u] = ci[jp[u]];
       c[u] = cj[ip[u]];
@@ -221,6 +249,207 @@ __device__ void g_step_block(R *G, int n, const R *S, const int16_t *pr) {
       else
         g_block_store(G, n, ip[u], jp[u], iq[u], jq[u], S, np, pp[u], qq[u], a[u], b[u], c[u],
                       d[u]);
+    }
+  }
+}
+
+// ------------------------------------------------ two steps of G in one pass
+//
+// Under the modified modulus ordering (m = n - 1, c = c_k with 2c = k mod m),
+// slot q >= 1 of step k pairs A_q = c + q with B_q = c - q (mod m), and slot 0
+// pairs A_0 = m with B_0 = c.  As 2 c_(k+1) = 2c + 1 (mod m), the pairs of step
+// k + 1 are {A_d, B_(d-1)}: slot np - d for d = 1 .. np - 1, and {A_0,
+// B_(np-1)} in slot 0.  So block (d, e) of step k + 1 (rows {A_d, B_(d-1)},
+// columns {A_e, B_(e-1)}) holds one element of each of the step-k blocks
+// (d, e), (d, e-1), (d-1, e) and (d-1, e-1) after step k.  One pass over G
+// forms every step-k block and, from four of them, every block of step k + 1:
+// G is read once and written once per two steps instead of twice, and every
+// element goes through exactly the operations of two separate steps, in the
+// same order (the same bits).  The pivots of step k + 1 are formed first, by
+// the same element formulas.
+
+// A and B indices of slot q of step k (c = c_k)
+__device__ inline void mm_ab(int m, int c, int q, int &A, int &B) {
+  int a = c + q, b = c - q;
+  a = a >= m ? a - m : a;
+  b = b < 0 ? b + m : b;
+  A = q == 0 ? m : a;
+  B = q == 0 ? c : b;
+}
+
+__device__ inline int mm_center(int n, int k) {
+  const int m = n - 1;
+  return (k & 1) ? (k + m) >> 1 : k >> 1;
+}
+
+// a 2x2 block given by A/B row and A/B column (xAB = element (A row, B column))
+// to its i/j form (a = (i, i), b = (j, i), c = (i, j), d = (j, j)); rai: the A
+// row is the smaller index of its pair, cai likewise for the columns
+template <class R>
+__device__ inline void ab_to_ij(bool rai, bool cai, R xAA, R xAB, R xBA, R xBB, R &a, R &b,
+                                R &c, R &d) {
+  R rAi = cai ? xAA : xAB, rAj = cai ? xAB : xAA;  // row A at columns i, j
+  R rBi = cai ? xBA : xBB, rBj = cai ? xBB : xBA;
+  a = rai ? rAi : rBi;
+  b = rai ? rBi : rAi;
+  c = rai ? rAj : rBj;
+  d = rai ? rBj : rAj;
+}
+
+template <class R> struct Wab {
+  R AA, AB, BA, BB;
+};
+
+// step-k block (p, q) after step k by A/B row and column (aip, aiq: A is the
+// smaller index of slot p, q), from its elements before it (a = (i_p, i_q),
+// b = (j_p, i_q), c = (i_p, j_q), d = (j_p, j_q))
+template <class R>
+__device__ inline Wab<R> blk_after(const R *S, int np, int p, int q, bool aip, bool aiq, R a,
+                                   R b, R c, R d) {
+  Blk<R> o;
+  if (p == q) {  // the pivot block becomes diag(sigma_1, sigma_2)
+    o.ii = S[C_S1 * np + p];
+    o.jj = S[C_S2 * np + p];
+    o.ij = (R)0;
+    o.ji = (R)0;
+  } else {
+    o = blk_rotate(S, np, p, q, a, b, c, d);
+  }
+  R rAi = aip ? o.ii : o.ji, rAj = aip ? o.ij : o.jj;
+  R rBi = aip ? o.ji : o.ii, rBj = aip ? o.jj : o.ij;
+  Wab<R> w;
+  w.AA = aiq ? rAi : rAj;
+  w.AB = aiq ? rAj : rAi;
+  w.BA = aiq ? rBi : rBj;
+  w.BB = aiq ? rBj : rBi;
+  return w;
+}
+
+// the pivots of step k + 1 from G before step k and the parameters S1 of step
+// k: pair d = {A_d, B_(d-1)} has the diagonal elements sigma of A_d (slot d)
+// and of B_(d-1) (slot d - 1), and its off-diagonal elements in the step-k
+// blocks (d, d-1) and (d-1, d).  Parameters to S2 (LDS) and slot2 (table).
+template <class R, int BS>
+__device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R *slot2) {
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+  for (int dd = threadIdx.x; dd < np; dd += BS) {
+    const int dm = dd == 0 ? np - 1 : dd - 1;
+    int Ad, Bd, Am, Bm;
+    mm_ab(m, c, dd, Ad, Bd);
+    mm_ab(m, c, dm, Am, Bm);
+    const bool aid = Ad < Bd, aim = Am < Bm;
+    const R gAA = aid ? S1[C_S1 * np + dd] : S1[C_S2 * np + dd];
+    const R gBB = aim ? S1[C_S2 * np + dm] : S1[C_S1 * np + dm];
+    const int id = min(Ad, Bd), jd = max(Ad, Bd), im = min(Am, Bm), jm = max(Am, Bm);
+    const R *cim = Gin + (int64_t)im * n, *cjm = Gin + (int64_t)jm * n;
+    const R *cid = Gin + (int64_t)id * n, *cjd = Gin + (int64_t)jd * n;
+    Wab<R> w1 = blk_after(S1, np, dd, dm, aid, aim, cim[id], cim[jd], cjm[id], cjm[jd]);
+    Wab<R> w2 = blk_after(S1, np, dm, dd, aim, aid, cid[im], cid[jm], cjd[im], cjd[jm]);
+    const R gAB = w1.AB, gBA = w2.BA;  // (A_d, B_(d-1)) and (B_(d-1), A_d)
+    const bool rai = Ad < Bm;
+    const R gii = rai ? gAA : gBB, gjj = rai ? gBB : gAA;
+    const R gij = rai ? gAB : gBA, gji = rai ? gBA : gAB;
+    Piv<R> P = pivot_svd_of(gii, gji, gij, gjj);
+    const int q2 = dd == 0 ? 0 : np - dd;
+    piv_store(S2, np, q2, P);
+    piv_store(slot2, np, q2, P);
+  }
+}
+
+// Steps k and k + 1 from Gin to G (another buffer: blocks of step k + 1 read
+// elements that other lanes write).  A wave takes up to 63 consecutive row
+// slots p and a segment of column slots: lane l forms the step-k blocks of
+// row slot p = d0 + l - 1 one column slot e after the other, e from e0 - 1
+// on; lanes 1.. own the output row pairs p, whose B row (B_(p-1)) the lane
+// below formed, and column e's B column (B_(e-1)) comes from the previous
+// column slot.  Row and column halos are formed twice (one row slot per 63,
+// one column slot per segment).  Loads run kAhead column slots ahead.
+template <class R, int BS, int kAhead>
+__device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, const R *S2) {
+  constexpr int NW = BS / 64;
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rw = (np + 62) / 63;  // row chunks of at most 63 output pairs
+  const int lr = (np + rw - 1) / rw;
+  const int cs = max(1, min(NW / rw, np / 8));  // column segments
+  const int ls = (np + cs - 1) / cs;
+  for (int u = wv; u < rw * cs; u += NW) {
+    const int d0 = (u % rw) * lr, e0 = (u / rw) * ls;
+    const int dn = min(lr, np - d0), e1 = min(np, e0 + ls);
+    if (dn <= 0 || e0 >= e1) continue;  // the same for the whole wave
+    const bool act = lane <= dn, own = act && lane >= 1;
+    int p = d0 + lane - 1;
+    p = act ? (p < 0 ? p + np : p) : 0;
+    int Ap, Bp, Aq, Bq;
+    mm_ab(m, c, p, Ap, Bp);
+    mm_ab(m, c, p == 0 ? np - 1 : p - 1, Aq, Bq);
+    const bool aip = Ap < Bp;
+    const int rA = Ap, rB = Bq;  // output row pair p of step k + 1
+    const bool rai = rA < rB;
+    const int i2 = rai ? rA : rB, j2 = rai ? rB : rA;
+    const int q2r = p == 0 ? 0 : np - p;
+    const int cnt = e1 - e0 + 1;
+    auto slot_of = [&](int t) {
+      int e = e0 - 1 + t;
+      return e < 0 ? e + np : e;
+    };
+    const int ip = min(Ap, Bp), jp = max(Ap, Bp);
+    // the step-k block (p, e) in i/j form
+    auto load = [&](int e, R &a, R &b, R &cc, R &dd) {
+      int Ae, Be;
+      mm_ab(m, c, e, Ae, Be);
+      const R *ci = Gin + (int64_t)min(Ae, Be) * n, *cj = Gin + (int64_t)max(Ae, Be) * n;
+      a = b = cc = dd = (R)0;
+      if (act) {
+        a = ci[ip];
+        b = ci[jp];
+        cc = cj[ip];
+        dd = cj[jp];
+      }
+    };
+    R f[kAhead][4];
+#pragma unroll
+    for (int z = 0; z < kAhead; ++z)
+      if (z < cnt) load(slot_of(z), f[z][0], f[z][1], f[z][2], f[z][3]);
+    R pAB = (R)0, pBB = (R)0;
+    int pB = 0;
+    for (int t0 = 0; t0 < cnt; t0 += kAhead) {
+#pragma unroll
+      for (int z = 0; z < kAhead; ++z) {
+        const int t = t0 + z;
+        if (t >= cnt) break;
+        R x0 = f[z][0], x1 = f[z][1], x2 = f[z][2], x3 = f[z][3];
+        if (t + kAhead < cnt) load(slot_of(t + kAhead), f[z][0], f[z][1], f[z][2], f[z][3]);
+        const int e = slot_of(t);
+        int Ae, Be;
+        mm_ab(m, c, e, Ae, Be);
+        const bool aie = Ae < Be;
+        Wab<R> w = blk_after(S1, np, p, e, aip, aie, x0, x1, x2, x3);
+        const R uBA = __shfl_up(w.BA, 1), uBB = __shfl_up(w.BB, 1);
+        if (t > 0 && own) {
+          // output block (p, e): columns A_e and B_(e-1)
+          const int cA = Ae, cB = pB;
+          const bool cai = cA < cB;
+          R *ci = G + (int64_t)(cai ? cA : cB) * n, *cj = G + (int64_t)(cai ? cB : cA) * n;
+          if (p == e) {
+            ci[i2] = S2[C_S1 * np + q2r];
+            cj[j2] = S2[C_S2 * np + q2r];
+            cj[i2] = (R)0;
+            ci[j2] = (R)0;
+          } else {
+            R a, b, cc, dd;
+            ab_to_ij(rai, cai, w.AA, pAB, uBA, pBB, a, b, cc, dd);
+            Blk<R> o = blk_rotate(S2, np, q2r, e == 0 ? 0 : np - e, a, b, cc, dd);
+            ci[i2] = o.ii;
+            cj[i2] = o.ij;
+            ci[j2] = o.ji;
+            cj[j2] = o.jj;
+          }
+        }
+        pAB = w.AB;
+        pBB = uBB;
+        pB = Be;
+      }
     }
   }
 }
@@ -559,13 +788,14 @@ __global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, R *G, R *sigma,
 // ------------------------------------------------------- mode 1: persistent
 //
 // One workgroup per matrix (the launch covers the matrices listed in `mats`,
-// longest first).  LDS holds the reduction buffer, the step's pivot
-// parameters and pair table, and the U/V row tile; G stays in global memory
-// (L2/MALL resident while it is hot); the chunk's rotation table is in the
-// workspace.
+// longest first).  LDS holds the reduction buffer, the pivot parameters of
+// one or two steps and the pair table, and the U/V row tile; G stays in
+// global memory (two steps at a time go from G to a second buffer in the
+// workspace and back); the chunk's rotation table is in the workspace.
 
 template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int maxn) {
-  size_t b = kRed * sizeof(double) + (size_t)(maxn / 2) * kPivComp * sizeof(R) + (size_t)maxn * 2;
+  size_t b = kRed * sizeof(double) + 2 * (size_t)(maxn / 2) * kPivComp * sizeof(R) +
+             (size_t)maxn * 2;
   return (b + 15) & ~(size_t)15;
 }
 
@@ -578,8 +808,8 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   extern __shared__ __align__(16) unsigned char smem[];
   double *red = reinterpret_cast<double *>(smem);
   R *spar = reinterpret_cast<R *>(smem + kRed * sizeof(double));
-  int16_t *spair = reinterpret_cast<int16_t *>(smem + kRed * sizeof(double) +
-                                               (size_t)(maxn / 2) * kPivComp * sizeof(R));
+  R *spar2 = spar + (size_t)(maxn / 2) * kPivComp;
+  int16_t *spair = reinterpret_cast<int16_t *>(spar2 + (size_t)(maxn / 2) * kPivComp);
   R *T = reinterpret_cast<R *>(smem + persistent_fixed_lds<R>(maxn));
   int m = mats[blockIdx.x];
   int n = d.n[m];
@@ -592,34 +822,52 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red, sg, nt);
   const double nsc = ldexp(1.0, -nt);
   __syncthreads();
+  // under the modified modulus ordering steps go in pairs through G and a
+  // second buffer; the sweep's last step (n - 1 steps, an odd count) lands in G
+  const bool pairs2 = d.ord == 1 && n >= 4;
+  R *Ga = pairs2 ? reinterpret_cast<R *>(d.galt) + d.aoff[m] : Gm;
   int sw = 0;
   bool conv = false;
   for (; sw < max_sweeps && !conv; ++sw) {
-    for (int k = 0; k < n - 1; ++k) {
+    const R *cur = Gm;
+    for (int k = 0; k < n - 1;) {
       R *slot = tab + (size_t)(k % kChunk) * kPivComp * np;
       for (int q = threadIdx.x; q < np; q += BS) {
         int i, j;
         piv_pair(d.ord, n, k, q, i, j);
         spair[2 * q] = (int16_t)i;
         spair[2 * q + 1] = (int16_t)j;
-        Piv<R> P = pivot_svd(Gm, n, i, j);
+        Piv<R> P = pivot_svd(cur, n, i, j);
         piv_store(spar, np, q, P);
         piv_store(slot, np, q, P);
       }
       __syncthreads();
-      // 1024 lanes keep 16 waves per CU in flight: two blocks each suffice and
-      // stay within the 128 registers that size allows
-      g_step_block<R, BS, (BS >= 1024 ? 2 : 4)>(Gm, n, spar, spair);
+      if (pairs2 && k + 2 <= n - 2) {
+        g_pivots_next<R, BS>(cur, n, k, spar, spar2,
+                             tab + (size_t)((k + 1) % kChunk) * kPivComp * np);
+        __syncthreads();
+        R *nxt = cur == Gm ? Ga : Gm;
+        g_fused_pair<R, BS, sizeof(R) == 8 ? 4 : 6>(cur, nxt, n, k, spar, spar2);
+        cur = nxt;
+        k += 2;
+      } else {
+        // 1024 lanes keep 16 waves per CU in flight: two blocks each suffice and
+        // stay within the 128 registers that size allows
+        g_step_block<R, BS, (BS >= 1024 ? 2 : 4)>(cur, Gm, n, spar, spair);
+        cur = Gm;
+        k += 1;
+      }
       __syncthreads();
-      if (k % kChunk == kChunk - 1 || k == n - 2) {
-        int k0 = chunk_begin(k);
+      const int kl = k - 1;  // the last step done
+      if (kl % kChunk == kChunk - 1 || kl == n - 2) {
+        int k0 = chunk_begin(kl);
         for (int side = 0; side < 2; ++side) {
           R *M = side ? Vm : Um;
           for (int r0 = 0; r0 < n; r0 += rows) {
             int nr = min(rows, n - r0);
             tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
-            tile_rotate(T, n, nr, k0, k, tab, side != 0, d.ord);
+            tile_rotate(T, n, nr, k0, kl, tab, side != 0, d.ord);
             __syncthreads();
             tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
@@ -795,10 +1043,12 @@ __global__ __launch_bounds__(kRed) void k_sw_sort(SweepDesc d, R *U, R *V, R *si
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t n, off, soff, poff, order, fro2, sweeps, done, scale, nexp, par, pairs, total;
+  size_t n, off, soff, poff, order, fro2, sweeps, done, scale, nexp, aoff, par, pairs, galt,
+      total;
 };
 
-static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
+// nsq: the sum of n^2 (the second G buffer of the persistent modes)
+static WsLayout ws_layout(int64_t nmat, int64_t npiv, int64_t nsq, size_t w) {
   WsLayout L;
   size_t p = 0;
   L.n = p;      p = align256(p + nmat * 4);
@@ -811,8 +1061,10 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
   L.done = p;   p = align256(p + nmat * 4);
   L.scale = p;  p = align256(p + nmat * 4);
   L.nexp = p;   p = align256(p + nmat * 4);
+  L.aoff = p;   p = align256(p + nmat * 8);
   L.par = p;    p = align256(p + (size_t)kChunk * npiv * 10 * w);
   L.pairs = p;  p = align256(p + (size_t)kChunk * npiv * 4);
+  L.galt = p;   p = align256(p + (size_t)nsq * w);
   L.total = p;
   return L;
 }
@@ -821,7 +1073,7 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, size_t w) {
 struct Tune {
   int block[2][5];
 };
-static Tune g_tune = {{{256, 256, 512, 1024, 1024}, {256, 256, 512, 1024, 1024}}};
+static Tune g_tune = {{{256, 512, 1024, 1024, 1024}, {256, 512, 1024, 1024, 1024}}};
 static std::mutex g_mu;
 
 static int bucket_of(int n) {
@@ -940,9 +1192,9 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   const size_t w = sizeof(R);
   KSVD2_REQ(G, w); KSVD2_REQ(U, w); KSVD2_REQ(V, w); KSVD2_REQ(ws, 256);
   KSVD2_OPT(sigma, w); KSVD2_OPT(sweeps_out, 4);
-  int64_t npiv = 0, stot = 0;
+  int64_t npiv = 0, stot = 0, nsq = 0;
   int maxn = 0;
-  std::vector<int64_t> soff(nmat), poff(nmat);
+  std::vector<int64_t> soff(nmat), poff(nmat), aoff(nmat);
   for (int64_t m = 0; m < nmat; ++m) {
     int n = n_host[m];
     if (n < 2 || (n & 1) || n > kMaxOrder)
@@ -951,11 +1203,13 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     if (off_host[m] < 0) return fail(KSVD2_EINVAL, "matrix %lld: negative offset", (long long)m);
     soff[m] = stot;
     poff[m] = npiv;
+    aoff[m] = nsq;
+    nsq += (int64_t)n * n;
     stot += n;
     npiv += n / 2;
     maxn = std::max(maxn, n);
   }
-  WsLayout L = ws_layout(nmat, npiv, w);
+  WsLayout L = ws_layout(nmat, npiv, nsq, w);
   if (ws_bytes < L.total)
     return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   // longest matrices first (they have the most steps)
@@ -970,6 +1224,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   std::memcpy(host.data() + L.soff, soff.data(), nmat * 8);
   std::memcpy(host.data() + L.poff, poff.data(), nmat * 8);
   std::memcpy(host.data() + L.order, order.data(), nmat * 4);
+  std::memcpy(host.data() + L.aoff, aoff.data(), nmat * 8);
   unsigned char *wsb = static_cast<unsigned char *>(ws);
   hipError_t e = hipMemcpyAsync(wsb, host.data(), L.par, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(KSVD2_EHIP, "descriptor upload: %s", hipGetErrorString(e));
@@ -984,6 +1239,8 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.scale = reinterpret_cast<int32_t *>(wsb + L.scale);
   d.nexp = reinterpret_cast<int32_t *>(wsb + L.nexp);
   d.ord = ordering;
+  d.aoff = reinterpret_cast<const int64_t *>(wsb + L.aoff);
+  d.galt = wsb + L.galt;
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
   R *par = reinterpret_cast<R *>(wsb + L.par);
@@ -1205,9 +1462,13 @@ extern "C" {
 
 size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host) {
   if (nmat <= 0 || !n_host || (dtype != 0 && dtype != 1)) return 0;
-  int64_t npiv = 0;
-  for (int64_t m = 0; m < nmat; ++m) npiv += std::max(n_host[m], 0) / 2;
-  size_t a = ws_layout(nmat, npiv, dtype ? 8 : 4).total;
+  int64_t npiv = 0, nsq = 0;
+  for (int64_t m = 0; m < nmat; ++m) {
+    int64_t nm = std::max(n_host[m], 0);
+    npiv += nm / 2;
+    nsq += nm * nm;
+  }
+  size_t a = ws_layout(nmat, npiv, nsq, dtype ? 8 : 4).total;
   size_t b = align256(nmat * 4) + align256(nmat * 8) * 2;
   return std::max(a, b);
 }
