@@ -172,11 +172,8 @@ template <class R> struct Blk {
 // block (p, q) of a step rotated: a = g(i_p, i_q), b = g(j_p, i_q), c = g(i_p, j_q),
 // d = g(j_p, j_q) before it
 template <class R>
-__device__ inline Blk<R> blk_rotate(const R *S, int np, int p, int q, R a, R b, R c, R d) {
-  R u11 = S[C_U11 * np + p], u21 = S[C_U21 * np + p];
-  R u12 = S[C_U12 * np + p], u22 = S[C_U22 * np + p];
-  R v11 = S[C_V11 * np + q], v21 = S[C_V21 * np + q];
-  R v12 = S[C_V12 * np + q], v22 = S[C_V22 * np + q];
+__device__ inline Blk<R> blk_rot(R u11, R u21, R u12, R u22, R v11, R v21, R v12, R v22, R a,
+                                 R b, R c, R d) {
   R a1 = lin(u11, a, u21, b), b1 = lin(u12, a, u22, b);
   R c1 = lin(u11, c, u21, d), d1 = lin(u12, c, u22, d);
   Blk<R> o;
@@ -185,6 +182,12 @@ __device__ inline Blk<R> blk_rotate(const R *S, int np, int p, int q, R a, R b, 
   o.ji = lin(v11, b1, v21, d1);
   o.jj = lin(v12, b1, v22, d1);
   return o;
+}
+template <class R>
+__device__ inline Blk<R> blk_rotate(const R *S, int np, int p, int q, R a, R b, R c, R d) {
+  return blk_rot(S[C_U11 * np + p], S[C_U21 * np + p], S[C_U12 * np + p], S[C_U22 * np + p],
+                 S[C_V11 * np + q], S[C_V21 * np + q], S[C_V12 * np + q], S[C_V22 * np + q], a,
+                 b, c, d);
 }
 
 template <class R>
@@ -356,6 +359,47 @@ __device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R 
   }
 }
 
+// Raw buffer access to one matrix: byte offsets as a per-lane part and a
+// wave-uniform (column) part; an offset at or past the end (kOff) reads zero
+// and stores nothing, without a memory access.
+constexpr int kOff = 0x40000000;
+template <class R> struct Buf;
+template <> struct Buf<double> {
+  typedef unsigned int V __attribute__((ext_vector_type(2)));
+  __amdgpu_buffer_rsrc_t r;
+  __device__ Buf(const double *p, int bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, bytes,
+                                            0x00020000)) {}
+  __device__ double ld(int vo, int so) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  __device__ void st(double x, int vo, int so) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, vo, so, 0);
+  }
+};
+template <> struct Buf<float> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ Buf(const float *p, int bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, bytes,
+                                            0x00020000)) {}
+  __device__ float ld(int vo, int so) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+  __device__ void st(float x, int vo, int so) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, vo, so, 0);
+  }
+};
+
+// lane l receives lane l - 1's value (a wave shift; every lane active)
+__device__ inline float lane_up(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ inline double lane_up(double x) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Steps k and k + 1 from Gin to G (another buffer: blocks of step k + 1 read
 // elements that other lanes write).  A wave takes up to 63 consecutive row
 // slots p and a segment of column slots: lane l forms the step-k blocks of
@@ -363,16 +407,26 @@ __device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R 
 // on; lanes 1.. own the output row pairs p, whose B row (B_(p-1)) the lane
 // below formed, and column e's B column (B_(e-1)) comes from the previous
 // column slot.  Row and column halos are formed twice (one row slot per 63,
-// one column slot per segment).  Loads run kAhead column slots ahead.
+// one column slot per segment).  Loads run kAhead column slots ahead; the
+// walk is padded to a multiple of kAhead (the padding re-reads the last
+// column and stores nothing), so its body has no branches but the wave-
+// uniform one around the stores.  Pivot blocks take their diag(sigma) by
+// selection, inactive lanes load and store nothing through the buffer's
+// range check.
 template <class R, int BS, int kAhead>
 __device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, const R *S2) {
   constexpr int NW = BS / 64;
+  constexpr int W = (int)sizeof(R);
   const int np = n >> 1, m = n - 1, c = mm_center(n, k);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is the same for all lanes of a wave: saying so keeps the
+  // column offsets in scalar registers
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rw = (np + 62) / 63;  // row chunks of at most 63 output pairs
   const int lr = (np + rw - 1) / rw;
   const int cs = max(1, min(NW / rw, np / 8));  // column segments
   const int ls = (np + cs - 1) / cs;
+  const int cb = n * W;  // bytes per column
+  const Buf<R> in(Gin, n * cb), out(G, n * cb);
   for (int u = wv; u < rw * cs; u += NW) {
     const int d0 = (u % rw) * lr, e0 = (u / rw) * ls;
     const int dn = min(lr, np - d0), e1 = min(np, e0 + ls);
@@ -386,70 +440,262 @@ __device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, cons
     const bool aip = Ap < Bp;
     const int rA = Ap, rB = Bq;  // output row pair p of step k + 1
     const bool rai = rA < rB;
-    const int i2 = rai ? rA : rB, j2 = rai ? rB : rA;
     const int q2r = p == 0 ? 0 : np - p;
+    const int vip = act ? min(Ap, Bp) * W : kOff, vjp = act ? max(Ap, Bp) * W : kOff;
+    const int vi2 = own ? min(rA, rB) * W : kOff, vj2 = own ? max(rA, rB) * W : kOff;
+    // the lane's row parameters: step k, slot p; step k + 1, slot q2r
+    const R u11 = S1[C_U11 * np + p], u21 = S1[C_U21 * np + p];
+    const R u12 = S1[C_U12 * np + p], u22 = S1[C_U22 * np + p];
+    const R s1p = S1[C_S1 * np + p], s2p = S1[C_S2 * np + p];
+    const R y11 = S2[C_U11 * np + q2r], y21 = S2[C_U21 * np + q2r];
+    const R y12 = S2[C_U12 * np + q2r], y22 = S2[C_U22 * np + q2r];
+    const R t1p = S2[C_S1 * np + q2r], t2p = S2[C_S2 * np + q2r];
     const int cnt = e1 - e0 + 1;
+    const int nt = (cnt + kAhead - 1) / kAhead * kAhead;
     auto slot_of = [&](int t) {
-      int e = e0 - 1 + t;
+      int e = e0 - 1 + min(t, cnt - 1);
       return e < 0 ? e + np : e;
     };
-    const int ip = min(Ap, Bp), jp = max(Ap, Bp);
-    // the step-k block (p, e) in i/j form
-    auto load = [&](int e, R &a, R &b, R &cc, R &dd) {
+    auto load = [&](int t, R *x) {
       int Ae, Be;
-      mm_ab(m, c, e, Ae, Be);
-      const R *ci = Gin + (int64_t)min(Ae, Be) * n, *cj = Gin + (int64_t)max(Ae, Be) * n;
-      a = b = cc = dd = (R)0;
-      if (act) {
-        a = ci[ip];
-        b = ci[jp];
-        cc = cj[ip];
-        dd = cj[jp];
-      }
+      mm_ab(m, c, slot_of(t), Ae, Be);
+      const int si = min(Ae, Be) * cb, sj = max(Ae, Be) * cb;
+      x[0] = in.ld(vip, si);
+      x[1] = in.ld(vjp, si);
+      x[2] = in.ld(vip, sj);
+      x[3] = in.ld(vjp, sj);
     };
     R f[kAhead][4];
 #pragma unroll
-    for (int z = 0; z < kAhead; ++z)
-      if (z < cnt) load(slot_of(z), f[z][0], f[z][1], f[z][2], f[z][3]);
+    for (int z = 0; z < kAhead; ++z) load(z, f[z]);
     R pAB = (R)0, pBB = (R)0;
     int pB = 0;
-    for (int t0 = 0; t0 < cnt; t0 += kAhead) {
+    for (int t0 = 0; t0 < nt; t0 += kAhead) {
 #pragma unroll
       for (int z = 0; z < kAhead; ++z) {
         const int t = t0 + z;
-        if (t >= cnt) break;
-        R x0 = f[z][0], x1 = f[z][1], x2 = f[z][2], x3 = f[z][3];
-        if (t + kAhead < cnt) load(slot_of(t + kAhead), f[z][0], f[z][1], f[z][2], f[z][3]);
+        const R x0 = f[z][0], x1 = f[z][1], x2 = f[z][2], x3 = f[z][3];
+        load(t + kAhead, f[z]);
         const int e = slot_of(t);
         int Ae, Be;
         mm_ab(m, c, e, Ae, Be);
         const bool aie = Ae < Be;
-        Wab<R> w = blk_after(S1, np, p, e, aip, aie, x0, x1, x2, x3);
-        const R uBA = __shfl_up(w.BA, 1), uBB = __shfl_up(w.BB, 1);
-        if (t > 0 && own) {
-          // output block (p, e): columns A_e and B_(e-1)
+        // step-k block (p, e) after step k, by A/B row and column
+        Blk<R> o = blk_rot(u11, u21, u12, u22, S1[C_V11 * np + e], S1[C_V21 * np + e],
+                           S1[C_V12 * np + e], S1[C_V22 * np + e], x0, x1, x2, x3);
+        const bool dg = p == e;
+        const R oii = dg ? s1p : o.ii, ojj = dg ? s2p : o.jj;
+        const R oij = dg ? (R)0 : o.ij, oji = dg ? (R)0 : o.ji;
+        const R rAi = aip ? oii : oji, rAj = aip ? oij : ojj;
+        const R rBi = aip ? oji : oii, rBj = aip ? ojj : oij;
+        const R wAA = aie ? rAi : rAj, wAB = aie ? rAj : rAi;
+        const R wBA = aie ? rBi : rBj, wBB = aie ? rBj : rBi;
+        const R uBA = lane_up(wBA), uBB = lane_up(wBB);
+        if (t > 0 && t < cnt) {
+          // output block (p, e) of step k + 1: columns A_e and B_(e-1)
           const int cA = Ae, cB = pB;
           const bool cai = cA < cB;
-          R *ci = G + (int64_t)(cai ? cA : cB) * n, *cj = G + (int64_t)(cai ? cB : cA) * n;
-          if (p == e) {
-            ci[i2] = S2[C_S1 * np + q2r];
-            cj[j2] = S2[C_S2 * np + q2r];
-            cj[i2] = (R)0;
-            ci[j2] = (R)0;
-          } else {
-            R a, b, cc, dd;
-            ab_to_ij(rai, cai, w.AA, pAB, uBA, pBB, a, b, cc, dd);
-            Blk<R> o = blk_rotate(S2, np, q2r, e == 0 ? 0 : np - e, a, b, cc, dd);
-            ci[i2] = o.ii;
-            cj[i2] = o.ij;
-            ci[j2] = o.ji;
-            cj[j2] = o.jj;
-          }
+          const int siq = min(cA, cB) * cb, sjq = max(cA, cB) * cb;
+          const int q2c = e == 0 ? 0 : np - e;
+          R a, b, cc, dd;
+          ab_to_ij(rai, cai, wAA, pAB, uBA, pBB, a, b, cc, dd);
+          Blk<R> o2 = blk_rot(y11, y21, y12, y22, S2[C_V11 * np + q2c], S2[C_V21 * np + q2c],
+                              S2[C_V12 * np + q2c], S2[C_V22 * np + q2c], a, b, cc, dd);
+          out.st(dg ? t1p : o2.ii, vi2, siq);
+          out.st(dg ? (R)0 : o2.ij, vi2, sjq);
+          out.st(dg ? (R)0 : o2.ji, vj2, siq);
+          out.st(dg ? t2p : o2.jj, vj2, sjq);
         }
-        pAB = w.AB;
+        pAB = wAB;
         pBB = uBB;
         pB = Be;
       }
+    }
+  }
+}
+
+// The same two steps in place, for orders up to 256 (np <= 128 slots): one
+// wave holds every row slot (lane l the S consecutive slots l S .. l S + S - 1;
+// the B row of a lane's first output pair comes from the lane before it, that
+// of lane 0 from the last slot np - 1), and the waves split the column slots
+// into segments.  A wave's loads then only read columns that no other wave
+// writes, and it writes a column only after its own last read of it, except
+// for the boundary column slot between two segments (the last of one, read
+// before the next one's first output pair writes its B column; the pre-step
+// of the next, whose A column the first writes): both waves take that slot
+// from a copy in LDS made before the pass.  kAhead S = 4 blocks are loaded
+// ahead per lane.
+struct FusedGeo {
+  int cs, ls;  // column segments and slots per segment
+};
+__device__ inline FusedGeo fused_geo(int n, int nw, int snap_elems) {
+  const int np = n >> 1;
+  FusedGeo g;
+  g.cs = max(1, min(min(nw, max(1, np / 4)), snap_elems / (2 * n)));
+  g.ls = (np + g.cs - 1) / g.cs;
+  g.cs = (np + g.ls - 1) / g.ls;
+  return g;
+}
+
+// columns A and B of each boundary slot (the pre-step slot of each segment)
+template <class R, int BS>
+__device__ void g_fused_snapshot(const R *G, int n, int k, FusedGeo g, R *snap) {
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+  for (int x = threadIdx.x; x < g.cs * 2 * n; x += BS) {
+    const int sg = x / (2 * n), r = x - sg * 2 * n, side = r / n, row = r - side * n;
+    int b = sg * g.ls - 1;
+    b = b < 0 ? b + np : b;
+    int A, B;
+    mm_ab(m, c, b, A, B);
+    snap[x] = G[row + (int64_t)(side ? B : A) * n];
+  }
+}
+
+template <class R, int BS, int S>
+__device__ void g_fused_inplace(R *G, int n, int k, const R *S1, const R *S2, FusedGeo g,
+                                const R *snap) {
+  constexpr int W = (int)sizeof(R);
+  constexpr int kAhead = 4 / S;
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+  const int lane = threadIdx.x & 63, sg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (sg >= g.cs) return;  // this wave has no segment (the same for all its lanes)
+  const int L = (np + S - 1) / S;  // lanes holding slots
+  const int cb = n * W;
+  const Buf<R> buf(G, n * cb);
+  const int e0 = sg * g.ls, e1 = min(np, e0 + g.ls), cnt = e1 - e0 + 1;
+  const int sgn = sg + 1 == g.cs ? 0 : sg + 1;
+  const int pred = lane == 0 ? L - 1 : lane - 1;
+  const int slast = lane == L - 1 ? np - 1 - (L - 1) * S : S - 1;
+  int pp[S], vip[S], vjp[S], vi2[S], vj2[S], sip[S], sjp[S], q2r[S];
+  bool aip[S], rai[S], val[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int p = lane * S + s;
+    val[s] = lane < L && p < np;
+    pp[s] = val[s] ? p : 0;
+    int Ap, Bp, Aq, Bq;
+    mm_ab(m, c, pp[s], Ap, Bp);
+    mm_ab(m, c, pp[s] == 0 ? np - 1 : pp[s] - 1, Aq, Bq);
+    aip[s] = Ap < Bp;
+    rai[s] = Ap < Bq;  // output pair p: rows A_p and B_(p-1)
+    sip[s] = min(Ap, Bp);
+    sjp[s] = max(Ap, Bp);
+    vip[s] = val[s] ? sip[s] * W : kOff;
+    vjp[s] = val[s] ? sjp[s] * W : kOff;
+    vi2[s] = val[s] ? min(Ap, Bq) * W : kOff;
+    vj2[s] = val[s] ? max(Ap, Bq) * W : kOff;
+    q2r[s] = pp[s] == 0 ? 0 : np - pp[s];
+  }
+  const int nt = (cnt + kAhead - 1) / kAhead * kAhead;
+  auto slot_of = [&](int t) {
+    int e = e0 - 1 + min(t, cnt - 1);
+    return e < 0 ? e + np : e;
+  };
+  // the blocks of column slot t (nothing is read for the boundary slots)
+  auto load = [&](int t, R (*x)[4]) {
+    int Ae, Be;
+    mm_ab(m, c, slot_of(t), Ae, Be);
+    const bool edge = t == 0 || t >= cnt - 1;
+    const int si = min(Ae, Be) * cb, sj = max(Ae, Be) * cb;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int oi = edge ? kOff : vip[s], oj = edge ? kOff : vjp[s];
+      x[s][0] = buf.ld(oi, si);
+      x[s][1] = buf.ld(oj, si);
+      x[s][2] = buf.ld(oi, sj);
+      x[s][3] = buf.ld(oj, sj);
+    }
+  };
+  R f[kAhead][S][4];
+#pragma unroll
+  for (int z = 0; z < kAhead; ++z) load(z, f[z]);
+  R pAB[S], pBB[S], pBBu = (R)0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) pAB[s] = pBB[s] = (R)0;
+  int pB = 0;
+  for (int t0 = 0; t0 < nt; t0 += kAhead) {
+#pragma unroll
+    for (int z = 0; z < kAhead; ++z) {
+      const int t = t0 + z;
+      R x[S][4];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[s][q] = f[z][s][q];
+      load(t + kAhead, f[z]);
+      const int e = slot_of(t);
+      int Ae, Be;
+      mm_ab(m, c, e, Ae, Be);
+      const bool aie = Ae < Be;
+      if (t == 0 || t == cnt - 1) {  // a boundary slot: from the copy
+        const R *sa = snap + (size_t)(t == 0 ? sg : sgn) * 2 * n, *sb = sa + n;
+        const R *ci = aie ? sa : sb, *cj = aie ? sb : sa;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          x[s][0] = ci[sip[s]];
+          x[s][1] = ci[sjp[s]];
+          x[s][2] = cj[sip[s]];
+          x[s][3] = cj[sjp[s]];
+        }
+      }
+      const R v11 = S1[C_V11 * np + e], v21 = S1[C_V21 * np + e];
+      const R v12 = S1[C_V12 * np + e], v22 = S1[C_V22 * np + e];
+      R wAA[S], wAB[S], wBA[S], wBB[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = pp[s];
+        Blk<R> o = blk_rot(S1[C_U11 * np + p], S1[C_U21 * np + p], S1[C_U12 * np + p],
+                           S1[C_U22 * np + p], v11, v21, v12, v22, x[s][0], x[s][1], x[s][2],
+                           x[s][3]);
+        const bool dg = p == e;
+        const R oii = dg ? S1[C_S1 * np + p] : o.ii, ojj = dg ? S1[C_S2 * np + p] : o.jj;
+        const R oij = dg ? (R)0 : o.ij, oji = dg ? (R)0 : o.ji;
+        const R rAi = aip[s] ? oii : oji, rAj = aip[s] ? oij : ojj;
+        const R rBi = aip[s] ? oji : oii, rBj = aip[s] ? ojj : oij;
+        wAA[s] = aie ? rAi : rAj;
+        wAB[s] = aie ? rAj : rAi;
+        wBA[s] = aie ? rBi : rBj;
+        wBB[s] = aie ? rBj : rBi;
+      }
+      // the B row of the lane's first output pair: the previous lane's last slot
+      R lBA = wBA[0], lBB = wBB[0];
+#pragma unroll
+      for (int s = 1; s < S; ++s) {
+        lBA = slast == s ? wBA[s] : lBA;
+        lBB = slast == s ? wBB[s] : lBB;
+      }
+      const R uBA = __shfl(lBA, pred), uBB = __shfl(lBB, pred);
+      if (t > 0 && t < cnt) {
+        // output blocks (p, e) of step k + 1: columns A_e and B_(e-1)
+        const int cA = Ae, cB = pB;
+        const bool cai = cA < cB;
+        const int siq = min(cA, cB) * cb, sjq = max(cA, cB) * cb;
+        const int q2c = e == 0 ? 0 : np - e;
+        const R y11 = S2[C_V11 * np + q2c], y21 = S2[C_V21 * np + q2c];
+        const R y12 = S2[C_V12 * np + q2c], y22 = S2[C_V22 * np + q2c];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const R bBA = s == 0 ? uBA : wBA[s > 0 ? s - 1 : 0];
+          const R bBB = s == 0 ? pBBu : pBB[s > 0 ? s - 1 : 0];
+          R a, b, cc, dd;
+          ab_to_ij(rai[s], cai, wAA[s], pAB[s], bBA, bBB, a, b, cc, dd);
+          const int q = q2r[s];
+          Blk<R> o2 = blk_rot(S2[C_U11 * np + q], S2[C_U21 * np + q], S2[C_U12 * np + q],
+                              S2[C_U22 * np + q], y11, y21, y12, y22, a, b, cc, dd);
+          const bool dg = pp[s] == e;
+          buf.st(dg ? S2[C_S1 * np + q] : o2.ii, vi2[s], siq);
+          buf.st(dg ? (R)0 : o2.ij, vi2[s], sjq);
+          buf.st(dg ? (R)0 : o2.ji, vj2[s], siq);
+          buf.st(dg ? S2[C_S2 * np + q] : o2.jj, vj2[s], sjq);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        pAB[s] = wAB[s];
+        pBB[s] = wBB[s];
+      }
+      pBBu = uBB;
+      pB = Be;
     }
   }
 }
@@ -826,6 +1072,10 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   // second buffer; the sweep's last step (n - 1 steps, an odd count) lands in G
   const bool pairs2 = d.ord == 1 && n >= 4;
   R *Ga = pairs2 ? reinterpret_cast<R *>(d.galt) + d.aoff[m] : Gm;
+  // orders up to 256 update G in place when the boundary columns fit the tile
+  // (in workgroups of up to 512 lanes, whose registers hold that path)
+  const FusedGeo geo = fused_geo(n, BS / 64, tile_elems);
+  const bool inplace = BS <= 512 && pairs2 && np <= 128 && tile_elems >= 2 * n;
   int sw = 0;
   bool conv = false;
   for (; sw < max_sweeps && !conv; ++sw) {
@@ -845,10 +1095,20 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
       if (pairs2 && k + 2 <= n - 2) {
         g_pivots_next<R, BS>(cur, n, k, spar, spar2,
                              tab + (size_t)((k + 1) % kChunk) * kPivComp * np);
+        if (inplace) g_fused_snapshot<R, BS>(Gm, n, k, geo, T);
         __syncthreads();
-        R *nxt = cur == Gm ? Ga : Gm;
-        g_fused_pair<R, BS, sizeof(R) == 8 ? 4 : 6>(cur, nxt, n, k, spar, spar2);
-        cur = nxt;
+        if (inplace) {
+          if constexpr (BS <= 512) {
+            if (np <= 64)
+              g_fused_inplace<R, BS, 1>(Gm, n, k, spar, spar2, geo, T);
+            else
+              g_fused_inplace<R, BS, 2>(Gm, n, k, spar, spar2, geo, T);
+          }
+        } else {
+          R *nxt = cur == Gm ? Ga : Gm;
+          g_fused_pair<R, BS, sizeof(R) == 8 ? 4 : 6>(cur, nxt, n, k, spar, spar2);
+          cur = nxt;
+        }
         k += 2;
       } else {
         // 1024 lanes keep 16 waves per CU in flight: two blocks each suffice and
@@ -1073,7 +1333,7 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, int64_t nsq, size_t w) {
 struct Tune {
   int block[2][5];
 };
-static Tune g_tune = {{{256, 512, 1024, 1024, 1024}, {256, 512, 1024, 1024, 1024}}};
+static Tune g_tune = {{{256, 512, 512, 1024, 1024}, {256, 512, 512, 1024, 1024}}};
 static std::mutex g_mu;
 
 static int bucket_of(int n) {
