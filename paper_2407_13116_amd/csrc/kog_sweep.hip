@@ -804,10 +804,128 @@ __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab
   }
 }
 
-template <class R>
+// wave rotation by one lane (lane l receives lane l - 1's value, lane 0 lane
+// 63's) and a read of one lane's value; every lane active
+__device__ inline float lane_ror(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x13c, 0xf, 0xf, false));
+}
+__device__ inline double lane_ror(double x) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x13c, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x13c, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_read(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ inline double lane_read(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Steps k and k + 1 of the modified modulus ordering on the wave's rows of the
+// tile in one pass (the chain of the two-step G update, in one dimension):
+// lane l holds the slots l + 64 s (s < S); per row it reads the two elements
+// of each of its step-k pairs, rotates them, forms its step-(k+1) pairs
+// {A_p, B_(p-1)} (B_(p-1) from the lane before it, or for lane 0 from lane 63's
+// previous slot, or from the last slot np - 1) and writes them: each element
+// is read and written once per two steps.  Slots past np use the padding
+// column n, which is never copied back.
+template <class R, int S>
+__device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool isv) {
+  const int ldt = n + 1, np = n >> 1, m = n - 1, c = mm_center(n, k);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int comp = isv ? C_V11 : C_U11;
+  const R *S1 = tab + (size_t)(k % kChunk) * kPivComp * np + comp * np;
+  const R *S2 = tab + (size_t)((k + 1) % kChunk) * kPivComp * np + comp * np;
+  const int wl = (np - 1) & 63, ws = (np - 1) >> 6;  // lane and slot of slot np - 1
+  int ia[S], ib[S], i2[S], j2[S];
+  bool aip[S], rai[S];
+  R a11[S], a21[S], a12[S], a22[S], b11[S], b21[S], b12[S], b22[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int p = lane + 64 * s;
+    const bool ok = p < np;
+    const int ps = ok ? p : 0;
+    int A, B, Aq, Bq;
+    mm_ab(m, c, ps, A, B);
+    mm_ab(m, c, ps == 0 ? np - 1 : ps - 1, Aq, Bq);
+    aip[s] = A < B;
+    rai[s] = A < Bq;
+    ia[s] = ok ? A : n;
+    ib[s] = ok ? B : n;
+    i2[s] = ok ? min(A, Bq) : n;
+    j2[s] = ok ? max(A, Bq) : n;
+    const int q2 = ps == 0 ? 0 : np - ps;
+    a11[s] = S1[ps];
+    a21[s] = S1[np + ps];
+    a12[s] = S1[2 * np + ps];
+    a22[s] = S1[3 * np + ps];
+    b11[s] = S2[q2];
+    b21[s] = S2[np + q2];
+    b12[s] = S2[2 * np + q2];
+    b22[s] = S2[3 * np + q2];
+  }
+  for (int r = wv; r < nr; r += nw) {
+    R *row = T + r * ldt;
+    R xa[S], xb[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      xa[s] = row[ia[s]];
+      xb[s] = row[ib[s]];
+    }
+    R nA[S], nB[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const R xi = aip[s] ? xa[s] : xb[s], xj = aip[s] ? xb[s] : xa[s];
+      const R ni = lin(a11[s], xi, a21[s], xj), nj = lin(a12[s], xi, a22[s], xj);
+      nA[s] = aip[s] ? ni : nj;
+      nB[s] = aip[s] ? nj : ni;
+    }
+    // the B element of slot np - 1 (lane wl, slot ws) for lane 0's first pair
+    R wsel = nB[0];
+#pragma unroll
+    for (int s = 1; s < S; ++s) wsel = ws == s ? nB[s] : wsel;
+    const R wrap = lane_read(wsel, wl);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      // lane 63 passes its previous slot to lane 0 of the next slot
+      const R give = (s > 0 && lane == 63) ? nB[s > 0 ? s - 1 : 0] : nB[s];
+      const R got = lane_ror(give);
+      const R bv = (s == 0 && lane == 0) ? wrap : got;
+      const R xi = rai[s] ? nA[s] : bv, xj = rai[s] ? bv : nA[s];
+      row[i2[s]] = lin(b11[s], xi, b21[s], xj);
+      row[j2[s]] = lin(b12[s], xi, b22[s], xj);
+    }
+  }
+}
+
+// kPairs: take consecutive steps of the modified modulus ordering in pairs
+// (orders up to 256; the register budget of workgroups of up to 512 lanes)
+template <class R, bool kPairs = true>
 __device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv, int ord) {
   if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
   const int np = n >> 1;
+  if (kPairs && ord == 1 && n >= 4 && np <= 128) {
+    // consecutive steps in pairs (the rows of a wave are its own: a wave
+    // barrier orders one pass after the previous)
+    int k = k0;
+    for (; k + 1 <= k1; k += 2) {
+      if (np <= 64)
+        tile_rotate_pair<R, 1>(T, n, nr, k, tab, isv);
+      else
+        tile_rotate_pair<R, 2>(T, n, nr, k, tab, isv);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (k <= k1) {
+      if (np <= 64)
+        tile_rotate_ng<R, 1>(T, n, nr, k, k, tab, isv, ord);
+      else
+        tile_rotate_ng<R, 2>(T, n, nr, k, k, tab, isv, ord);
+    }
+    return;
+  }
   if (np <= 64)
     tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord);
   else
@@ -1005,7 +1123,8 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   R *M = (blockIdx.y ? V : U) + d.off[m];
   tile_load(T, M, n, r0, nr);
   __syncthreads();
-  tile_rotate(T, n, nr, k0, k1, par + kChunk * d.poff[m] * kPivComp, blockIdx.y != 0, d.ord);
+  tile_rotate<R, false>(T, n, nr, k0, k1, par + kChunk * d.poff[m] * kPivComp, blockIdx.y != 0,
+                        d.ord);
   __syncthreads();
   tile_store(T, M, n, r0, nr);
 }
@@ -1127,7 +1246,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
             int nr = min(rows, n - r0);
             tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
-            tile_rotate(T, n, nr, k0, kl, tab, side != 0, d.ord);
+            tile_rotate<R, (BS <= 512)>(T, n, nr, k0, kl, tab, side != 0, d.ord);
             __syncthreads();
             tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
