@@ -417,3 +417,32 @@ def test_sparse_and_structured_bitwise(orc, dtype, mode):
         assert _same(got["U"][k], U), (mode, k, "U")
         assert _same(got["V"][k], V), (mode, k, "V")
 
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_two_step_passes_every_block_size(orc, dtype):
+    """The persistent kernel at every workgroup size (in place for orders up to 256
+    in workgroups of up to 512 lanes, through the second buffer otherwise, paired U/V
+    rotations or not): orders at the boundaries of the lane layouts (n/2 = 2, 3, 63,
+    64, 65, 128, 129), bit for bit against the oracle over a sweep and a half."""
+    import torch
+
+    from paper_2407_13116_amd import sweep as sw
+
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    ns = [4, 6, 126, 128, 130, 256, 258, 202]
+    mats = _mats(np.random.default_rng(44), ns, dtype)
+    ref = [orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0) for G0 in mats]
+    try:
+        for block in (256, 512, 1024):
+            for bucket in range(5):
+                sw.set_tuning(tdt, bucket, block)
+            p, got = _run(mats, dtype, "persistent", max_sweeps=2, tolf=-1.0)
+            for k in range(len(ns)):
+                G, U, V, st, swp = ref[k]
+                assert _same(got["G"][k], G), (block, ns[k], "G")
+                assert _same(got["U"][k], U), (block, ns[k], "U")
+                assert _same(got["V"][k], V), (block, ns[k], "V")
+    finally:
+        for bucket, block in enumerate((256, 512, 512, 1024, 1024)):
+            sw.set_tuning(tdt, bucket, block)
