@@ -53,7 +53,7 @@ namespace ksvd2 {
 
 constexpr int kRed = 256;        // lanes of the fixed-order reductions
 constexpr int kMaxOrder = 8192;  // pair indices are stored as int16
-constexpr int kChunk = 16;       // steps whose U/V rotations are applied together
+constexpr int kChunk = 128;      // steps whose U/V rotations are applied together
 constexpr int kApplyBlock = 256; // workgroup of the mode-0 U/V kernel
 constexpr size_t kApplyLds = 64 * 1024;
 
