@@ -361,15 +361,18 @@ __device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R 
 
 // Raw buffer access to one matrix: byte offsets as a per-lane part and a
 // wave-uniform (column) part; an offset at or past the end (kOff) reads zero
-// and stores nothing, without a memory access.
+// and stores nothing, without a memory access.  The descriptor's last word
+// (kBufWord3) selects 32-bit raw data access on this GPU family; the range is
+// the matrix's size in bytes, with no stride.
 constexpr int kOff = 0x40000000;
+constexpr int kBufWord3 = 0x00020000;
 template <class R> struct Buf;
 template <> struct Buf<double> {
   typedef unsigned int V __attribute__((ext_vector_type(2)));
   __amdgpu_buffer_rsrc_t r;
   __device__ Buf(const double *p, int bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, bytes,
-                                            0x00020000)) {}
+                                            kBufWord3)) {}
   __device__ double ld(int vo, int so) const {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
@@ -381,7 +384,7 @@ template <> struct Buf<float> {
   __amdgpu_buffer_rsrc_t r;
   __device__ Buf(const float *p, int bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, bytes,
-                                            0x00020000)) {}
+                                            kBufWord3)) {}
   __device__ float ld(int vo, int so) const {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
