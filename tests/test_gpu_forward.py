@@ -4,7 +4,8 @@ Cases: the 65,536-matrix forward workload with its zero patterns; every zero pat
 edge values (signed zeros, subnormals, mu, nu, ties); the accuracy/throughput recipe at
 2^20 + 37 matrices (several tiles and a ragged tail) for both precisions, and at its full
 size 2^24 in the launch configuration the benchmark times, checked on sampled outputs;
-batch sizes 0, 1, 255, 257; non-finite inputs; the autograd layout; the device hypot.
+batch sizes 0, 1, 255, 257, and 2^28 + 4,099 (more than one launch); non-finite inputs;
+the autograd layout; the device hypot.
 """
 import numpy as np
 import pytest
@@ -150,3 +151,29 @@ def test_device_hypot(orc, dtype):
     # and the exact reference on a subset (independent of both)
     for i in list(range(0, n, 997)) + list(range(n, X.size)):
         assert got[i] == exact_hypot(X[i], Y[i], dtype), (X[i], Y[i])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_past_one_launch(orc, dtype):
+    """A batch of 2^28 + 4,099 matrices: more than one launch (each covers at most 2^28
+    matrices with 32-bit offsets).  Inputs drawn on the device; outputs around the launch
+    boundary, the last 1,000 and 2^14 random ones recomputed by the oracle."""
+    import torch
+
+    from paper_2407_13116_amd import api
+
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    B = (1 << 28) + 4099
+    gen = torch.Generator(device="cuda").manual_seed(2828)
+    planes = [torch.randn(B, dtype=tdt, device="cuda", generator=gen) for _ in range(4)]
+    out = api.ksvd2_batch(*planes, plain=False)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([np.arange((1 << 28) - 3000, (1 << 28) + 3000),
+                                    np.arange(B - 1000, B), rng.integers(0, B, 1 << 14)]))
+    it = torch.from_numpy(idx).cuda()
+    g = [p.index_select(0, it).cpu().numpy() for p in planes]
+    got = {k: v.index_select(0, it).cpu().numpy() for k, v in out.items()}
+    del planes, out
+    torch.cuda.empty_cache()
+    assert_bitwise(got, orc.ksvd2(*g), label=f"2^28+4099 {dtype.__name__}")
