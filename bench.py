@@ -175,6 +175,10 @@ def sigma2_error_sample(g, host, dtype, n=1500):
     B = g[0].size
     idx = np.random.default_rng(5).choice(B, n, replace=False)
     worst = {"triangular": 0.0, "general": 0.0}
+    # general inputs over the full exponent range lose sigma_2 on some matrices (the
+    # paper's Sect. 4 / Fig. 4): report how many stay within 8 eps, 2^10 eps, 2^26 eps
+    edges = (8.0, 2.0 ** 10, 2.0 ** 26)
+    hist = {"<=8": 0, "<=2^10": 0, "<=2^26": 0, ">2^26": 0}
     with mpmath.workprec(320):
         for i in idx:
             a, b, c, d = (Fraction(float(p[i])) for p in g)
@@ -190,6 +194,10 @@ def sigma2_error_sample(g, host, dtype, n=1500):
             re = 0.0 if s2 == 0 and got == 0 else float(abs(got - s2) / s2 / eps) if s2 else float("inf")
             key = "triangular" if b == 0 else "general"
             worst[key] = max(worst[key], re)
+            if key == "general":
+                k = next((j for j, e in enumerate(edges) if re <= e), len(edges))
+                hist[list(hist)[k]] += 1
+    worst["general_histogram"] = hist
     return worst
 
 
