@@ -854,8 +854,8 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
     mm_ab(m, c, ps == 0 ? np - 1 : ps - 1, Aq, Bq);
     aip[s] = A < B;
     rai[s] = A < Bq;
-    ia[s] = ok ? A : n;
-    ib[s] = ok ? B : n;
+    ia[s] = ok ? min(A, B) : n;  // the step-k pair (i, j) of slot p
+    ib[s] = ok ? max(A, B) : n;
     i2[s] = ok ? min(A, Bq) : n;
     j2[s] = ok ? max(A, Bq) : n;
     const int q2 = ps == 0 ? 0 : np - ps;
@@ -879,7 +879,7 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
     R nA[S], nB[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const R xi = aip[s] ? xa[s] : xb[s], xj = aip[s] ? xb[s] : xa[s];
+      const R xi = xa[s], xj = xb[s];
       const R ni = lin(a11[s], xi, a21[s], xj), nj = lin(a12[s], xi, a22[s], xj);
       nA[s] = aip[s] ? ni : nj;
       nB[s] = aip[s] ? nj : ni;
