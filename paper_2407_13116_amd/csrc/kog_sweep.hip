@@ -1161,8 +1161,11 @@ __global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, R *G, R *sigma,
 // global memory (two steps at a time go from G to a second buffer in the
 // workspace and back); the chunk's rotation table is in the workspace.
 
-template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int maxn) {
-  size_t b = kRed * sizeof(double) + 2 * (size_t)(maxn / 2) * kPivComp * sizeof(R) +
+// two: LDS holds the parameters of two steps, for the two-step passes (orders
+// whose two steps' parameters leave no room for 16 U/V tile rows go one step
+// per pass, which keeps room for a tile row up to the largest orders)
+template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int maxn, bool two) {
+  size_t b = kRed * sizeof(double) + (two ? 2 : 1) * (size_t)(maxn / 2) * kPivComp * sizeof(R) +
              (size_t)maxn * 2;
   return (b + 15) & ~(size_t)15;
 }
@@ -1172,13 +1175,14 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
                                                       R *U, R *V, R *par, R *sigma,
                                                       int32_t *sweeps_out, int max_sweeps,
                                                       double tolf, int accumulate, int maxn,
-                                                      int tile_elems) {
+                                                      int tile_elems, int two) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *red = reinterpret_cast<double *>(smem);
   R *spar = reinterpret_cast<R *>(smem + kRed * sizeof(double));
-  R *spar2 = spar + (size_t)(maxn / 2) * kPivComp;
-  int16_t *spair = reinterpret_cast<int16_t *>(spar2 + (size_t)(maxn / 2) * kPivComp);
-  R *T = reinterpret_cast<R *>(smem + persistent_fixed_lds<R>(maxn));
+  R *spar2 = two ? spar + (size_t)(maxn / 2) * kPivComp : nullptr;
+  int16_t *spair =
+      reinterpret_cast<int16_t *>(spar + (size_t)(two ? 2 : 1) * (maxn / 2) * kPivComp);
+  R *T = reinterpret_cast<R *>(smem + persistent_fixed_lds<R>(maxn, two != 0));
   int m = mats[blockIdx.x];
   int n = d.n[m];
   int np = n >> 1;
@@ -1192,7 +1196,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   __syncthreads();
   // under the modified modulus ordering steps go in pairs through G and a
   // second buffer; the sweep's last step (n - 1 steps, an odd count) lands in G
-  const bool pairs2 = d.ord == 1 && n >= 4;
+  const bool pairs2 = d.ord == 1 && n >= 4 && two;
   R *Ga = pairs2 ? reinterpret_cast<R *>(d.galt) + d.aoff[m] : Gm;
   // orders up to 256 update G in place when the boundary columns fit the tile
   // (in workgroups of up to 512 lanes, whose registers hold that path)
@@ -1215,8 +1219,8 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
       }
       __syncthreads();
       if (pairs2 && k + 2 <= n - 2) {
-        g_pivots_next<R, BS>(cur, n, k, spar, spar2,
-                             tab + (size_t)((k + 1) % kChunk) * kPivComp * np);
+        R *slot2 = tab + (size_t)((k + 1) % kChunk) * kPivComp * np;
+        g_pivots_next<R, BS>(cur, n, k, spar, spar2, slot2);
         if (inplace) g_fused_snapshot<R, BS>(Gm, n, k, geo, T);
         __syncthreads();
         if (inplace) {
@@ -1483,16 +1487,23 @@ static size_t device_lds_limit() {
 }
 
 // LDS of a persistent launch over matrices of order <= maxn: the fixed part
-// plus the largest U/V tile that fits (at least one row of maxn + 1)
-template <class R> static size_t persistent_lds(int maxn, size_t limit, int &tile_elems) {
-  size_t fixed = persistent_fixed_lds<R>(maxn);
+// plus the largest U/V tile that fits (at least one row of maxn + 1); the
+// parameters of two steps when that leaves room for 16 tile rows, else of one
+// (and one step per pass)
+template <class R> static size_t persistent_lds(int maxn, size_t limit, int &tile_elems,
+                                                int &two) {
   tile_elems = 0;
-  if (limit <= fixed) return 0;
-  size_t te = (limit - fixed) / sizeof(R);
-  if (te < (size_t)maxn + 1) return 0;
-  te = std::min(te, (size_t)maxn * (size_t)(maxn + 1));  // never more than the whole matrix
-  tile_elems = (int)std::min<size_t>(te, (size_t)1 << 30);
-  return fixed + (size_t)tile_elems * sizeof(R);
+  for (two = 1; two >= 0; --two) {
+    size_t fixed = persistent_fixed_lds<R>(maxn, two != 0);
+    size_t rows = two ? std::min(16, maxn) : 1;
+    if (limit <= fixed || (limit - fixed) / sizeof(R) < rows * ((size_t)maxn + 1)) continue;
+    size_t te = (limit - fixed) / sizeof(R);
+    te = std::min(te, (size_t)maxn * (size_t)(maxn + 1));  // never more than the whole matrix
+    tile_elems = (int)std::min<size_t>(te, (size_t)1 << 30);
+    return fixed + (size_t)tile_elems * sizeof(R);
+  }
+  two = 0;
+  return 0;
 }
 
 template <class R, int BS> static void set_lds_attr(size_t lds) {
@@ -1505,8 +1516,8 @@ static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int co
                              int block, R *G, R *U, R *V, R *par, R *sigma,
                              int32_t *sweeps_out, int max_sweeps, double tolf, int accumulate,
                              size_t lds_limit, hipStream_t st) {
-  int tile_elems = 0;
-  size_t lds = persistent_lds<R>(maxn, lds_limit, tile_elems);
+  int tile_elems = 0, two = 0;
+  size_t lds = persistent_lds<R>(maxn, lds_limit, tile_elems, two);
   if (lds == 0)
     return fail(KSVD2_EINVAL,
                 "order %d needs more LDS than a workgroup may allocate (%zu bytes) in the "
@@ -1517,19 +1528,19 @@ static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int co
       set_lds_attr<R, 256>(lds);
       hipLaunchKernelGGL((k_sw_persistent<R, 256>), dim3(count), dim3(256), lds, st, d, mats_dev,
                          G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate, maxn,
-                         tile_elems);
+                         tile_elems, two);
       break;
     case 512:
       set_lds_attr<R, 512>(lds);
       hipLaunchKernelGGL((k_sw_persistent<R, 512>), dim3(count), dim3(512), lds, st, d, mats_dev,
                          G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate, maxn,
-                         tile_elems);
+                         tile_elems, two);
       break;
     case 1024:
       set_lds_attr<R, 1024>(lds);
       hipLaunchKernelGGL((k_sw_persistent<R, 1024>), dim3(count), dim3(1024), lds, st, d,
                          mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate,
-                         maxn, tile_elems);
+                         maxn, tile_elems, two);
       break;
     default:
       return fail(KSVD2_EINVAL, "unsupported block size %d", block);

@@ -446,3 +446,17 @@ def test_two_step_passes_every_block_size(orc, dtype):
     finally:
         for bucket, block in enumerate((256, 512, 512, 1024, 1024)):
             sw.set_tuning(tdt, bucket, block)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_large_orders_persistent_matches_plain(dtype):
+    """Orders whose two steps' parameters do not fit the LDS beside 16 U/V tile rows
+    (the second step's come from the step table): one sweep in the persistent mode and
+    in mode 0 (per-step launches, one step per pass), bit for bit."""
+    ns = [1024, 2000]
+    mats = _mats(np.random.default_rng(61), ns, dtype)
+    _, a = _run(mats, dtype, "persistent", max_sweeps=1, tolf=-1.0)
+    _, b = _run(mats, dtype, "plain", max_sweeps=1, tolf=-1.0)
+    for k in range(len(ns)):
+        for key in ("G", "U", "V"):
+            assert _same(a[key][k], b[key][k]), (ns[k], key)
