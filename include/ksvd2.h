@@ -309,7 +309,11 @@ size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);
 
 /* Tuning table of the persistent sweep kernels: workgroup size (256, 512 or
    1024) for order bucket 0: n <= 64, 1: n <= 128, 2: n <= 256, 3: n <= 512,
-   4: larger.  Process-wide; set by the autotuner. */
+   4: larger (defaults 256, 512, 512, 1024, 1024).  Process-wide; set by the
+   autotuner.  Results do not depend on it: every size performs the same
+   arithmetic in the same order (workgroups of up to 512 lanes also update G in
+   place for orders up to 256, and pair the U/V rotations of consecutive steps,
+   under the modified modulus ordering). */
 int kog_sweep_tune(int dtype, int bucket, int block);
 
 /*
