@@ -1,0 +1,34 @@
+"""bench.py's contract pieces that need no GPU: the one-GPU refusal, the roofline
+object, and the traffic figure read from the committed counter summary."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_roofline_object():
+    import bench
+
+    f64 = {"B": 1 << 24, "ms_kernel": 0.44, "GBs": 3500.0}
+    r = bench.roofline(f64)
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    # achieved = the algorithmic FP work per launch over the launch time
+    assert r["achieved"] == pytest.approx(2 * 700 * (1 << 24) / 0.44e-3 / 1e12)
+    # traffic: the counter summary's figure when it was taken on these kernel sources and
+    # this batch, else null; never a figure for another batch size
+    assert r["traffic"] is None or r["traffic"] > 0
+    assert bench.measured_traffic((1 << 24) + 1) is None
