@@ -75,6 +75,22 @@ __device__ inline void ld4(const R *p, R &a, R &b, R &c, R &d) {
     a = p[0]; b = p[1]; c = p[2]; d = p[3];
   }
 }
+// streaming loads for the backward pass, whose 2x2 operands are each read once:
+// non-temporal loads let the memory system stream them (measured: 142 -> 123 us
+// per 2^22 FP64 matrices; non-temporal loads of the sigma pairs and a
+// non-temporal store of dG measured slower)
+typedef double Nt2d __attribute__((ext_vector_type(2)));
+typedef float Nt4f __attribute__((ext_vector_type(4)));
+template <class R> __device__ inline void ld4s(const R *p, R &a, R &b, R &c, R &d) {
+  if constexpr (sizeof(R) == 8) {
+    Nt2d x = __builtin_nontemporal_load(reinterpret_cast<const Nt2d *>(p));
+    Nt2d y = __builtin_nontemporal_load(reinterpret_cast<const Nt2d *>(p) + 1);
+    a = x.x; b = x.y; c = y.x; d = y.y;
+  } else {
+    Nt4f x = __builtin_nontemporal_load(reinterpret_cast<const Nt4f *>(p));
+    a = x.x; b = x.y; c = x.z; d = x.w;
+  }
+}
 template <class R, bool kVec> __device__ inline void st4(R *p, R a, R b, R c, R d) {
   if constexpr (kVec && sizeof(R) == 8) {
     reinterpret_cast<double2 *>(p)[0] = double2{a, b};
@@ -150,20 +166,24 @@ __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__
                                                 R tau) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  auto ldq = [](const R *p, R &a, R &b, R &c, R &d) {
+    if constexpr (kVec) ld4s<R>(p, a, b, c, d); else ld4<R, kVec>(p, a, b, c, d);
+  };
+  auto ldp = [](const R *p, R &a, R &b) { ld2<R, kVec>(p, a, b); };
   R u11, u12, u21, u22, v11, v12, v21, v22, s1, s2;
-  ld4<R, kVec>(U + 4 * i, u11, u12, u21, u22);
-  ld4<R, kVec>(V + 4 * i, v11, v12, v21, v22);
-  ld2<R, kVec>(S + 2 * i, s1, s2);
+  ldq(U + 4 * i, u11, u12, u21, u22);
+  ldq(V + 4 * i, v11, v12, v21, v22);
+  ldp(S + 2 * i, s1, s2);
   R a = 0, b = 0;
   if (dU) {
     R w11, w12, w21, w22;
-    ld4<R, kVec>(dU + 4 * i, w11, w12, w21, w22);
+    ldq(dU + 4 * i, w11, w12, w21, w22);
     // (U^T dU)_12 = u11 w12 + u21 w22 ; (U^T dU)_21 = u12 w11 + u22 w21
     a = fma(u11, w12, u21 * w22) - fma(u12, w11, u22 * w21);
   }
   if (dV) {
     R w11, w12, w21, w22;
-    ld4<R, kVec>(dV + 4 * i, w11, w12, w21, w22);
+    ldq(dV + 4 * i, w11, w12, w21, w22);
     b = fma(v11, w12, v21 * w22) - fma(v12, w11, v22 * w21);
   }
   R p = (R)0.5 * (a + b), q = (R)0.5 * (a - b);
@@ -178,14 +198,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__
   }
   R ism = (sm != (R)0) ? (R)1 / sm : (R)0;
   R m11 = 0, m22 = 0;
-  if (dS) ld2<R, kVec>(dS + 2 * i, m11, m22);
+  if (dS) ldp(dS + 2 * i, m11, m22);
   R pd = p * idm, qs = q * ism;
   R m12 = qs - pd, m21 = -pd - qs;
   // T = U M, then dG = T V^T
   R t11 = fma(u11, m11, u12 * m21), t12 = fma(u11, m12, u12 * m22);
   R t21 = fma(u21, m11, u22 * m21), t22 = fma(u21, m12, u22 * m22);
-  st4<R, kVec>(dG + 4 * i, fma(t11, v11, t12 * v12), fma(t11, v21, t12 * v22),
-               fma(t21, v11, t22 * v12), fma(t21, v21, t22 * v22));
+  const R g11 = fma(t11, v11, t12 * v12), g12 = fma(t11, v21, t12 * v22);
+  const R g21 = fma(t21, v11, t22 * v12), g22 = fma(t21, v21, t22 * v22);
+  st4<R, kVec>(dG + 4 * i, g11, g12, g21, g22);
 }
 
 template <class R, bool CR>
