@@ -231,11 +231,13 @@ int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, v
  *           is k mod m, and the index c with 2c = k mod m with m.
  *           Both visit every pair once per sweep, in different step orders.
  * All modes perform the same arithmetic in the same order: bitwise identical.
- * workspace: device memory of at least kog_sweep_workspace_size() bytes,
- * 256-byte aligned, owned by the caller, used only during the call's work
- * (it includes a second buffer of G's size, sum of n^2 elements, through which
- * the persistent modes update G two steps at a time under the modified modulus
- * ordering).
+ * workspace: device memory of at least kog_sweep_workspace_size() bytes (an
+ * amount that covers every mode, ordering and tuning; a call checks only what
+ * it uses), 256-byte aligned, owned by the caller, used only during the call's
+ * work: the batch descriptor, the counters, the step table (the parameters of
+ * up to 128 steps of every pivot), mode 0's pair table, and a second buffer,
+ * of G's size at most, through which the persistent modes update G two steps
+ * at a time under the modified modulus ordering.
  * Overflow: G is first multiplied by 2^s_G with s_G = e_nu - 2 - e_G - ceil(lg n)
  * when that is negative (e_G the largest exponent of its entries, e_nu that of
  * the largest finite value), so no two-sided update can overflow, and scaled
@@ -307,13 +309,39 @@ int kog_qrcp_apply(int dtype, int64_t nmat, const int32_t *m_host, const int32_t
    (0 for invalid arguments). */
 size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);
 
-/* Tuning table of the persistent sweep kernels: workgroup size (256, 512 or
-   1024) for order bucket 0: n <= 64, 1: n <= 128, 2: n <= 256, 3: n <= 512,
-   4: larger (defaults 256, 512, 512, 1024, 1024).  Process-wide; set by the
-   autotuner.  Results do not depend on it: every size performs the same
-   arithmetic in the same order (workgroups of up to 512 lanes also update G in
-   place for orders up to 256, and pair the U/V rotations of consecutive steps,
-   under the modified modulus ordering). */
+/*
+ * Tuning table of kog_sweep_batch's persistent modes, per dtype and order
+ * bucket (0: n <= 64, 1: n <= 128, 2: n <= 256, 3: n <= 512, 4: larger).
+ * Process-wide; set by the autotuner.  Results do not depend on it: every
+ * setting performs the same arithmetic in the same order.  Knobs:
+ *   KOG_TUNE_BLOCK   (0) lanes per workgroup (one workgroup per matrix): 256,
+ *                        512 or 1024; defaults 256, 512, 512, 1024, 1024
+ *   KOG_TUNE_CHUNK   (1) steps whose U/V rotations are applied together, a
+ *                        power of two in [2, 128] (default 128); a call uses
+ *                        the entry of the bucket of its largest order; it sets
+ *                        the size of the step table in the workspace
+ *   KOG_TUNE_TWO     (2) 1 (default): two steps of G per pass under the
+ *                        modified modulus ordering; 0: one step per pass
+ *   KOG_TUNE_INPLACE (3) 1 (default): that pass in place for orders up to 256
+ *                        in workgroups of up to 512 lanes; 0: through the
+ *                        second buffer
+ *   KOG_TUNE_ROWS    (4) at most this many U/V tile rows in LDS (0, the
+ *                        default: as many as fit), which leaves LDS for more
+ *                        workgroups per compute unit
+ * kog_sweep_set_tuning sets `knob` of `bucket` (-1: of every bucket) and returns
+ * KSVD2_EINVAL for a value out of range; kog_sweep_get_tuning returns the entry
+ * (or a negative status); kog_sweep_reset_tuning restores the defaults;
+ * kog_sweep_tune(dtype, bucket, block) is kog_sweep_set_tuning(dtype, bucket,
+ * KOG_TUNE_BLOCK, block).
+ */
+#define KOG_TUNE_BLOCK 0
+#define KOG_TUNE_CHUNK 1
+#define KOG_TUNE_TWO 2
+#define KOG_TUNE_INPLACE 3
+#define KOG_TUNE_ROWS 4
+int kog_sweep_set_tuning(int dtype, int bucket, int knob, int value);
+int kog_sweep_get_tuning(int dtype, int bucket, int knob);
+int kog_sweep_reset_tuning(void);
 int kog_sweep_tune(int dtype, int bucket, int block);
 
 /*

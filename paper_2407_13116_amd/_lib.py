@@ -65,6 +65,12 @@ def lib():
                                          ctypes.c_size_t, p]
             L.kog_sweep_tune.restype = i32
             L.kog_sweep_tune.argtypes = [i32, i32, i32]
+            L.kog_sweep_set_tuning.restype = i32
+            L.kog_sweep_set_tuning.argtypes = [i32, i32, i32, i32]
+            L.kog_sweep_get_tuning.restype = i32
+            L.kog_sweep_get_tuning.argtypes = [i32, i32, i32]
+            L.kog_sweep_reset_tuning.restype = i32
+            L.kog_sweep_reset_tuning.argtypes = []
         _lib = L
     return _lib
 

@@ -53,7 +53,8 @@ namespace ksvd2 {
 
 constexpr int kRed = 256;        // lanes of the fixed-order reductions
 constexpr int kMaxOrder = 8192;  // pair indices are stored as int16
-constexpr int kChunk = 128;      // steps whose U/V rotations are applied together
+constexpr int kChunk = 128;      // default and largest count of steps whose U/V rotations
+                                 // are applied together (a power of two)
 constexpr int kApplyBlock = 256; // workgroup of the mode-0 U/V kernel
 constexpr size_t kApplyLds = 64 * 1024;
 
@@ -70,6 +71,7 @@ struct SweepDesc {
   int ord;               // pivot ordering: 0 round-robin, 1 modified modulus
   const int64_t *aoff;   // offset of matrix m in galt
   void *galt;            // a second buffer of G's size (the two-step G updates)
+  int chunk;             // steps per U/V update, a power of two in [2, kChunk]
 };
 
 // Slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
@@ -761,13 +763,13 @@ template <class R, int D = 8> __device__ void tile_store(const R *T, R *M, int n
 // the loop body has no branches
 template <class R, int NG>
 __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv,
-                               int ord) {
+                               int ord, int cm) {
   const int ldt = n + 1;
   const int np = n >> 1;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int k = k0; k <= k1; ++k) {
-    const R *S = tab + (size_t)(k % kChunk) * kPivComp * np + (isv ? C_V11 : C_U11) * np;
+    const R *S = tab + (size_t)(k & cm) * kPivComp * np + (isv ? C_V11 : C_U11) * np;
     for (int q0 = lane; q0 < np; q0 += 64 * NG) {
       R e1[NG], e2[NG], e3[NG], e4[NG];
       int ii[NG], jj[NG];
@@ -834,12 +836,12 @@ __device__ inline double lane_read(double x, int l) {
 // is read and written once per two steps.  Slots past np use the padding
 // column n, which is never copied back.
 template <class R, int S>
-__device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool isv) {
+__device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool isv, int cm) {
   const int ldt = n + 1, np = n >> 1, m = n - 1, c = mm_center(n, k);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int comp = isv ? C_V11 : C_U11;
-  const R *S1 = tab + (size_t)(k % kChunk) * kPivComp * np + comp * np;
-  const R *S2 = tab + (size_t)((k + 1) % kChunk) * kPivComp * np + comp * np;
+  const R *S1 = tab + (size_t)(k & cm) * kPivComp * np + comp * np;
+  const R *S2 = tab + (size_t)((k + 1) & cm) * kPivComp * np + comp * np;
   const int wl = (np - 1) & 63, ws = (np - 1) >> 6;  // lane and slot of slot np - 1
   int ia[S], ib[S], i2[S], j2[S];
   bool aip[S], rai[S];
@@ -905,7 +907,8 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
 // kPairs: take consecutive steps of the modified modulus ordering in pairs
 // (orders up to 256; the register budget of workgroups of up to 512 lanes)
 template <class R, bool kPairs = true>
-__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv, int ord) {
+__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv, int ord,
+                            int cm) {
   if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
   const int np = n >> 1;
   if (kPairs && ord == 1 && n >= 4 && np <= 128) {
@@ -914,25 +917,25 @@ __device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, b
     int k = k0;
     for (; k + 1 <= k1; k += 2) {
       if (np <= 64)
-        tile_rotate_pair<R, 1>(T, n, nr, k, tab, isv);
+        tile_rotate_pair<R, 1>(T, n, nr, k, tab, isv, cm);
       else
-        tile_rotate_pair<R, 2>(T, n, nr, k, tab, isv);
+        tile_rotate_pair<R, 2>(T, n, nr, k, tab, isv, cm);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (k <= k1) {
       if (np <= 64)
-        tile_rotate_ng<R, 1>(T, n, nr, k, k, tab, isv, ord);
+        tile_rotate_ng<R, 1>(T, n, nr, k, k, tab, isv, ord, cm);
       else
-        tile_rotate_ng<R, 2>(T, n, nr, k, k, tab, isv, ord);
+        tile_rotate_ng<R, 2>(T, n, nr, k, k, tab, isv, ord, cm);
     }
     return;
   }
   if (np <= 64)
-    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord);
+    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord, cm);
   else
-    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv, ord);
+    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv, ord, cm);
 }
 
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
@@ -1042,8 +1045,8 @@ __device__ void finish_matrix(R *G, int n, int sg, R *sig, int32_t *sweeps_out, 
   if (threadIdx.x == 0 && sweeps_out) *sweeps_out = conv ? sweeps : -sweeps;
 }
 
-// the first step of the chunk that ends with step k
-__device__ inline int chunk_begin(int k) { return k - k % kChunk; }
+// the first step of the chunk (of cm + 1 steps) that ends with step k
+__device__ inline int chunk_begin(int k, int cm) { return k - (k & cm); }
 
 // ----------------------------------------------------------- mode 0 kernels
 
@@ -1074,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, R
   if (q >= np || k >= n - 1 || d.done[m]) return;
   int i, j;
   piv_pair(d.ord, n, k, q, i, j);
-  int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
+  int64_t slot = d.chunk * d.poff[m] + (int64_t)(k & (d.chunk - 1)) * np;
   pairs[2 * (slot + q)] = (int16_t)i;
   pairs[2 * (slot + q) + 1] = (int16_t)j;
   piv_store(par + slot * kPivComp, np, q, pivot_svd(G + d.off[m], n, i, j));
@@ -1089,7 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_update(SweepDesc d, R *G, const R
   int np = n >> 1;
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= np * np) return;
-  int64_t slot = kChunk * d.poff[m] + (int64_t)(k % kChunk) * np;
+  int64_t slot = d.chunk * d.poff[m] + (int64_t)(k & (d.chunk - 1)) * np;
   const int16_t *pt = pairs + 2 * slot;
   const R *S = par + slot * kPivComp;
   R *Gm = G + d.off[m];
@@ -1117,7 +1120,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   int m = blockIdx.z;
   int n = d.n[m];
   if (d.done[m]) return;
-  int k0 = chunk_begin(k), k1 = min(k, n - 2);
+  int k0 = chunk_begin(k, d.chunk - 1), k1 = min(k, n - 2);
   if (k0 > k1) return;
   int rows = min(n, tile_elems / (n + 1));
   int r0 = blockIdx.x * rows;
@@ -1126,8 +1129,8 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   R *M = (blockIdx.y ? V : U) + d.off[m];
   tile_load(T, M, n, r0, nr);
   __syncthreads();
-  tile_rotate<R, false>(T, n, nr, k0, k1, par + kChunk * d.poff[m] * kPivComp, blockIdx.y != 0,
-                        d.ord);
+  tile_rotate<R, false>(T, n, nr, k0, k1, par + d.chunk * d.poff[m] * kPivComp, blockIdx.y != 0,
+                        d.ord, d.chunk - 1);
   __syncthreads();
   tile_store(T, M, n, r0, nr);
 }
@@ -1164,6 +1167,12 @@ __global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, R *G, R *sigma,
 // two: LDS holds the parameters of two steps, for the two-step passes (orders
 // whose two steps' parameters leave no room for 16 U/V tile rows go one step
 // per pass, which keeps room for a tile row up to the largest orders)
+// the in-place two-step pass: orders up to 256 in workgroups of up to 512 lanes
+// (their registers hold that path), with the boundary columns in the tile
+__host__ __device__ inline bool uses_inplace(int bs, int n, int tile_elems) {
+  return bs <= 512 && (n >> 1) <= 128 && tile_elems >= 2 * n;
+}
+
 template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int maxn, bool two) {
   size_t b = kRed * sizeof(double) + (two ? 2 : 1) * (size_t)(maxn / 2) * kPivComp * sizeof(R) +
              (size_t)maxn * 2;
@@ -1175,7 +1184,8 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
                                                       R *U, R *V, R *par, R *sigma,
                                                       int32_t *sweeps_out, int max_sweeps,
                                                       double tolf, int accumulate, int maxn,
-                                                      int tile_elems, int two) {
+                                                      int tile_elems, int two,
+                                                      int inplace_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *red = reinterpret_cast<double *>(smem);
   R *spar = reinterpret_cast<R *>(smem + kRed * sizeof(double));
@@ -1188,7 +1198,8 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   int np = n >> 1;
   int64_t o = d.off[m];
   R *Gm = G + o, *Um = U + o, *Vm = V + o;
-  R *tab = par + kChunk * d.poff[m] * kPivComp;
+  R *tab = par + d.chunk * d.poff[m] * kPivComp;
+  const int cm = d.chunk - 1;
   int rows = min(n, tile_elems / (n + 1));
   int sg, nt;
   double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red, sg, nt);
@@ -1201,13 +1212,13 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   // orders up to 256 update G in place when the boundary columns fit the tile
   // (in workgroups of up to 512 lanes, whose registers hold that path)
   const FusedGeo geo = fused_geo(n, BS / 64, tile_elems);
-  const bool inplace = BS <= 512 && pairs2 && np <= 128 && tile_elems >= 2 * n;
+  const bool inplace = inplace_ok && uses_inplace(BS, n, tile_elems) && pairs2;
   int sw = 0;
   bool conv = false;
   for (; sw < max_sweeps && !conv; ++sw) {
     const R *cur = Gm;
     for (int k = 0; k < n - 1;) {
-      R *slot = tab + (size_t)(k % kChunk) * kPivComp * np;
+      R *slot = tab + (size_t)(k & cm) * kPivComp * np;
       for (int q = threadIdx.x; q < np; q += BS) {
         int i, j;
         piv_pair(d.ord, n, k, q, i, j);
@@ -1219,7 +1230,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
       }
       __syncthreads();
       if (pairs2 && k + 2 <= n - 2) {
-        R *slot2 = tab + (size_t)((k + 1) % kChunk) * kPivComp * np;
+        R *slot2 = tab + (size_t)((k + 1) & cm) * kPivComp * np;
         g_pivots_next<R, BS>(cur, n, k, spar, spar2, slot2);
         if (inplace) g_fused_snapshot<R, BS>(Gm, n, k, geo, T);
         __syncthreads();
@@ -1245,15 +1256,15 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
       }
       __syncthreads();
       const int kl = k - 1;  // the last step done
-      if (kl % kChunk == kChunk - 1 || kl == n - 2) {
-        int k0 = chunk_begin(kl);
+      if ((kl & cm) == cm || kl == n - 2) {
+        int k0 = chunk_begin(kl, cm);
         for (int side = 0; side < 2; ++side) {
           R *M = side ? Vm : Um;
           for (int r0 = 0; r0 < n; r0 += rows) {
             int nr = min(rows, n - r0);
             tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
-            tile_rotate<R, (BS <= 512)>(T, n, nr, k0, kl, tab, side != 0, d.ord);
+            tile_rotate<R, (BS <= 512)>(T, n, nr, k0, kl, tab, side != 0, d.ord, cm);
             __syncthreads();
             tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
@@ -1433,8 +1444,11 @@ struct WsLayout {
       total;
 };
 
-// nsq: the sum of n^2 (the second G buffer of the persistent modes)
-static WsLayout ws_layout(int64_t nmat, int64_t npiv, int64_t nsq, size_t w) {
+// npiv: the sum of n/2; chunk: steps per U/V update (rows of the step table);
+// pairs: mode 0's pair table; galt_elems: the second G buffer (only the
+// matrices whose two-step passes go through it)
+static WsLayout ws_layout(int64_t nmat, int64_t npiv, int chunk, bool pairs, int64_t galt_elems,
+                          size_t w) {
   WsLayout L;
   size_t p = 0;
   L.n = p;      p = align256(p + nmat * 4);
@@ -1448,18 +1462,41 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, int64_t nsq, size_t w) {
   L.scale = p;  p = align256(p + nmat * 4);
   L.nexp = p;   p = align256(p + nmat * 4);
   L.aoff = p;   p = align256(p + nmat * 8);
-  L.par = p;    p = align256(p + (size_t)kChunk * npiv * 10 * w);
-  L.pairs = p;  p = align256(p + (size_t)kChunk * npiv * 4);
-  L.galt = p;   p = align256(p + (size_t)nsq * w);
+  L.par = p;    p = align256(p + (size_t)chunk * npiv * kPivComp * w);
+  L.pairs = p;  p = align256(p + (pairs ? (size_t)chunk * npiv * 4 : 0));
+  L.galt = p;   p = align256(p + (size_t)galt_elems * w);
   L.total = p;
   return L;
 }
 
-// persistent-kernel tuning table: block size per (dtype, order bucket)
+// Tuning table of the persistent sweep, per dtype and order bucket (0: n <= 64,
+// 1: n <= 128, 2: n <= 256, 3: n <= 512, 4: larger).  No entry changes a bit
+// of the results: every choice performs the same operations in the same order.
+//   block    lanes per workgroup (one workgroup per matrix): 256, 512, 1024
+//   chunk    steps per U/V update (power of two, 2..128); a call takes the
+//            entry of the bucket of its largest order
+//   two      two steps of G per pass under the modified modulus ordering
+//   inplace  the in-place form of that pass (orders up to 256, up to 512 lanes)
+//   rows     at most this many U/V tile rows in LDS (0: as many as fit); fewer
+//            rows leave LDS for a second workgroup on a compute unit
+enum Knob { K_BLOCK = 0, K_CHUNK = 1, K_TWO = 2, K_INPLACE = 3, K_ROWS = 4, K_NKNOB = 5 };
 struct Tune {
-  int block[2][5];
+  int v[2][5][K_NKNOB];
 };
-static Tune g_tune = {{{256, 512, 512, 1024, 1024}, {256, 512, 512, 1024, 1024}}};
+static Tune default_tune() {
+  Tune t;
+  const int blocks[5] = {256, 512, 512, 1024, 1024};
+  for (int d = 0; d < 2; ++d)
+    for (int b = 0; b < 5; ++b) {
+      t.v[d][b][K_BLOCK] = blocks[b];
+      t.v[d][b][K_CHUNK] = kChunk;
+      t.v[d][b][K_TWO] = 1;
+      t.v[d][b][K_INPLACE] = 1;
+      t.v[d][b][K_ROWS] = 0;
+    }
+  return t;
+}
+static Tune g_tune = default_tune();
 static std::mutex g_mu;
 
 static int bucket_of(int n) {
@@ -1468,6 +1505,28 @@ static int bucket_of(int n) {
   if (n <= 256) return 2;
   if (n <= 512) return 3;
   return 4;
+}
+
+static int tune_check(int knob, int value) {
+  switch (knob) {
+    case K_BLOCK:
+      if (value != 256 && value != 512 && value != 1024)
+        return fail(KSVD2_EINVAL, "block must be 256, 512 or 1024");
+      return KSVD2_OK;
+    case K_CHUNK:
+      if (value < 2 || value > kChunk || (value & (value - 1)))
+        return fail(KSVD2_EINVAL, "chunk must be a power of two in [2, %d]", kChunk);
+      return KSVD2_OK;
+    case K_TWO:
+    case K_INPLACE:
+      if (value != 0 && value != 1) return fail(KSVD2_EINVAL, "this knob is 0 or 1");
+      return KSVD2_OK;
+    case K_ROWS:
+      if (value < 0 || value > kMaxOrder) return fail(KSVD2_EINVAL, "rows must be in [0, %d]", kMaxOrder);
+      return KSVD2_OK;
+    default:
+      return fail(KSVD2_EINVAL, "unknown knob %d", knob);
+  }
 }
 
 // LDS a workgroup may allocate on the current device (queried once per device)
@@ -1487,18 +1546,19 @@ static size_t device_lds_limit() {
 }
 
 // LDS of a persistent launch over matrices of order <= maxn: the fixed part
-// plus the largest U/V tile that fits (at least one row of maxn + 1); the
-// parameters of two steps when that leaves room for 16 tile rows, else of one
-// (and one step per pass)
-template <class R> static size_t persistent_lds(int maxn, size_t limit, int &tile_elems,
-                                                int &two) {
+// plus the largest U/V tile that fits (at least one row of maxn + 1, at most
+// max_rows rows when max_rows > 0); the parameters of two steps when allowed
+// and when that leaves room for 16 tile rows, else of one (one step per pass)
+template <class R> static size_t persistent_lds(int maxn, size_t limit, bool allow_two,
+                                                int max_rows, int &tile_elems, int &two) {
   tile_elems = 0;
-  for (two = 1; two >= 0; --two) {
+  for (two = allow_two ? 1 : 0; two >= 0; --two) {
     size_t fixed = persistent_fixed_lds<R>(maxn, two != 0);
     size_t rows = two ? std::min(16, maxn) : 1;
     if (limit <= fixed || (limit - fixed) / sizeof(R) < rows * ((size_t)maxn + 1)) continue;
     size_t te = (limit - fixed) / sizeof(R);
-    te = std::min(te, (size_t)maxn * (size_t)(maxn + 1));  // never more than the whole matrix
+    size_t cap = max_rows > 0 ? std::min(max_rows, maxn) : maxn;
+    te = std::min(te, cap * (size_t)(maxn + 1));  // never more than the whole matrix
     tile_elems = (int)std::min<size_t>(te, (size_t)1 << 30);
     return fixed + (size_t)tile_elems * sizeof(R);
   }
@@ -1511,45 +1571,144 @@ template <class R, int BS> static void set_lds_attr(size_t lds) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// one persistent launch: matrices order[begin .. begin + count) (longest
+// first), their largest order, workgroup size and LDS partition
+struct Seg {
+  int begin, count, maxn, block, tile_elems, two, inplace_ok;
+  size_t lds;
+};
+
+// Everything a call needs on the host before it touches the device: the
+// per-matrix offsets, the order of processing, the launches and the exact
+// workspace layout.
+struct Plan {
+  int maxn = 0, chunk = kChunk;
+  int64_t npiv = 0, galt = 0;
+  std::vector<int64_t> soff, poff, aoff;
+  std::vector<int32_t> order;
+  std::vector<Seg> segs;
+  WsLayout L;
+};
+
 template <class R>
-static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, int count, int maxn,
-                             int block, R *G, R *U, R *V, R *par, R *sigma,
-                             int32_t *sweeps_out, int max_sweeps, double tolf, int accumulate,
-                             size_t lds_limit, hipStream_t st) {
-  int tile_elems = 0, two = 0;
-  size_t lds = persistent_lds<R>(maxn, lds_limit, tile_elems, two);
-  if (lds == 0)
-    return fail(KSVD2_EINVAL,
-                "order %d needs more LDS than a workgroup may allocate (%zu bytes) in the "
-                "persistent modes; use mode 0",
-                maxn, lds_limit);
-  switch (block) {
+static int make_plan(int64_t nmat, const int32_t *n_host, const int64_t *off_host, int mode,
+                     int ordering, const Tune &tune, int chunk, Plan &P) {
+  const size_t w = sizeof(R);
+  const int di = (w == 8) ? 1 : 0;
+  P.soff.assign(nmat, 0);
+  P.poff.assign(nmat, 0);
+  P.aoff.assign(nmat, 0);
+  int64_t stot = 0;
+  for (int64_t m = 0; m < nmat; ++m) {
+    int n = n_host[m];
+    if (n < 2 || (n & 1) || n > kMaxOrder)
+      return fail(KSVD2_EINVAL, "matrix %lld: order %d must be even, in [2, %d]", (long long)m,
+                  n, kMaxOrder);
+    if (off_host[m] < 0) return fail(KSVD2_EINVAL, "matrix %lld: negative offset", (long long)m);
+    P.soff[m] = stot;
+    P.poff[m] = P.npiv;
+    stot += n;
+    P.npiv += n / 2;
+    P.maxn = std::max(P.maxn, n);
+  }
+  P.chunk = chunk;
+  // longest matrices first (they have the most steps)
+  P.order.resize(nmat);
+  std::iota(P.order.begin(), P.order.end(), 0);
+  std::stable_sort(P.order.begin(), P.order.end(),
+                   [&](int a, int b) { return n_host[a] > n_host[b]; });
+  P.segs.clear();
+  P.galt = 0;
+  if (mode != 0) {
+    // one persistent launch per order bucket, longest first
+    for (int64_t a = 0; a < nmat;) {
+      int b0 = bucket_of(n_host[P.order[a]]);
+      int64_t bb = a;
+      while (bb < nmat && bucket_of(n_host[P.order[bb]]) == b0) ++bb;
+      const int *t = tune.v[di][b0];
+      Seg s{(int)a, (int)(bb - a), n_host[P.order[a]], t[K_BLOCK], 0, t[K_TWO], t[K_INPLACE], 0};
+      s.tile_elems = t[K_ROWS];  // the row cap until the LDS is partitioned
+      P.segs.push_back(s);
+      a = bb;
+    }
+    // one launch over all matrices, longest first, when the buckets agree on
+    // the launch: the dispatcher then starts each next matrix as soon as a CU
+    // frees up, with no drain between buckets
+    bool same = std::all_of(P.segs.begin(), P.segs.end(), [&](const Seg &x) {
+      const Seg &y = P.segs[0];
+      return x.block == y.block && x.two == y.two && x.inplace_ok == y.inplace_ok &&
+             x.tile_elems == y.tile_elems;
+    });
+    if (same && P.segs.size() > 1) {
+      Seg s = P.segs[0];
+      s.begin = 0;
+      s.count = (int)nmat;
+      P.segs = {s};
+    }
+    const size_t lds_limit = device_lds_limit();
+    if (lds_limit == 0) return fail(KSVD2_EHIP, "cannot read the device's LDS limit");
+    for (Seg &s : P.segs) {
+      int te = 0, two = 0;
+      s.lds = persistent_lds<R>(s.maxn, lds_limit, s.two != 0, s.tile_elems, te, two);
+      if (s.lds == 0)
+        return fail(KSVD2_EINVAL,
+                    "order %d needs more LDS than a workgroup may allocate (%zu bytes) in the "
+                    "persistent modes; use mode 0",
+                    s.maxn, lds_limit);
+      s.tile_elems = te;
+      s.two = two;
+      // the matrices whose two-step passes go through the second buffer
+      for (int x = s.begin; x < s.begin + s.count; ++x) {
+        const int m = P.order[x], n = n_host[m];
+        const bool pairs2 = ordering == 1 && n >= 4 && two;
+        const bool inplace = s.inplace_ok && uses_inplace(s.block, n, te) && pairs2;
+        if (pairs2 && !inplace) {
+          P.aoff[m] = P.galt;
+          P.galt += (int64_t)n * n;
+        }
+      }
+    }
+  }
+  P.L = ws_layout(nmat, P.npiv, chunk, mode == 0, P.galt, w);
+  return KSVD2_OK;
+}
+
+template <class R>
+static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, const Seg &s, R *G,
+                             R *U, R *V, R *par, R *sigma, int32_t *sweeps_out, int max_sweeps,
+                             double tolf, int accumulate, hipStream_t st) {
+  const unsigned cnt = (unsigned)s.count;
+  switch (s.block) {
     case 256:
-      set_lds_attr<R, 256>(lds);
-      hipLaunchKernelGGL((k_sw_persistent<R, 256>), dim3(count), dim3(256), lds, st, d, mats_dev,
-                         G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate, maxn,
-                         tile_elems, two);
+      set_lds_attr<R, 256>(s.lds);
+      hipLaunchKernelGGL((k_sw_persistent<R, 256>), dim3(cnt), dim3(256), s.lds, st, d,
+                         mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
+                         accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
       break;
     case 512:
-      set_lds_attr<R, 512>(lds);
-      hipLaunchKernelGGL((k_sw_persistent<R, 512>), dim3(count), dim3(512), lds, st, d, mats_dev,
-                         G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate, maxn,
-                         tile_elems, two);
+      set_lds_attr<R, 512>(s.lds);
+      hipLaunchKernelGGL((k_sw_persistent<R, 512>), dim3(cnt), dim3(512), s.lds, st, d,
+                         mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
+                         accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
       break;
     case 1024:
-      set_lds_attr<R, 1024>(lds);
-      hipLaunchKernelGGL((k_sw_persistent<R, 1024>), dim3(count), dim3(1024), lds, st, d,
-                         mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf, accumulate,
-                         maxn, tile_elems, two);
+      set_lds_attr<R, 1024>(s.lds);
+      hipLaunchKernelGGL((k_sw_persistent<R, 1024>), dim3(cnt), dim3(1024), s.lds, st, d,
+                         mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
+                         accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
       break;
     default:
-      return fail(KSVD2_EINVAL, "unsupported block size %d", block);
+      return fail(KSVD2_EINVAL, "unsupported block size %d", s.block);
   }
   return launch_status("kog_sweep persistent launch");
 }
 
+// Executable graphs of mode 2, one per argument set, at most kGraphCache per
+// process: the least recently used one is destroyed (after its device has
+// finished its work) to make room.
+constexpr size_t kGraphCache = 16;
 struct GraphKey {
-  int dtype, mode, ordering;
+  int dev, dtype, ordering;
   int64_t nmat;
   const void *G, *U, *V, *sigma, *sweeps, *ws;
   int max_sweeps, accumulate;
@@ -1557,21 +1716,43 @@ struct GraphKey {
   hipStream_t st;
   std::vector<int32_t> n;
   std::vector<int64_t> off;
-  int tune_hash;
+  std::vector<int> tune;
   bool operator<(const GraphKey &o) const {
-    return std::tie(dtype, mode, ordering, nmat, G, U, V, sigma, sweeps, ws, max_sweeps, accumulate, tolf,
-                    st, n, off, tune_hash) <
-           std::tie(o.dtype, o.mode, o.ordering, o.nmat, o.G, o.U, o.V, o.sigma, o.sweeps, o.ws, o.max_sweeps,
-                    o.accumulate, o.tolf, o.st, o.n, o.off, o.tune_hash);
+    return std::tie(dev, dtype, ordering, nmat, G, U, V, sigma, sweeps, ws, max_sweeps,
+                    accumulate, tolf, st, n, off, tune) <
+           std::tie(o.dev, o.dtype, o.ordering, o.nmat, o.G, o.U, o.V, o.sigma, o.sweeps, o.ws,
+                    o.max_sweeps, o.accumulate, o.tolf, o.st, o.n, o.off, o.tune);
   }
 };
-static std::map<GraphKey, hipGraphExec_t> g_graphs;
+struct GraphEntry {
+  hipGraphExec_t exec;
+  uint64_t used;
+};
+static std::map<GraphKey, GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
 
+// room for one more graph (caller holds g_mu)
+static void graph_evict_one() {
+  if (g_graphs.size() < kGraphCache) return;
+  auto lru = g_graphs.begin();
+  for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+    if (it->second.used < lru->second.used) lru = it;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (lru->first.dev != cur) (void)hipSetDevice(lru->first.dev);
+  (void)hipDeviceSynchronize();  // the graph may still run
+  (void)hipGraphExecDestroy(lru->second.exec);
+  if (lru->first.dev != cur) (void)hipSetDevice(cur);
+  g_graphs.erase(lru);
+}
+
+// The iteration on one batch.  ws_bytes must cover the plan's layout; with
+// shrink_chunk the chunk is halved (down to 2) until it does.
 template <class R>
 static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int64_t *off_host,
                       R *G, R *U, R *V, R *sigma, int32_t *sweeps_out, int max_sweeps,
                       double tolf, int accumulate, int mode, int ordering, void *ws,
-                      size_t ws_bytes, hipStream_t st) {
+                      size_t ws_bytes, hipStream_t st, bool shrink_chunk) {
   if (nmat < 0) return fail(KSVD2_EINVAL, "nmat < 0");
   if (nmat == 0) return KSVD2_OK;
   if (!n_host || !off_host) return fail(KSVD2_EINVAL, "n_host and off_host are required");
@@ -1585,39 +1766,35 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   const size_t w = sizeof(R);
   KSVD2_REQ(G, w); KSVD2_REQ(U, w); KSVD2_REQ(V, w); KSVD2_REQ(ws, 256);
   KSVD2_OPT(sigma, w); KSVD2_OPT(sweeps_out, 4);
-  int64_t npiv = 0, stot = 0, nsq = 0;
-  int maxn = 0;
-  std::vector<int64_t> soff(nmat), poff(nmat), aoff(nmat);
-  for (int64_t m = 0; m < nmat; ++m) {
-    int n = n_host[m];
-    if (n < 2 || (n & 1) || n > kMaxOrder)
-      return fail(KSVD2_EINVAL, "matrix %lld: order %d must be even, in [2, %d]", (long long)m,
-                  n, kMaxOrder);
-    if (off_host[m] < 0) return fail(KSVD2_EINVAL, "matrix %lld: negative offset", (long long)m);
-    soff[m] = stot;
-    poff[m] = npiv;
-    aoff[m] = nsq;
-    nsq += (int64_t)n * n;
-    stot += n;
-    npiv += n / 2;
-    maxn = std::max(maxn, n);
+  Tune tune;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    tune = g_tune;
   }
-  WsLayout L = ws_layout(nmat, npiv, nsq, w);
-  if (ws_bytes < L.total)
-    return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
-  // longest matrices first (they have the most steps)
-  std::vector<int32_t> order(nmat);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return n_host[a] > n_host[b]; });
-  // stage the descriptor into the workspace (one host buffer, one copy)
+  const int di = (w == 8) ? 1 : 0;
+  int maxn0 = 0;
+  for (int64_t m = 0; m < nmat; ++m) maxn0 = std::max(maxn0, n_host[m]);
+  int chunk = tune.v[di][bucket_of(maxn0)][K_CHUNK];
+  Plan P;
+  for (;;) {
+    int rc = make_plan<R>(nmat, n_host, off_host, mode, ordering, tune, chunk, P);
+    if (rc) return rc;
+    if (P.L.total <= ws_bytes) break;
+    if (!shrink_chunk || chunk <= 2)
+      return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, P.L.total);
+    chunk >>= 1;
+  }
+  const WsLayout &L = P.L;
+  const int maxn = P.maxn;
+  // stage the descriptor into the workspace (one host buffer, one copy); the
+  // zeros also clear the counters and flags
   std::vector<unsigned char> host(L.par, 0);
   std::memcpy(host.data() + L.n, n_host, nmat * 4);
   std::memcpy(host.data() + L.off, off_host, nmat * 8);
-  std::memcpy(host.data() + L.soff, soff.data(), nmat * 8);
-  std::memcpy(host.data() + L.poff, poff.data(), nmat * 8);
-  std::memcpy(host.data() + L.order, order.data(), nmat * 4);
-  std::memcpy(host.data() + L.aoff, aoff.data(), nmat * 8);
+  std::memcpy(host.data() + L.soff, P.soff.data(), nmat * 8);
+  std::memcpy(host.data() + L.poff, P.poff.data(), nmat * 8);
+  std::memcpy(host.data() + L.order, P.order.data(), nmat * 4);
+  std::memcpy(host.data() + L.aoff, P.aoff.data(), nmat * 8);
   unsigned char *wsb = static_cast<unsigned char *>(ws);
   hipError_t e = hipMemcpyAsync(wsb, host.data(), L.par, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(KSVD2_EHIP, "descriptor upload: %s", hipGetErrorString(e));
@@ -1634,6 +1811,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.ord = ordering;
   d.aoff = reinterpret_cast<const int64_t *>(wsb + L.aoff);
   d.galt = wsb + L.galt;
+  d.chunk = P.chunk;
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
   R *par = reinterpret_cast<R *>(wsb + L.par);
@@ -1661,6 +1839,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     if (minrows < 1)
       return fail(KSVD2_EINVAL, "order %d too large for the U/V tile", maxn);
     unsigned apply_tiles = (unsigned)((maxn + minrows - 1) / minrows);
+    const int cm = P.chunk - 1;
     std::vector<int32_t> done(nmat);
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int k = 0; k < maxn - 1; ++k) {
@@ -1668,7 +1847,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
                            st, d, G, par, pairs, k);
         hipLaunchKernelGGL(k_sw_update<R>, dim3(grid_for(maxblocks), (unsigned)nmat),
                            dim3(kBlock), 0, st, d, G, par, pairs, k);
-        if (k % kChunk == kChunk - 1 || k == maxn - 2)
+        if ((k & cm) == cm || k == maxn - 2)
           hipLaunchKernelGGL(k_sw_apply<R>, dim3(apply_tiles, 2, (unsigned)nmat),
                              dim3(kApplyBlock), apply_lds, st, d, U, V, par, k, apply_elems);
       }
@@ -1685,37 +1864,10 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     return launch_status("kog_sweep finish");
   }
 
-  // modes 1 and 2: one persistent launch per order bucket, longest first
-  Tune tune;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    tune = g_tune;
-  }
-  int di = (w == 8) ? 1 : 0;
-  struct Seg {
-    int begin, count, maxn, block;
-  };
-  std::vector<Seg> segs;
-  for (int64_t a = 0; a < nmat;) {
-    int b0 = bucket_of(n_host[order[a]]);
-    int64_t bb = a;
-    while (bb < nmat && bucket_of(n_host[order[bb]]) == b0) ++bb;
-    segs.push_back(Seg{(int)a, (int)(bb - a), n_host[order[a]], tune.block[di][b0]});
-    a = bb;
-  }
-  size_t lds_limit = device_lds_limit();
-  // one launch over all matrices, longest first, when the buckets agree on the
-  // workgroup size: the dispatcher then starts each next matrix as soon as a
-  // CU frees up, with no drain between buckets
-  bool same_block = std::all_of(segs.begin(), segs.end(),
-                                [&](const Seg &x) { return x.block == segs[0].block; });
-  if (same_block && segs.size() > 1)
-    segs = {Seg{0, (int)nmat, n_host[order[0]], segs[0].block}};
   auto launch_all = [&]() -> int {
-    for (const Seg &s : segs) {
-      int rc = launch_persistent<R>(d, order_dev + s.begin, s.count, s.maxn, s.block, G, U, V,
-                                    par, sigma, sweeps_out, max_sweeps, tolf, accumulate,
-                                    lds_limit, st);
+    for (const Seg &s : P.segs) {
+      int rc = launch_persistent<R>(d, order_dev + s.begin, s, G, U, V, par, sigma, sweeps_out,
+                                    max_sweeps, tolf, accumulate, st);
       if (rc) return rc;
     }
     return KSVD2_OK;
@@ -1723,15 +1875,23 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   if (mode == 1) return launch_all();
 
   // mode 2: capture the launches once per argument set, then replay
-  GraphKey key{dtype, mode, ordering, nmat, G, U, V, sigma, sweeps_out, ws, max_sweeps, accumulate,
-               tolf, st, std::vector<int32_t>(n_host, n_host + nmat),
-               std::vector<int64_t>(off_host, off_host + nmat), 0};
-  for (int b = 0; b < 5; ++b) key.tune_hash = key.tune_hash * 31 + tune.block[di][b];
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(KSVD2_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  GraphKey key{dev, dtype, ordering, nmat, G, U, V, sigma, sweeps_out, ws, max_sweeps,
+               accumulate, tolf, st, std::vector<int32_t>(n_host, n_host + nmat),
+               std::vector<int64_t>(off_host, off_host + nmat), {}};
+  for (const Seg &s : P.segs)
+    key.tune.insert(key.tune.end(), {s.block, s.two, s.inplace_ok, s.tile_elems});
+  key.tune.push_back(P.chunk);
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) exec = it->second;
+    if (it != g_graphs.end()) {
+      exec = it->second.exec;
+      it->second.used = ++g_graph_clock;
+    }
   }
   if (!exec) {
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -1748,7 +1908,8 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(KSVD2_EHIP, "graph instantiate: %s", hipGetErrorString(e));
     std::lock_guard<std::mutex> lk(g_mu);
-    g_graphs[key] = exec;
+    graph_evict_one();
+    g_graphs[key] = GraphEntry{exec, ++g_graph_clock};
   }
   e = hipGraphLaunch(exec, st);
   if (e != hipSuccess) return fail(KSVD2_EHIP, "graph launch: %s", hipGetErrorString(e));
@@ -1861,7 +2022,9 @@ size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host) 
     npiv += nm / 2;
     nsq += nm * nm;
   }
-  size_t a = ws_layout(nmat, npiv, nsq, dtype ? 8 : 4).total;
+  // every mode, ordering and tuning: the longest chunk, the pair table and a
+  // second buffer for every matrix
+  size_t a = ws_layout(nmat, npiv, kChunk, true, nsq, dtype ? 8 : 4).total;
   size_t b = align256(nmat * 4) + align256(nmat * 8) * 2;
   return std::max(a, b);
 }
@@ -1874,21 +2037,41 @@ int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_
   if (dtype == 1)
     return sweep_impl<double>(1, nmat, n_host, off_host, (double *)G, (double *)U, (double *)V,
                               (double *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate,
-                              mode, ordering, workspace, ws_bytes, st);
+                              mode, ordering, workspace, ws_bytes, st, false);
   if (dtype == 0)
     return sweep_impl<float>(0, nmat, n_host, off_host, (float *)G, (float *)U, (float *)V,
                              (float *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate, mode,
-                             ordering, workspace, ws_bytes, st);
+                             ordering, workspace, ws_bytes, st, false);
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
 }
 
+int kog_sweep_set_tuning(int dtype, int bucket, int knob, int value) {
+  if (dtype != 0 && dtype != 1) return fail(KSVD2_EDTYPE, "dtype must be 0 or 1");
+  if (bucket < -1 || bucket > 4) return fail(KSVD2_EINVAL, "bucket must be in [-1, 4]");
+  int rc = tune_check(knob, value);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int b = 0; b < 5; ++b)
+    if (bucket == -1 || bucket == b) g_tune.v[dtype][b][knob] = value;
+  return KSVD2_OK;
+}
+
 int kog_sweep_tune(int dtype, int bucket, int block) {
+  if (bucket < 0) return fail(KSVD2_EINVAL, "bucket must be in [0, 4]");
+  return kog_sweep_set_tuning(dtype, bucket, K_BLOCK, block);
+}
+
+int kog_sweep_get_tuning(int dtype, int bucket, int knob) {
   if (dtype != 0 && dtype != 1) return fail(KSVD2_EDTYPE, "dtype must be 0 or 1");
   if (bucket < 0 || bucket > 4) return fail(KSVD2_EINVAL, "bucket must be in [0, 4]");
-  if (block != 256 && block != 512 && block != 1024)
-    return fail(KSVD2_EINVAL, "block must be 256, 512 or 1024");
+  if (knob < 0 || knob >= K_NKNOB) return fail(KSVD2_EINVAL, "unknown knob %d", knob);
   std::lock_guard<std::mutex> lk(g_mu);
-  g_tune.block[dtype][bucket] = block;
+  return g_tune.v[dtype][bucket][knob];
+}
+
+int kog_sweep_reset_tuning(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tune = default_tune();
   return KSVD2_OK;
 }
 

@@ -209,5 +209,25 @@ def svd_rect(mats, max_sweeps: int = 40, tol_factor: float = 1.0, mode="persiste
     return res, out["sweeps"].cpu().numpy()
 
 
-def set_tuning(dtype, bucket: int, block: int):
-    _lib.check(_lib.lib().kog_sweep_tune(_DT[dtype], bucket, block), "kog_sweep_tune")
+# knobs of the persistent sweep's tuning table (kog_sweep_set_tuning); none of them
+# changes a bit of the results
+KNOBS = {"block": 0, "chunk": 1, "two": 2, "inplace": 3, "rows": 4}
+
+
+def set_tuning(dtype, bucket: int, block: int | None = None, **knobs):
+    """Set entries of the tuning table for an order bucket (-1: every bucket):
+    ``block`` and any of the KNOBS as keywords."""
+    if block is not None:
+        knobs["block"] = block
+    for k, v in knobs.items():
+        _lib.check(_lib.lib().kog_sweep_set_tuning(_DT[dtype], bucket, KNOBS[k], int(v)),
+                   "kog_sweep_set_tuning")
+
+
+def get_tuning(dtype, bucket: int) -> dict:
+    L = _lib.lib()
+    return {k: int(L.kog_sweep_get_tuning(_DT[dtype], bucket, v)) for k, v in KNOBS.items()}
+
+
+def reset_tuning():
+    _lib.check(_lib.lib().kog_sweep_reset_tuning(), "kog_sweep_reset_tuning")

@@ -83,7 +83,7 @@ def test_sweep_arguments_rejected(L):
     assert L.kog_sweep_batch(*args(n, 1, 1 << 20)) == -1
     assert b"even" in L.ksvd2_last_error()
     n2 = np.array([4, 6], dtype=np.int32)
-    assert L.kog_sweep_batch(*args(n2, 1, 16)) == -4                 # workspace too small
+    assert L.kog_sweep_batch(*args(n2, 0, 16)) == -4                 # workspace too small
     need = L.kog_sweep_workspace_size(1, 2, n2.ctypes.data_as(ctypes.c_void_p))
     assert need >= 8 * (4 * 4 + 6 * 6)                                # holds a second G
     assert L.kog_sweep_batch(*args(n2, 2, need)) == -1                # graph mode, null stream
@@ -91,3 +91,29 @@ def test_sweep_arguments_rejected(L):
     assert L.kog_sweep_batch(*args(n2, 1, need, 2)) == -1             # bad ordering
     assert b"ordering" in L.ksvd2_last_error()
     assert L.kog_sweep_tune(1, 9, 256) == -1 and L.kog_sweep_tune(1, 0, 300) == -1
+
+
+def test_sweep_tuning_table(L):
+    """The tuning knobs: defaults, per-bucket and all-bucket settings, range checks."""
+    try:
+        assert L.kog_sweep_reset_tuning() == 0
+        assert [L.kog_sweep_get_tuning(1, b, 0) for b in range(5)] == [256, 512, 512, 1024, 1024]
+        assert L.kog_sweep_get_tuning(0, 2, 1) == 128                  # chunk
+        assert L.kog_sweep_get_tuning(0, 2, 2) == 1 and L.kog_sweep_get_tuning(0, 2, 3) == 1
+        assert L.kog_sweep_get_tuning(0, 2, 4) == 0                    # rows: as many as fit
+        assert L.kog_sweep_set_tuning(1, -1, 1, 32) == 0
+        assert [L.kog_sweep_get_tuning(1, b, 1) for b in range(5)] == [32] * 5
+        assert L.kog_sweep_get_tuning(0, 0, 1) == 128                  # the other dtype
+        assert L.kog_sweep_set_tuning(1, 3, 4, 24) == 0 and L.kog_sweep_get_tuning(1, 3, 4) == 24
+        assert L.kog_sweep_set_tuning(1, 0, 1, 48) == -1               # not a power of two
+        assert L.kog_sweep_set_tuning(1, 0, 1, 256) == -1              # above 128
+        assert L.kog_sweep_set_tuning(1, 0, 2, 2) == -1
+        assert L.kog_sweep_set_tuning(1, 0, 9, 0) == -1
+        assert L.kog_sweep_set_tuning(1, 5, 0, 256) == -1
+        assert L.kog_sweep_set_tuning(3, 0, 0, 256) == -2
+        assert L.kog_sweep_get_tuning(1, 0, 7) < 0
+        assert L.kog_sweep_tune(1, 2, 1024) == 0 and L.kog_sweep_get_tuning(1, 2, 0) == 1024
+        assert L.kog_sweep_tune(1, -1, 256) == -1
+    finally:
+        L.kog_sweep_reset_tuning()
+
