@@ -30,13 +30,16 @@ sys.path.insert(0, ROOT)
 METRIC = ("2x2 SVDs/sec (fwd, fwd+bwd) FP64/FP32; %HBM roofline; max rel err σ2 (ulp)")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_VECTOR_TFLOPS = 78.6      # 256 CU x 64 lanes x 2.4 GHz x 2 (an FMA counts twice)
-# algorithmic FP work per matrix of the forward method (main class-15 path): about 8
-# correctly rounded hypot (~45 VALU slots each in FP64), 18 IEEE divisions (~13 slots),
-# ~45 add/mul/fma, the double-word EXT block and ~25 exponent operations -> ~700 VALU
-# slots per FP64 matrix (~400 for FP32, hypot evaluated in binary64); a slot is priced
-# as one FMA = 2 flops against the FP64 vector peak
+# VALU lane-operation peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction
+# occupies a SIMD for 4 cycles; binary64 FMA at this full rate is the 78.6 TFLOP/s above)
+VALU_LANE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic work per matrix of the forward method (main class-15 path), in VALU lane
+# operations: about 8 correctly rounded hypot (~45 each in FP64), 18 IEEE divisions (~13),
+# ~45 add/mul/fma, the double-word EXT block and ~25 exponent operations -> ~700 per FP64
+# matrix (~400 for FP32, hypot evaluated in binary64)
 ALG_VALU_SLOTS = {np.float64: 700, np.float32: 400}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pmc_traffic_k_fwd_soa_f64.md")
+VALU_PROFILE = os.path.join(ROOT, "profiles", "pmc_valu_2x2_kernels.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_13116_amd", "csrc", f)
                   for f in ("ksvd2_device.hpp", "ksvd2_kernels.hip", "abi_common.hpp")]
 BYTES_FWD = {np.float64: 92, np.float32: 52}      # algorithmic bytes per matrix (in + out)
@@ -47,11 +50,16 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    # the GPU clock ramps up over the first ~25 ms of back-to-back launches
+    # untimed steps after the clock-settling phase (settle())
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline only")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--profile-workload", default=None,
+                    help="run one named workload for a profiler and exit (see "
+                         "PROFILE_WORKLOADS)")
+    ap.add_argument("--reps", type=int, default=3, help="launches after the first, with "
+                    "--profile-workload")
     return ap.parse_args()
 
 
@@ -59,11 +67,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_loop(fn, steps, warmup):
-    """Warm up, then time exactly `steps` calls: wall clock between two synchronisations,
-    and HIP events recorded on the launch stream around the same region."""
+SETTLE_S = 0.25   # the GPU clock ramps up over the first ~25 ms of back-to-back launches
+
+
+def settle(fn, seconds=SETTLE_S):
+    """Run fn back to back for at least `seconds` (untimed, before the warm-up steps) so
+    that the timed steps do not sit inside the clock ramp; returns the calls made."""
     import torch
 
+    calls, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(4):
+            fn()
+        calls += 4
+        torch.cuda.synchronize()
+    return calls
+
+
+def timed_loop(fn, steps, warmup):
+    """Settle the clock, do `warmup` untimed calls, then time exactly `steps` calls: wall
+    clock between two synchronisations, and HIP events recorded on the launch stream
+    around the same region."""
+    import torch
+
+    settle(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -278,25 +305,53 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def _profile_values(path):
+    """The `- key: value` lines of a committed counter summary."""
+    kv = {}
+    if not os.path.exists(path):
+        return kv
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    return kv
+
+
 def measured_traffic(batch):
     """HBM bytes per launch of the FP64 forward kernel from the committed rocprofv3
     --pmc summary (FETCH_SIZE scaled by the copy-kernel calibration factor, plus
     WRITE_SIZE), or None when that summary was taken on other kernel sources or another
     batch size."""
-    if not os.path.exists(TRAFFIC_PROFILE):
-        return None
-    kv = {}
-    with open(TRAFFIC_PROFILE) as fh:
-        for line in fh:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                kv[k.strip()] = v.strip().strip("`")
+    kv = _profile_values(TRAFFIC_PROFILE)
     try:
         if kv["kernel_source_sha256"] != kernel_source_hash() or int(kv["batch"]) != batch:
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def measured_issue(batch, ms):
+    """What the FP64 forward kernel issues, from the committed SQ counter summary (taken
+    on the same kernel sources, else None): VALU instructions per wave (= lane operations
+    per matrix, one matrix per lane) and binary64 flops per matrix (add, mul, 2 x fma,
+    transcendental), turned into rates with this run's launch time."""
+    kv = _profile_values(VALU_PROFILE)
+    try:
+        if kv["kernel_source_sha256"] != kernel_source_hash():
+            return None
+        valu = float(kv["fwd64_valu_per_wave"])
+        flops = float(kv["fwd64_fp64_flops_per_matrix"])
+    except (KeyError, ValueError):
+        return None
+    t = ms * 1e-3
+    return {"valu_lane_ops_per_matrix": valu,
+            "issued_T_lane_ops_per_s": valu * batch / t / 1e12,
+            "issue_frac": valu * batch / t / 1e12 / VALU_LANE_PEAK_T,
+            "fp64_flops_per_matrix": flops,
+            "fp64_TFLOPs": flops * batch / t / 1e12,
+            "fp64_frac": flops * batch / t / 1e12 / FP64_VECTOR_TFLOPS}
 
 
 def cpu_baseline(seconds):
@@ -373,21 +428,124 @@ def oracle_beside(kind, seconds=2.0):
 
 def roofline(f64):
     """The FP64 forward kernel is bound by VALU issue (its algorithmic bytes need only a
-    quarter of HBM bandwidth at the measured rate): achieved = algorithmic FP work per
-    launch / the kernel's average duration (HIP events on its launch stream)."""
+    third of HBM bandwidth at the measured rate): achieved = the method's algorithmic
+    VALU lane operations per launch (700 per matrix) / the kernel's average duration (HIP
+    events on its launch stream), against the chip's VALU lane-operation peak; beside it,
+    what the kernel actually issues (counter summary) at this run's speed."""
     B, ms = f64["B"], f64["ms_kernel"]
-    achieved = 2.0 * ALG_VALU_SLOTS[np.float64] * B / (ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_VECTOR_TFLOPS, "traffic": measured_traffic(B),
+    achieved = ALG_VALU_SLOTS[np.float64] * B / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_LANE_PEAK_T,
+            "unit": "T VALU lane-ops/s", "frac": achieved / VALU_LANE_PEAK_T,
+            "traffic": measured_traffic(B),
             "kernel": "k_fwd_soa<double>", "avg_kernel_ms": ms, "batch": B,
-            "alg_valu_slots_per_matrix": ALG_VALU_SLOTS[np.float64],
+            "alg_valu_lane_ops_per_matrix": ALG_VALU_SLOTS[np.float64],
+            "measured": measured_issue(B, ms),
             "hbm": {"achieved_GBs": f64["GBs"], "peak_GBs": HBM_PEAK_GBS,
                     "frac": f64["GBs"] / HBM_PEAK_GBS,
                     "alg_bytes_per_matrix": BYTES_FWD[np.float64]}}
 
 
+def _class_batch(dtype, tri, B=1 << 22, seed=31):
+    from paper_2407_13116_amd import inputs
+
+    rng = np.random.default_rng(seed)
+    G = inputs.signed_pow2_entries(rng, (B, 2, 2), -20, 20, dtype)
+    if tri:
+        G[:, 1, 0] = 0
+    return inputs.soa_from_mats(G)
+
+
+PROFILE_WORKLOADS = """
+  fwd64 / fwd32     the 2^24-matrix forward workload (k_fwd_soa)
+  fast64 / fast32   the same workload, the variant without a correctly rounded hypot
+  cls15_64 / cls13_64 / cls15_32 / cls13_32
+                    2^22 matrices of one class only (general, upper triangular; exponents
+                    in [-20,20]): no lane divergence between classes, so the per-wave VALU
+                    instruction count is the per-matrix path length of that class
+  bwd64 / bwd32     the 2^22-matrix backward (k_bwd) after one forward (k_fwd_full)
+  bwdsoa64 / bwdsoa32  the 2^22-matrix backward on the SoA planes (k_bwd_soa)
+  cplx128 / cplx64  the 2^22-matrix complex 2x2 SVD (k_fwd_c)
+  rect64            256 tall 512 x 256 FP64 matrices: k_qrcp, the sweep, k_qapply
+  copy              a plain 1 GiB device-to-device copy (counter calibration: FETCH_SIZE
+                    and WRITE_SIZE should each read 1 GiB)
+  sweep4            one persistent sweep of the 256 x (n=256) FP64 workload
+  sweep4rr          the same with the round-robin ordering
+"""
+
+
+def profile_workload(w, reps):
+    """One named workload for a profiling run (rocprofv3 --kernel-trace / --pmc): the
+    kernel launched 1 + reps times on the same inputs, no timing, no JSON line."""
+    import torch
+
+    from paper_2407_13116_amd import api, inputs
+
+    dev = lambda *a: [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in a]
+
+    def fwd(g, fast=False):
+        d = dev(*g)
+        out = api.ksvd2_batch(*d, plain=False, fast=fast)
+        for _ in range(reps):
+            api.ksvd2_batch(*d, plain=False, out=out, fast=fast)
+
+    if w in ("fwd64", "fwd32", "fast64", "fast32"):
+        fwd(inputs.forward_sweep(np.float64 if w.endswith("64") else np.float32),
+            fast=w.startswith("fast"))
+    elif w.startswith("cls"):
+        fwd(_class_batch(np.float64 if w.endswith("64") else np.float32,
+                         tri=w.startswith("cls13")))
+    elif w in ("bwd64", "bwd32"):
+        G, dS, dU, dV, _ = inputs.diff_batch(np.float64 if w == "bwd64" else np.float32)
+        t = dev(G, dS, dU, dV)
+        U, S, V = api.svd2x2_raw(t[0])
+        for _ in range(reps + 1):
+            api.svd2x2_backward(U, S, V, t[1], t[2], t[3])
+    elif w in ("bwdsoa64", "bwdsoa32"):
+        dt = np.float64 if w == "bwdsoa64" else np.float32
+        G, dS, dU, dV, _ = inputs.diff_batch(dt)
+        g = dev(*inputs.soa_from_mats(G))
+        out = api.ksvd2_batch(*g, plain=True)
+        up = dev(*(np.ascontiguousarray(x) for x in (dS[:, 0], dS[:, 1])),
+                 *(np.ascontiguousarray(dU[:, i, j]) for j in range(2) for i in range(2)),
+                 *(np.ascontiguousarray(dV[:, i, j]) for j in range(2) for i in range(2)))
+        for _ in range(reps + 1):
+            api.ksvd2_backward_soa(out, up[0], up[1], up[2:6], up[6:10])
+    elif w in ("cplx128", "cplx64"):
+        G = torch.from_numpy(inputs.complex_batch(np.complex128 if w == "cplx128"
+                                                  else np.complex64)).cuda()
+        for _ in range(reps + 1):
+            api.ksvd2c(G)
+    elif w == "rect64":
+        from paper_2407_13116_amd import sweep as sw
+
+        pr = sw.PackedRect(inputs.rect_batch(), dtype=np.float64)
+        for _ in range(reps):
+            pr.reset()
+            sw.svd_rect_device(pr)
+    elif w == "copy":
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(reps):
+            dst.copy_(src)
+    elif w in ("sweep4", "sweep4rr"):
+        from paper_2407_13116_amd import sweep as sw
+
+        p = sw.Packed(inputs.sweep_uniform())
+        for _ in range(reps):
+            sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="persistent",
+                               ordering="round-robin" if w == "sweep4rr" else "modulus")
+    else:
+        print(f"unknown workload {w}; one of:{PROFILE_WORKLOADS}", file=sys.stderr)
+        return 2
+    torch.cuda.synchronize()
+    log(f"[bench] profile workload {w}: done")
+    return 0
+
+
 def main():
     args = parse()
+    if args.profile_workload:
+        sys.exit(profile_workload(args.profile_workload, args.reps))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the batched 2x2 "
               "SVD shards by matrix with no communication, and runs on several GPUs are not "
@@ -422,10 +580,10 @@ def main():
     if not args.no_extra:
         log("[bench] FP32 forward, 2^24 matrices")
         f32, g32, h32 = fwd_case(np.float32, args.steps, args.warmup)
+        a32 = ALG_VALU_SLOTS[np.float32] * f32["B"] / (f32["ms_kernel"] * 1e-3) / 1e12
         extra["fwd_f32"] = {"rate": f32["rate"], "ms_per_launch": f32["ms_kernel"],
                             "GBs": f32["GBs"], "hbm_frac": f32["GBs"] / HBM_PEAK_GBS,
-                            "alg_TFLOPs": 2.0 * ALG_VALU_SLOTS[np.float32] * f32["B"]
-                            / (f32["ms_kernel"] * 1e-3) / 1e12}
+                            "alg_T_lane_ops": a32, "alu_frac": a32 / VALU_LANE_PEAK_T}
         fast_err = {}
         for dt, name in ((np.float64, "fwd_fast_f64"), (np.float32, "fwd_fast_f32")):
             log(f"[bench] {name}: the variant without a correctly rounded hypot, 2^24")
