@@ -590,84 +590,100 @@ template <bool CR, class R> static Part<R> svd_z5(const M2<R> &G, int t) {
 
 /* The SVD of R~ = [a b; 0 d] with a >= d > 0, b > 0 (Sect. 3.3.1). */
 template <class R> struct Tri {
-  R cphi, sphi, tphi, sec_phi; /* functions of phi (Algorithm tf) */
-  R cpsi, spsi, tpsi;          /* functions of psi (Algorithm tp) */
+  R cphi, sphi, tphi, sec_phi; /* functions of phi */
+  R cpsi, spsi, tpsi;          /* functions of psi */
   EF<R> s1, s2;                /* sigma~' after the ordering */
   bool psig;                   /* P_sigma = X */
   bool ovf;                    /* tan(psi) overflowed */
 };
 
+/* The expressions Sect. 3.3.1 gives for tan(2 phi) of [a b; 0 d], and the
+   conditions under which each one is the one to use.  When several conditions
+   hold, the one named first below decides (the precedence of Algorithm tf). */
+enum class T2phi {
+  diag_equal,   /* a = d: the squares cancel exactly; eq. t2f'', 2d/b         */
+  offd_equal,   /* b = d: eq. t2f''', 2bd / a^2 in (e,f) arithmetic           */
+  a_negligible, /* fl(a/b) < eps: a^2 vanishes beside b^2; eq. t2f'' again    */
+  no_cr_hypot,  /* the variant for a hypot that is not correctly rounded      */
+  right_angle,  /* hypot(a, b) = d: the denominator is zero, 2 phi = pi/2    */
+  general       /* eq. t2f': 2bd / ((h - d)(h + d)) with h = hypot(a, b)      */
+};
+
+template <bool CR, class R> static T2phi t2phi_case(R a, R b, R d, R &h) {
+  h = (R)0;
+  if (a == d) return T2phi::diag_equal;
+  if (b == d) return T2phi::offd_equal;
+  if (a / b < Fmt<R>::eps()) return T2phi::a_negligible;
+  if (!CR) return T2phi::no_cr_hypot;
+  h = cr_hypot(a, b);
+  return (h == d) ? T2phi::right_angle : T2phi::general;
+}
+
+/* tan(2 phi) = 2bd / (a^2 + b^2 - d^2) of R~, evaluated by the expression
+   t2phi_case selects; (e,f) expressions are evaluated left to right. */
+template <bool CR, class R> static R tan_2phi(R a, R b, R d) {
+  R h;
+  const EF<R> two_bd = ef_mul(ef_pow2(1, ef_of(b)), ef_of(d)); /* 2 (.) b (.) d */
+  switch (t2phi_case<CR>(a, b, d, h)) {
+    case T2phi::diag_equal:
+    case T2phi::a_negligible:
+      return ((R)2 * d) / b;
+    case T2phi::offd_equal:
+      return ef_fl(ef_div(two_bd, ef_mul(ef_of(a), ef_of(a))));
+    case T2phi::right_angle:
+      return (R)INFINITY;
+    case T2phi::general:
+      return ef_fl(ef_div(two_bd, ef_mul(ef_minus(h, d), ef_plus(h, d))));
+    case T2phi::no_cr_hypot:
+      break;
+  }
+  /* No squares of the inputs: divide the numerator and the denominator by the
+     square of m = max(a, b).  With x = min(a, b)/m and y = d/m, the denominator
+     becomes 1 + (x - y)(x + y) (one fma); the numerator is 2xy when a is the
+     larger and 2y when b is.  A negative denominator counts as zero. */
+  const bool a_big = a > b;
+  const R x = a_big ? b / a : a / b;
+  const R y = a_big ? d / a : d / b;
+  const R num = a_big ? ((R)2 * x) * y : (R)2 * y;
+  return num / std::max(std::fma(x - y, x + y, (R)1), (R)0);
+}
+
 template <bool CR, class R> static Tri<R> tri_svd(R a, R b, R d) {
-  const R eps = Fmt<R>::eps();
-  const R inf = (R)INFINITY;
   Tri<R> o;
-  /* Algorithm tf: tan(2 phi), in the listed order of cases */
-  R t2;
-  if (a == d) {
-    t2 = ((R)2 * d) / b; /* eq. t2f'' */
-  } else if (b == d) {   /* eq. t2f''' */
-    t2 = ef_fl(ef_div(ef_mul(ef_pow2(1, ef_of(b)), ef_of(d)), ef_mul(ef_of(a), ef_of(a))));
-  } else if (a / b < eps) {
-    t2 = ((R)2 * d) / b; /* eq. t2f'' */
-  } else if (!CR) {
-    /* hypot not correctly rounded: x and y are the smaller of a, b and d
-       divided by the larger of a, b, and tan(2 phi) = 2xy / (1 + (x-y)(x+y))
-       when a is the larger, 2y / (1 + (x-y)(x+y)) when b is; no square of an
-       input is formed, and a negative denominator is taken as 0 */
-    R x, y;
-    if (a > b) {
-      x = b / a;
-      y = d / a;
-      t2 = (((R)2 * x) * y) / std::max(std::fma(x - y, x + y, (R)1), (R)0);
-    } else {
-      x = a / b;
-      y = d / b;
-      t2 = ((R)2 * y) / std::max(std::fma(x - y, x + y, (R)1), (R)0);
-    }
-  } else {
-    R h = cr_hypot(a, b);
-    if (h == d) {
-      t2 = inf; /* eq. t2f' */
-    } else {
-      EF<R> s = ef_plus(h, d), df = ef_minus(h, d);
-      t2 = ef_fl(ef_div(ef_mul(ef_pow2(1, ef_of(b)), ef_of(d)), ef_mul(df, s)));
-    }
-  }
-  /* tan(phi) by eq. tf, then sec, cos, sin */
-  R tphi = (t2 == inf) ? (R)1 : t2 / ((R)1 + hyp<CR>(t2, (R)1));
-  R sec_phi = hyp<CR>(tphi, (R)1);
-  o.tphi = tphi;
-  o.sec_phi = sec_phi;
-  o.cphi = (R)1 / sec_phi;
-  o.sphi = tphi / sec_phi;
-  /* Algorithm tp: tan(psi) by eq. tp, the singular values by eq. s' or,
-     when tan(psi) overflows, by eq. tp' and the sigma assignments of
-     Algorithm tp */
-  R t = std::fma(d, tphi, b);
-  R tpsi = t / a;
-  o.tpsi = tpsi;
-  EF<R> s1, s2;
-  if (tpsi == inf) {
-    o.ovf = true;
-    EF<R> tt = ef_of(t);
-    EF<R> cpsi = ef_div(ef_of(a), tt);
-    o.cpsi = ef_fl(cpsi);
+  /* phi: tan(phi) from tan(2 phi) by eq. tf (2 phi = pi/2 gives tan(phi) = 1),
+     then sec, cos, sin */
+  const R t2 = tan_2phi<CR>(a, b, d);
+  o.tphi = std::isinf(t2) ? (R)1 : t2 / ((R)1 + hyp<CR>(t2, (R)1));
+  o.sec_phi = hyp<CR>(o.tphi, (R)1);
+  o.cphi = (R)1 / o.sec_phi;
+  o.sphi = o.tphi / o.sec_phi;
+  /* psi: tan(psi) = (b + d tan(phi)) / a by eq. tp, the numerator by one fma */
+  const R num = std::fma(d, o.tphi, b);
+  o.tpsi = num / a;
+  o.ovf = std::isinf(o.tpsi);
+  EF<R> big, small;
+  if (o.ovf) {
+    /* eq. tp': cos(psi) = a / num in (e,f) form, sin(psi) = 1; the singular
+       values then follow Algorithm tp: num and d cos(psi) */
+    const EF<R> cos_psi = ef_div(ef_of(a), ef_of(num));
+    o.cpsi = ef_fl(cos_psi);
     o.spsi = (R)1;
-    s1 = tt;
-    s2 = ef_mul(ef_of(d), cpsi);
+    big = ef_of(num);
+    small = ef_mul(ef_of(d), cos_psi);
   } else {
-    o.ovf = false;
-    R sec_psi = hyp<CR>(tpsi, (R)1);
+    /* eq. s': with the ratio sec(phi) / sec(psi), sigma_1 = a / ratio and
+       sigma_2 = d * ratio */
+    const R sec_psi = hyp<CR>(o.tpsi, (R)1);
     o.cpsi = (R)1 / sec_psi;
-    o.spsi = tpsi / sec_psi;
-    EF<R> sp = ef_div(ef_of(sec_phi), ef_of(sec_psi));
-    s1 = ef_div(ef_of(a), sp);
-    s2 = ef_mul(ef_of(d), sp);
+    o.spsi = o.tpsi / sec_psi;
+    const EF<R> ratio = ef_div(ef_of(o.sec_phi), ef_of(sec_psi));
+    big = ef_div(ef_of(a), ratio);
+    small = ef_mul(ef_of(d), ratio);
   }
-  o.psig = ef_prec(s1, s2);
-  if (o.psig) std::swap(s1, s2);
-  o.s1 = s1;
-  o.s2 = s2;
+  /* order by eq. prec: P_sigma = X when the first is strictly the smaller */
+  o.psig = ef_prec(big, small);
+  o.s1 = o.psig ? small : big;
+  o.s2 = o.psig ? big : small;
   return o;
 }
 
