@@ -308,3 +308,53 @@ def test_worked_example(orc, dtype):
             rounded = +exact          # round-to-nearest-even to p bits
         with mpmath.workprec(600):
             assert rounded == mpmath.ldexp(mpmath.mpf(float.fromhex(fh)), e)
+
+
+PSIG, RSWAP = 1 << 13, 1 << 11
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("fast", [False, True])
+def test_psigma_swap_not_taken_near_degenerate(orc, dtype, fast):
+    """Algorithm tp's reordering P_sigma needs sigma~1'' < sigma~2'', i.e. sec(phi) >
+    sec(psi) after rounding, i.e. tan(phi) > tan(psi) as computed.  Exactly, tan(psi) >=
+    (a/d) tan(phi) for [a b; 0 d] with a >= d; the computed values could only invert
+    where a - d is an ulp or so and b < 2(a - d) (the near-degenerate triangular
+    matrices), and there the relations of the roundings exclude it for the correctly
+    rounded hypot (the argument is written out with the readings of the paper).  Pinned on
+    that region: a in [1, 2), d = a - j ulp (j = 1, 2, 3), b = x (a - d), x log-uniform
+    in [0.005, 20]; no P_sigma swap, and sec(phi) <= sec(psi) (cos(phi) >= cos(psi))."""
+    rng = np.random.default_rng(77)
+    N = 1 << 20
+    u = np.finfo(dtype).eps
+    a = (1 + rng.random(N)).astype(dtype)
+    d = (a - rng.integers(1, 4, N) * u).astype(dtype)
+    x = np.exp(rng.uniform(np.log(0.005), np.log(20), N))
+    b = ((a.astype(np.float64) - d.astype(np.float64)) * x).astype(dtype)
+    o = orc.ksvd2(a, np.zeros_like(a), b, d, plain=False, fast=fast)
+    assert np.all(((o["info"] >> 4) & 15) == 13)            # [a b; 0 d]: class 13
+    assert not np.any(o["info"] & (PSIG | RSWAP))
+    assert np.all(np.abs(o["cu"]) >= np.abs(o["cv"]))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_class15_wide_spread_never_swapped(orc, dtype):
+    """tan(psi) can underflow to 0 only when r12/r11 is below about 2^-1127 (2^-150 in
+    binary32), which in class 15 needs an exponent spread above the format's range
+    within a column or across the second column; the diagonal of R then stays in
+    order (r11 >= r22), so the swapped case, where tan(phi-bar) = 1/tan(psi) would be
+    infinite, is not reached.  Pinned on class-15 matrices with such spreads:
+    [g11 g12; g21 g22] with g21/g11 and g12/g22 tiny, |g22| near |g11|."""
+    rng = np.random.default_rng(78)
+    N = 1 << 18
+    lo, hi = (-1074, 1020) if dtype == np.float64 else (-149, 124)
+    big = inputs.signed_pow2_entries(rng, (N,), hi - 2, hi, dtype)
+    g11 = np.abs(big)
+    g22 = (g11 * (1 - rng.integers(0, 3, N) * np.finfo(dtype).eps) *
+           rng.choice([-1, 1], N)).astype(dtype)
+    g21 = inputs.signed_pow2_entries(rng, (N,), lo, lo + 40, dtype)
+    g12 = inputs.signed_pow2_entries(rng, (N,), lo, lo + 40, dtype)
+    o = orc.ksvd2(g11, g21, g12, g22, plain=False)
+    cls15 = (o["info"] & 15) == 15
+    assert cls15.mean() > 0.9
+    assert not np.any(o["info"][cls15] & RSWAP)
