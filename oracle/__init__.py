@@ -72,6 +72,7 @@ def lib():
             fn.restype = i32
             fn.argtypes = [i32, p, p, p, i32, d, i32, i32, ctypes.POINTER(i32)]
         L.orc_step_pairs.argtypes = [i32, i32, i32, p]
+        L.orc_dynamic_pairs_f64.argtypes = [i32, p, p]
         for t in ("f64", "f32"):
             getattr(L, "orc_qrcp_" + t).argtypes = [i32, i32, p, p, p, p]
             getattr(L, "orc_qapply_" + t).argtypes = [i32, i32, p, p, p, p, p, p, p]
@@ -272,6 +273,17 @@ def step_pairs(ordering: int, n: int, k: int):
     """The n/2 pivot pairs (i < j) of step k of a sweep, as an int array [n/2, 2]."""
     out = np.empty((n // 2, 2), np.int32)
     lib().orc_step_pairs(int(ordering), int(n), int(k), _ptr(out))
+    return out
+
+
+def dynamic_pairs(G):
+    """The pivot pairs the dynamic ordering takes for the square matrix G (float64, its
+    own weights w_ij = g_ij^2 + g_ji^2), in the order the greedy matching took them, as
+    an int array [n/2, 2] with i < j."""
+    G = np.asfortranarray(G, dtype=np.float64)
+    n = G.shape[0]
+    out = np.empty((n // 2, 2), np.int32)
+    lib().orc_dynamic_pairs_f64(int(n), _ptr(G), _ptr(out))
     return out
 
 

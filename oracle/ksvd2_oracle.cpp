@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -1347,6 +1348,44 @@ static void step_pairs(int ordering, int n, int k, int *pi, int *pj) {
       }
 }
 
+/* Dynamic ordering (ordering 2; Sect. 1 names dynamic orderings as candidates
+   for parallel strategies that are not cyclic; read here as follows): the
+   pivots of a step are chosen from the current iterate by a greedy matching on
+   the weights w_ij = x_ij^2 + x_ji^2 (i < j, x = G 2^-t with t the norm
+   exponent of the sweep, one fma in binary64: fma(x_ij, x_ij, x_ji * x_ji)):
+   the pairs are taken in decreasing order of weight, equal weights by the
+   smaller i and then the smaller j, each one when both of its indices are still
+   free.  On the complete graph of an even order this pairs every index. */
+struct DynEdge {
+  double w;
+  int i, j;
+};
+
+template <class R>
+static void dynamic_pairs(int n, const R *G, double ns, int *pi, int *pj) {
+  std::vector<DynEdge> e;
+  e.reserve((size_t)n * (n - 1) / 2);
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double a = (double)G[i + (int64_t)j * n] * ns, b = (double)G[j + (int64_t)i * n] * ns;
+      e.push_back(DynEdge{std::fma(a, a, b * b), i, j});
+    }
+  std::sort(e.begin(), e.end(), [](const DynEdge &x, const DynEdge &y) {
+    if (x.w != y.w) return x.w > y.w;
+    if (x.i != y.i) return x.i < y.i;
+    return x.j < y.j;
+  });
+  std::vector<char> used(n, 0);
+  int t = 0;
+  for (const DynEdge &x : e) {
+    if (used[x.i] || used[x.j]) continue;
+    used[x.i] = used[x.j] = 1;
+    pi[t] = x.i;
+    pj[t] = x.j;
+    ++t;
+  }
+}
+
 /* one element pair of a rotation: x' = a x + b y as fma(a, x, b*y) */
 template <class R> static R rot_lin(R a, R x, R b, R y) { return std::fma(a, x, b * y); }
 
@@ -1390,7 +1429,10 @@ static int sweep_one(int n, R *G, R *U, R *V, int max_sweeps, double tol_factor,
   int sw = 0;
   for (sw = 0; sw < max_sweeps; ++sw) {
     for (int k = 0; k < n - 1; ++k) {
-      step_pairs(ordering, n, k, pi, pj);
+      if (ordering == 2)
+        dynamic_pairs(n, G, ns, pi, pj);
+      else
+        step_pairs(ordering, n, k, pi, pj);
       for (int q = 0; q < np; ++q) {
         int i = pi[q], j = pj[q];
         R gii = G[i + (int64_t)i * n], gji = G[j + (int64_t)i * n];
@@ -1741,6 +1783,18 @@ void orc_ksvd2c_f64(int64_t n, const double *G, double *U, double *S, double *V,
 void orc_ksvd2c_f32(int64_t n, const float *G, float *U, float *S, float *V, float *f,
                     int32_t *e, int32_t *info, int nthreads) {
   batch_c<float>(n, G, U, S, V, f, e, info, nthreads);
+}
+
+/* the pairs of the dynamic ordering for an n x n matrix (weights of G itself,
+   t = 0): 2 * (n/2) ints, i then j, in the order they were taken */
+void orc_dynamic_pairs_f64(int n, const double *G, int *out) {
+  int np = n / 2;
+  std::vector<int> pi(np), pj(np);
+  dynamic_pairs(n, G, 1.0, pi.data(), pj.data());
+  for (int q = 0; q < np; ++q) {
+    out[2 * q] = pi[q];
+    out[2 * q + 1] = pj[q];
+  }
 }
 
 /* the pivot pairs of step k (for the ordering pins): 2 * (n/2) ints, i then j */

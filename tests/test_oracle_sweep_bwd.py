@@ -12,6 +12,8 @@ numerical derivative) on general, near-degenerate (gauge-invariant polar-factor 
 rank-deficient (first singular triple only) matrices, and the textbook special case
 d sigma_i / dG = u_i v_i^T.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -49,7 +51,7 @@ def test_orderings_differ_in_step_order(orc):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", [2, 4, 6, 10, 16, 32])
-@pytest.mark.parametrize("ordering", [0, 1], ids=["round-robin", "modulus"])
+@pytest.mark.parametrize("ordering", [0, 1, 2], ids=["round-robin", "modulus", "dynamic"])
 def test_sweep_converges_to_svd(orc, dtype, n, ordering):
     rng = np.random.default_rng(100 + n)
     G0 = (rng.standard_normal((n, n)) * np.exp2(rng.integers(-3, 4, (n, n)))).astype(dtype)
@@ -237,3 +239,72 @@ def test_backward_sigma_only_closed_form(orc):
     want = U[:, :, 0, None] * V[:, None, :, 0] * dS[:, 0, None, None] + \
         U[:, :, 1, None] * V[:, None, :, 1] * dS[:, 1, None, None]
     assert np.max(np.abs(got - want)) <= 1e-15 * np.max(np.abs(want))
+
+
+def _ld_matching(W):
+    """Locally dominant matching, written from its definition (independent of the
+    oracle's greedy one): with edges totally ordered by (weight desc, i asc, j asc),
+    every free index points to its best edge among free indices, and the edges whose two
+    ends point to each other are taken, round after round."""
+    n = W.shape[0]
+    mate = [-1] * n
+
+    def key(i, j):
+        a, b = min(i, j), max(i, j)
+        return (W[a, b], -a, -b)
+
+    while any(m < 0 for m in mate):
+        free = [v for v in range(n) if mate[v] < 0]
+        best = {v: max((u for u in free if u != v), key=lambda u: key(v, u)) for v in free}
+        for v in free:
+            u = best[v]
+            if best[u] == v and v < u:
+                mate[v], mate[u] = u, v
+    return sorted((v, mate[v]) for v in range(n) if v < mate[v])
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 10, 16, 30])
+@pytest.mark.parametrize("ties", [False, True])
+def test_dynamic_pairs_greedy_matching(orc, n, ties):
+    """The dynamic ordering's pairs: a perfect matching, taken in decreasing order of
+    weight (equal weights by index), equal to the locally dominant matching computed
+    independently, and (small orders, brute force over every perfect matching) within
+    the greedy factor 1/2 of the heaviest matching."""
+    rng = np.random.default_rng(500 + n + 7 * ties)
+    for rep in range(20):
+        if ties:   # few distinct magnitudes and zeros: many equal weights
+            G = rng.choice([0.0, 1.0, -1.0, 2.0, 0.5], (n, n))
+        else:
+            G = rng.standard_normal((n, n)) * np.exp2(rng.integers(-4, 5, (n, n)))
+        P = orc.dynamic_pairs(G)
+        assert sorted(P.ravel().tolist()) == list(range(n)) and np.all(P[:, 0] < P[:, 1])
+        # the weight as the ordering defines it: one fma, fma(a, a, b*b) = RN(a^2 + RN(b^2))
+        W = np.zeros((n, n))
+        for i in range(n):
+            for j in range(i + 1, n):
+                a, b = Fraction(float(G[i, j])), float(G[j, i]) * float(G[j, i])
+                W[i, j] = float(a * a + Fraction(b))
+        keys = [(-W[i, j], i, j) for i, j in P]
+        assert keys == sorted(keys)
+        assert sorted(map(tuple, P.tolist())) == _ld_matching(W)
+        if n <= 8:
+            def best(vs):
+                if not vs:
+                    return 0.0
+                a = vs[0]
+                return max(W[a, b] + best([x for x in vs if x not in (a, b)]) for b in vs[1:])
+            assert sum(W[i, j] for i, j in P) >= 0.5 * best(list(range(n))) - 1e-12
+
+
+def test_dynamic_ordering_fewer_sweeps(orc):
+    """On random matrices the dynamic ordering converges in no more sweeps than the
+    cyclic ones (it annihilates the heaviest off-diagonal pairs first)."""
+    rng = np.random.default_rng(8)
+    for n in (16, 32):
+        G0 = np.asfortranarray(rng.standard_normal((n, n)) * np.exp2(-np.arange(n) / 8.0))
+        counts = {}
+        for o in (0, 1, 2):
+            *_, st, sw = orc.kog_sweep(G0, max_sweeps=30, tol_factor=1.0, ordering=o)
+            assert st == 0
+            counts[o] = sw
+        assert counts[2] <= min(counts[0], counts[1]), counts
