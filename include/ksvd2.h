@@ -251,6 +251,29 @@ int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_
                     int ordering, void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * kog_sweep_batch_noalloc -- kog_sweep_batch for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same iteration, bit for bit the same results, with the
+ * workspace taken from a static device array of KOG_SWEEP_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that each GPU holds from the library's first call on it until the
+ * process ends.  The call allocates nothing; the caller still owns G, U, V,
+ * sigma and sweeps_out.  Arguments as for kog_sweep_batch without the workspace;
+ * modes 0 and 1 only (mode 2 is KSVD2_EINVAL: instantiating its graph may
+ * allocate).  When the step table of 128 steps does not fit, fewer steps per U/V
+ * update are used (down to 2; the results do not change); a batch whose
+ * workspace exceeds the scratch even then returns KSVD2_EWORKSPACE with a
+ * message naming kog_sweep_batch.  Every call on one GPU shares that GPU's
+ * scratch and leaves its contents behind (the next call re-initialises what it
+ * reads): calls that overlap on one GPU (other streams or host threads) race
+ * and must be serialised by the caller.
+ */
+#define KOG_SWEEP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int kog_sweep_batch_noalloc(int dtype, int64_t nmat, const int32_t *n_host,
+                            const int64_t *off_host, void *G, void *U, void *V, void *sigma,
+                            int32_t *sweeps_out, int32_t max_sweeps, double tol_factor,
+                            int accumulate, int mode, int ordering, void *stream);
+
+/*
  * kog_sweep_sort -- the delivered singular values in the usual order: for each
  * matrix of a kog_sweep_batch result, sigma (packed as kog_sweep_batch writes
  * it, on entry the iterate's diagonal) is put in descending order, equal values

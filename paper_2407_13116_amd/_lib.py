@@ -50,6 +50,9 @@ def lib():
             L.kog_sweep_batch.restype = i32
             L.kog_sweep_batch.argtypes = [i32, i64, p, p, p, p, p, p, p, i32, d, i32, i32, i32, p,
                                           ctypes.c_size_t, p]
+            L.kog_sweep_batch_noalloc.restype = i32
+            L.kog_sweep_batch_noalloc.argtypes = [i32, i64, p, p, p, p, p, p, p, i32, d, i32, i32,
+                                                  i32, p]
             L.kog_sweep_workspace_size.restype = ctypes.c_size_t
             L.kog_sweep_workspace_size.argtypes = [i32, i64, p]
             L.kog_sigma_grad.restype = i32

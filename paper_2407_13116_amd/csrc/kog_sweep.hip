@@ -1916,6 +1916,37 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   return KSVD2_OK;
 }
 
+// Scratch of kog_sweep_batch_noalloc: a file-scope device array in place of the
+// caller's workspace, so that the call allocates no device memory.  Every GPU the
+// library runs on holds its own copy for the life of the process.  In host code
+// the array's name stands for no device address: the address comes from
+// hipGetSymbolAddress, once per device with that device current, and only that
+// address is handed to the copies and kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(KSVD2_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(KSVD2_EINVAL, "device %d: the static scratch serves devices 0..%d", dev,
+                kMaxDevices - 1);
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KSVD2_EHIP, "address of the static scratch on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KSVD2_OK;
+}
+
 template <class R>
 static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *off_host,
                            const R *U, const R *V, const R *ds, R *dG, void *ws, size_t ws_bytes,
@@ -2043,6 +2074,38 @@ int kog_sweep_batch(int dtype, int64_t nmat, const int32_t *n_host, const int64_
                              (float *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate, mode,
                              ordering, workspace, ws_bytes, st, false);
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+int kog_sweep_batch_noalloc(int dtype, int64_t nmat, const int32_t *n_host,
+                            const int64_t *off_host, void *G, void *U, void *V, void *sigma,
+                            int32_t *sweeps_out, int32_t max_sweeps, double tol_factor,
+                            int accumulate, int mode, int ordering, void *stream) {
+  if (mode == 2)
+    return fail(KSVD2_EINVAL, "kog_sweep_batch_noalloc takes modes 0 and 1 (a graph of "
+                              "mode 2 would be instantiated, which may allocate)");
+  if (dtype != 0 && dtype != 1)
+    return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+  if (nmat == 0) return KSVD2_OK;
+  void *ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // the step table shrinks (fewer steps per U/V update, the same results) until the
+  // call's workspace fits the scratch; a batch that does not fit even then is refused
+  if (dtype == 1)
+    rc = sweep_impl<double>(1, nmat, n_host, off_host, (double *)G, (double *)U, (double *)V,
+                            (double *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate,
+                            mode, ordering, ws, kScratchBytes, st, true);
+  else
+    rc = sweep_impl<float>(0, nmat, n_host, off_host, (float *)G, (float *)U, (float *)V,
+                           (float *)sigma, sweeps_out, max_sweeps, tol_factor, accumulate, mode,
+                           ordering, ws, kScratchBytes, st, true);
+  if (rc == KSVD2_EWORKSPACE)
+    return fail(KSVD2_EWORKSPACE,
+                "kog_sweep_batch_noalloc: the batch needs more than the %zu bytes of static "
+                "scratch (%s); use kog_sweep_batch with a workspace",
+                kScratchBytes, last_error_ref().c_str());
+  return rc;
 }
 
 int kog_sweep_set_tuning(int dtype, int bucket, int knob, int value) {
