@@ -153,25 +153,49 @@ int ksvd2_svd2x2(int dtype, int64_t batch, const void *G, void *U, void *S, void
                  int32_t *info, void *stream);
 
 /*
- * ksvd2_batch_backward -- the adjoint of G = U diag(S) V^T for square 2x2
- * matrices with full U and V (the standard SVD adjoint,
- *   dG = U [diag(dS) + (F o (J - J^T)) S + S (F o (K - K^T))] V^T,
+ * ksvd2_batch_backward -- the adjoint of G = U diag(sigma) V^T on the planes of
+ * ksvd2_batch_f64 / ksvd2_batch_f32 (the standard SVD adjoint,
+ *   dG = U [diag(dsigma) + (F o (J - J^T)) Sigma + Sigma (F o (K - K^T))] V^T,
  *   J = U^T dU, K = V^T dV, F_ij = 1/(s_j^2 - s_i^2) (i != j),
  * written out for order two with a = J12 - J21, b = K12 - K21, p = (a+b)/2,
  * q = (a-b)/2:  M12 = -p/(s1-s2) + q/(s1+s2), M21 = -p/(s1-s2) - q/(s1+s2),
- * dG = U [[dS1, M12], [M21, dS2]] V^T).  The paper defines the forward map only;
- * the adjoint is textbook calculus on it.
- * Layout: U, V, dU, dV, dG are [batch,2,2] row-major; S, dS are [batch,2].
- * dS, dU, dV are nullable (a null pointer means a zero upstream gradient).
+ * dG = U [[ds1, M12], [M21, ds2]] V^T).  The paper defines the forward map
+ * (Sect. 1, G = U Sigma V^T; Sect. 3.3.2 for the delivered factors); the adjoint
+ * is textbook calculus on it.
+ * Inputs (planes of `batch` elements, as the forward entry points write them):
+ *   cu, su, cv, sv, info  U = [cu -d su; su d cu], d = -1 if info bit 8 else
+ *                         +1; V likewise with info bit 9 (the other info bits
+ *                         are ignored)
+ *   s1, s2                the plain singular values (s1_plain, s2_plain)
+ *   ds1, ds2              upstream gradient of sigma (each nullable: 0)
+ *   dU, dV                upstream gradients of U and V (nullable: 0), each
+ *                         four consecutive planes [4][batch] holding the
+ *                         entries (1,1), (2,1), (1,2), (2,2) of every matrix
+ * Outputs: dg11, dg21, dg12, dg22, the four planes of dG (required; they must
+ * not alias the inputs).
  * Degenerate singular values: with tau > 0, 1/(s1-s2) is replaced by
  * (s1-s2)/((s1-s2)^2 + (tau s1)^2) (Lorentzian broadening); with tau = 0 the
  * exact formula is used and the p-term is dropped only when s1 - s2 == 0.  The
  * q-term needs 1/(s1+s2) only, so s2 = 0 < s1 is finite; s1 = s2 = 0 gives
- * M = diag(dS).  tau < 0 is KSVD2_EINVAL.  dtype: 0 = float, 1 = double.
+ * M = diag(ds).  tau < 0 is KSVD2_EINVAL.  dtype: 0 = float, 1 = double.
+ * The result equals, bit for bit, ksvd2_svd2x2_backward on the full matrices.
  */
-int ksvd2_batch_backward(int dtype, int64_t batch, const void *U, const void *S, const void *V,
-                         const void *dS, const void *dU, const void *dV, void *dG, double tau,
-                         void *stream);
+int ksvd2_batch_backward(int dtype, int64_t batch, const void *cu, const void *su,
+                         const void *cv, const void *sv, const int32_t *info, const void *s1,
+                         const void *s2, const void *ds1, const void *ds2, const void *dU,
+                         const void *dV, void *dg11, void *dg21, void *dg12, void *dg22,
+                         double tau, void *stream);
+
+/*
+ * ksvd2_svd2x2_backward -- the same adjoint in the layout of ksvd2_svd2x2 (the
+ * layout of an autograd graph): U, V, dU, dV, dG are [batch,2,2] row-major,
+ * S and dS are [batch,2].  dS, dU, dV are nullable (a null pointer means a
+ * zero upstream gradient).  Degenerate handling, tau and errors as for
+ * ksvd2_batch_backward.  dtype: 0 = float, 1 = double.
+ */
+int ksvd2_svd2x2_backward(int dtype, int64_t batch, const void *U, const void *S, const void *V,
+                          const void *dS, const void *dU, const void *dV, void *dG, double tau,
+                          void *stream);
 
 /*
  * ksvd2_hypot_batch -- the correctly rounded hypot(x, y) = fl(sqrt(x^2 + y^2))
@@ -230,12 +254,18 @@ int ksvd2_hypot_fast_batch(int dtype, int64_t n, const void *x, const void *y, v
  *           iteration): with m = n-1, step k pairs the indices below m whose sum
  *           is k mod m, and the index c with 2c = k mod m with m.
  *           Both visit every pair once per sweep, in different step orders.
+ *           2 = dynamic (Sect. 1 names dynamic orderings for non-cyclic parallel
+ *           strategies): every step takes a greedy matching of the current G on
+ *           the weights w_ij = fma(x_ij, x_ij, x_ji * x_ji) (binary64, x = G
+ *           2^-t as for the stopping test), pairs by decreasing weight, equal
+ *           weights by the smaller index, then the larger; a sweep is n-1 such
+ *           steps.  One step per pass of G (the two-step passes need ordering 1).
  * All modes perform the same arithmetic in the same order: bitwise identical.
  * workspace: device memory of at least kog_sweep_workspace_size() bytes (an
  * amount that covers every mode, ordering and tuning; a call checks only what
  * it uses), 256-byte aligned, owned by the caller, used only during the call's
  * work: the batch descriptor, the counters, the step table (the parameters of
- * up to 128 steps of every pivot), mode 0's pair table, and a second buffer,
+ * up to 128 steps of every pivot), the pair table (mode 0, ordering 2), and a second buffer,
  * of G's size at most, through which the persistent modes update G two steps
  * at a time under the modified modulus ordering.
  * Overflow: G is first multiplied by 2^s_G with s_G = e_nu - 2 - e_G - ceil(lg n)

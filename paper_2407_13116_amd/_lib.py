@@ -38,8 +38,10 @@ def lib():
             fn.argtypes = [i64] + [p] * 15 + [p]
         L.ksvd2_svd2x2.restype = i32
         L.ksvd2_svd2x2.argtypes = [i32, i64, p, p, p, p, p, p]
+        L.ksvd2_svd2x2_backward.restype = i32
+        L.ksvd2_svd2x2_backward.argtypes = [i32, i64, p, p, p, p, p, p, p, d, p]
         L.ksvd2_batch_backward.restype = i32
-        L.ksvd2_batch_backward.argtypes = [i32, i64, p, p, p, p, p, p, p, d, p]
+        L.ksvd2_batch_backward.argtypes = [i32, i64] + [p] * 15 + [d, p]
         L.ksvd2c_batch.restype = i32
         L.ksvd2c_batch.argtypes = [i32, i64, p, p, p, p, p, p, p, p]
         for name in ("ksvd2_hypot_batch", "ksvd2_hypot_fast_batch"):

@@ -98,10 +98,43 @@ def svd2x2_backward(U, S, V, dS=None, dU=None, dV=None, tau: float = 0.0):
     dt = _check_gpu(U, S, V, dS, dU, dV)
     B = U.shape[0]
     dG = torch.empty_like(U)
-    rc = _lib.lib().ksvd2_batch_backward(_DT[dt], B, _ptr(U), _ptr(S), _ptr(V), _ptr(dS),
-                                         _ptr(dU), _ptr(dV), _ptr(dG), float(tau), _stream())
-    _lib.check(rc, "ksvd2_batch_backward")
+    rc = _lib.lib().ksvd2_svd2x2_backward(_DT[dt], B, _ptr(U), _ptr(S), _ptr(V), _ptr(dS),
+                                          _ptr(dU), _ptr(dV), _ptr(dG), float(tau), _stream())
+    _lib.check(rc, "ksvd2_svd2x2_backward")
     return dG
+
+
+def ksvd2_backward_soa(fwd: dict, ds1=None, ds2=None, dU=None, dV=None, tau: float = 0.0,
+                       out=None):
+    """The adjoint on the planes of ``ksvd2_batch(..., plain=True)``: ``fwd`` holds cu su
+    cv sv info s1 s2; ds1, ds2 are planes; dU, dV are [4, B] tensors holding the entries
+    (1,1), (2,1), (1,2), (2,2) of every matrix (each argument may be None: zero).
+    Returns dG as a [4, B] tensor of the planes g11, g21, g12, g22 (or fills ``out``)."""
+    for k in ("cu", "su", "cv", "sv", "info", "s1", "s2"):
+        if fwd.get(k) is None:
+            raise _lib.KSVD2Error(f"ksvd2_backward_soa: forward plane {k} missing "
+                                  "(run ksvd2_batch with plain=True)")
+    dt = _check_gpu(fwd["cu"], fwd["su"], fwd["cv"], fwd["sv"], fwd["s1"], fwd["s2"], ds1, ds2,
+                    dU, dV, out)
+    inf = fwd["info"]
+    if not (inf.is_cuda and inf.is_contiguous() and inf.dtype == torch.int32):
+        raise _lib.KSVD2Error("ksvd2_backward_soa: info must be a contiguous int32 GPU tensor")
+    B = fwd["cu"].numel()
+    for t in (dU, dV, out):
+        if t is not None and tuple(t.shape) != (4, B):
+            raise _lib.KSVD2Error("dU, dV and out must have shape [4, B]")
+    for t in (ds1, ds2):
+        if t is not None and t.numel() != B:
+            raise _lib.KSVD2Error("ds1 and ds2 must have B elements")
+    if out is None:
+        out = torch.empty((4, B), dtype=dt, device=fwd["cu"].device)
+    rc = _lib.lib().ksvd2_batch_backward(
+        _DT[dt], B, _ptr(fwd["cu"]), _ptr(fwd["su"]), _ptr(fwd["cv"]), _ptr(fwd["sv"]),
+        _ptr(fwd["info"]), _ptr(fwd["s1"]), _ptr(fwd["s2"]), _ptr(ds1), _ptr(ds2), _ptr(dU),
+        _ptr(dV), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(out[3]), float(tau),
+        _stream())
+    _lib.check(rc, "ksvd2_batch_backward")
+    return out
 
 
 def hypot(x, y, fast: bool = False):

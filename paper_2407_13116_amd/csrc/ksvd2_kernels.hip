@@ -31,6 +31,7 @@ template <class T> __device__ inline const T &at(const T *base, uint32_t bo) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + bo);
 }
 constexpr int64_t kMaxLaunch = int64_t(1) << 28;  // elements per launch: offsets < 2^31
+constexpr int64_t kMaxLaunchFull = int64_t(1) << 26;  // [B,2,2] matrices per launch: 32 B each
 
 // 6 waves per SIMD (at most 80 registers): the straight-line SVD code issues
 // back-to-back dependent FP64 instructions, and one more resident wave hides
@@ -131,22 +132,24 @@ static bool vec_aligned(size_t w, std::initializer_list<const void *> ps) {
 }
 
 // Autograd layout: G, U, V are [B,2,2] row-major, S is [B,2] (plain sigma).
+// Addressed like k_fwd_soa: scalar bases and one 32-bit byte offset per lane
+// (launches are split so that the offsets of G, U, V stay below 2^31).
 template <class R, bool kVec>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_full(int64_t n, const R *__restrict__ G,
-                                                     R *__restrict__ U, R *__restrict__ S,
-                                                     R *__restrict__ V,
-                                                     int32_t *__restrict__ info) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_full(
+    uint32_t n, const R *__restrict__ G, R *__restrict__ U, R *__restrict__ S,
+    R *__restrict__ V, int32_t *__restrict__ info) {
+  const uint32_t i = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
   if (i >= n) return;
+  const uint32_t b4 = i * (uint32_t)(4 * sizeof(R)), b2 = i * (uint32_t)(2 * sizeof(R));
   R g11, g12, g21, g22;
-  ld4<R, kVec>(G + 4 * i, g11, g12, g21, g22);
+  ld4<R, kVec>(&at(G, b4), g11, g12, g21, g22);
   Svd2<R> r = svd2<R>(g11, g21, g12, g22);
   R du = (r.info & I_DETU) ? (R)-1 : (R)1;
   R dv = (r.info & I_DETV) ? (R)-1 : (R)1;
-  st4<R, kVec>(U + 4 * i, r.cu, -du * r.su, r.su, du * r.cu);
-  st4<R, kVec>(V + 4 * i, r.cv, -dv * r.sv, r.sv, dv * r.cv);
-  st2<R, kVec>(S + 2 * i, scale2(r.f1, r.e1), scale2(r.f2, r.e2));
-  if (info) info[i] = (int32_t)r.info;
+  st4<R, kVec>(&at(U, b4), r.cu, -du * r.su, r.su, du * r.cu);
+  st4<R, kVec>(&at(V, b4), r.cv, -dv * r.sv, r.sv, dv * r.cv);
+  st2<R, kVec>(&at(S, b2), scale2(r.f1, r.e1), scale2(r.f2, r.e2));
+  if (info) at(info, i * 4u) = (int32_t)r.info;
 }
 
 // Adjoint of G = U diag(S) V^T (2x2, square, full U and V):
@@ -209,6 +212,66 @@ __global__ __launch_bounds__(kBlock) void k_bwd(int64_t n, const R *__restrict__
   st4<R, kVec>(dG + 4 * i, g11, g12, g21, g22);
 }
 
+// The same adjoint on the structure-of-arrays planes of the forward entry
+// points: U = [cu -dU su; su dU cu] and V likewise, with the determinant signs
+// dU, dV from info bits 8 and 9, so a matrix reads 4 + 4 + 1 words of U, V and
+// info instead of 8 full entries.  U and V are expanded into their four entries
+// (sign changes only) and then go through exactly the operations of k_bwd in
+// the same order: the result is bit for bit that of k_bwd on the expanded
+// matrices.  Upstream gradients: ds1, ds2 (nullable: 0), dU, dV (nullable: 0)
+// as plane pointers u11, u21, u12, u22; dG as four planes g11, g21, g12, g22.
+template <class R> struct BwdSoaArgs {
+  const R *cu, *su, *cv, *sv, *s1, *s2, *ds1, *ds2;
+  const int32_t *info;
+  const R *du[4], *dv[4];
+  R *dg[4];
+};
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_bwd_soa(uint32_t n, BwdSoaArgs<R> A, R tau) {
+  const uint32_t i = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t bw = i * (uint32_t)sizeof(R);
+  const uint32_t inf = (uint32_t)at(A.info, i * 4u);
+  const R c_u = at(A.cu, bw), s_u = at(A.su, bw), c_v = at(A.cv, bw), s_v = at(A.sv, bw);
+  const bool nu = (inf & I_DETU) != 0, nv = (inf & I_DETV) != 0;
+  // U = [u11 u12; u21 u22] with u12 = -dU su, u22 = dU cu (likewise V)
+  const R u11 = c_u, u21 = s_u, u12 = nu ? s_u : -s_u, u22 = nu ? -c_u : c_u;
+  const R v11 = c_v, v21 = s_v, v12 = nv ? s_v : -s_v, v22 = nv ? -c_v : c_v;
+  const R s1 = at(A.s1, bw), s2 = at(A.s2, bw);
+  R a = 0, b = 0;
+  if (A.du[0]) {
+    const R w11 = at(A.du[0], bw), w21 = at(A.du[1], bw), w12 = at(A.du[2], bw),
+            w22 = at(A.du[3], bw);
+    a = fma(u11, w12, u21 * w22) - fma(u12, w11, u22 * w21);
+  }
+  if (A.dv[0]) {
+    const R w11 = at(A.dv[0], bw), w21 = at(A.dv[1], bw), w12 = at(A.dv[2], bw),
+            w22 = at(A.dv[3], bw);
+    b = fma(v11, w12, v21 * w22) - fma(v12, w11, v22 * w21);
+  }
+  R p = (R)0.5 * (a + b), q = (R)0.5 * (a - b);
+  R dm = s1 - s2, sm = s1 + s2;
+  R idm;
+  if (tau > (R)0) {
+    R eta = tau * s1;
+    R den = fma(dm, dm, eta * eta);
+    idm = (den > (R)0) ? dm / den : (R)0;
+  } else {
+    idm = (dm != (R)0) ? (R)1 / dm : (R)0;
+  }
+  R ism = (sm != (R)0) ? (R)1 / sm : (R)0;
+  const R m11 = A.ds1 ? at(A.ds1, bw) : (R)0, m22 = A.ds2 ? at(A.ds2, bw) : (R)0;
+  R pd = p * idm, qs = q * ism;
+  R m12 = qs - pd, m21 = -pd - qs;
+  R t11 = fma(u11, m11, u12 * m21), t12 = fma(u11, m12, u12 * m22);
+  R t21 = fma(u21, m11, u22 * m21), t22 = fma(u21, m12, u22 * m22);
+  at(A.dg[0], bw) = fma(t11, v11, t12 * v12);
+  at(A.dg[1], bw) = fma(t21, v11, t22 * v12);
+  at(A.dg[2], bw) = fma(t11, v21, t12 * v22);
+  at(A.dg[3], bw) = fma(t21, v21, t22 * v22);
+}
+
 template <class R, bool CR>
 __global__ __launch_bounds__(kBlock) void k_hypot(int64_t n, const R *__restrict__ x,
                                                   const R *__restrict__ y, R *__restrict__ out) {
@@ -245,12 +308,17 @@ static int fwd_full(int64_t n, const R *G, R *U, R *S, R *V, int32_t *info, void
   const size_t w = sizeof(R);
   KSVD2_REQ(G, w); KSVD2_REQ(U, w); KSVD2_REQ(S, w); KSVD2_REQ(V, w);
   KSVD2_OPT(info, 4);
-  if (vec_aligned(w, {G, U, S, V}))
-    hipLaunchKernelGGL((k_fwd_full<R, true>), dim3(grid_for(n)), dim3(kBlock), 0,
-                       (hipStream_t)stream, n, G, U, S, V, info);
-  else
-    hipLaunchKernelGGL((k_fwd_full<R, false>), dim3(grid_for(n)), dim3(kBlock), 0,
-                       (hipStream_t)stream, n, G, U, S, V, info);
+  const bool vec = vec_aligned(w, {G, U, S, V});
+  for (int64_t o = 0; o < n; o += kMaxLaunchFull) {
+    const uint32_t c = (uint32_t)(n - o < kMaxLaunchFull ? n - o : kMaxLaunchFull);
+    int32_t *io = info ? info + o : nullptr;
+    if (vec)
+      hipLaunchKernelGGL((k_fwd_full<R, true>), dim3(grid_for(c)), dim3(kBlock), 0,
+                         (hipStream_t)stream, c, G + 4 * o, U + 4 * o, S + 2 * o, V + 4 * o, io);
+    else
+      hipLaunchKernelGGL((k_fwd_full<R, false>), dim3(grid_for(c)), dim3(kBlock), 0,
+                         (hipStream_t)stream, c, G + 4 * o, U + 4 * o, S + 2 * o, V + 4 * o, io);
+  }
   return launch_status("ksvd2 forward (full layout) launch");
 }
 
@@ -272,6 +340,40 @@ static int bwd(int64_t n, const void *U, const void *S, const void *V, const voi
                        (hipStream_t)stream, n, (const R *)U, (const R *)S, (const R *)V,
                        (const R *)dS, (const R *)dU, (const R *)dV, (R *)dG, (R)tau);
   return launch_status("ksvd2 backward launch");
+}
+
+template <class R>
+static int bwd_soa(int64_t n, const void *cu, const void *su, const void *cv, const void *sv,
+                   const int32_t *info, const void *s1, const void *s2, const void *ds1,
+                   const void *ds2, const void *dU, const void *dV, void *dg11, void *dg21,
+                   void *dg12, void *dg22, double tau, void *stream) {
+  if (n < 0) return fail(KSVD2_EINVAL, "batch < 0");
+  if (!(tau >= 0.0)) return fail(KSVD2_EINVAL, "tau must be >= 0");
+  if (n == 0) return KSVD2_OK;
+  const size_t w = sizeof(R);
+  KSVD2_REQ(cu, w); KSVD2_REQ(su, w); KSVD2_REQ(cv, w); KSVD2_REQ(sv, w); KSVD2_REQ(info, 4);
+  KSVD2_REQ(s1, w); KSVD2_REQ(s2, w);
+  KSVD2_OPT(ds1, w); KSVD2_OPT(ds2, w); KSVD2_OPT(dU, w); KSVD2_OPT(dV, w);
+  KSVD2_REQ(dg11, w); KSVD2_REQ(dg21, w); KSVD2_REQ(dg12, w); KSVD2_REQ(dg22, w);
+  for (int64_t o = 0; o < n; o += kMaxLaunch) {
+    const uint32_t c = (uint32_t)(n - o < kMaxLaunch ? n - o : kMaxLaunch);
+    BwdSoaArgs<R> A;
+    A.cu = (const R *)cu + o; A.su = (const R *)su + o;
+    A.cv = (const R *)cv + o; A.sv = (const R *)sv + o;
+    A.s1 = (const R *)s1 + o; A.s2 = (const R *)s2 + o;
+    A.ds1 = ds1 ? (const R *)ds1 + o : nullptr;
+    A.ds2 = ds2 ? (const R *)ds2 + o : nullptr;
+    A.info = info + o;
+    for (int k = 0; k < 4; ++k) {
+      A.du[k] = dU ? (const R *)dU + (int64_t)k * n + o : nullptr;
+      A.dv[k] = dV ? (const R *)dV + (int64_t)k * n + o : nullptr;
+    }
+    A.dg[0] = (R *)dg11 + o; A.dg[1] = (R *)dg21 + o;
+    A.dg[2] = (R *)dg12 + o; A.dg[3] = (R *)dg22 + o;
+    hipLaunchKernelGGL(k_bwd_soa<R>, dim3(grid_for(c)), dim3(kBlock), 0, (hipStream_t)stream, c,
+                       A, (R)tau);
+  }
+  return launch_status("ksvd2 backward (planes) launch");
 }
 
 template <bool CR>
@@ -299,7 +401,7 @@ using namespace ksvd2;
 
 extern "C" {
 
-int ksvd2_version(void) { return 3; }
+int ksvd2_version(void) { return 4; }
 
 const char *ksvd2_last_error(void) { return last_error_ref().c_str(); }
 
@@ -330,11 +432,25 @@ int ksvd2_svd2x2(int dtype, int64_t batch, const void *G, void *U, void *S, void
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
 }
 
-int ksvd2_batch_backward(int dtype, int64_t batch, const void *U, const void *S, const void *V,
-                         const void *dS, const void *dU, const void *dV, void *dG, double tau,
-                         void *stream) {
+int ksvd2_svd2x2_backward(int dtype, int64_t batch, const void *U, const void *S, const void *V,
+                          const void *dS, const void *dU, const void *dV, void *dG, double tau,
+                          void *stream) {
   if (dtype == 1) return bwd<double>(batch, U, S, V, dS, dU, dV, dG, tau, stream);
   if (dtype == 0) return bwd<float>(batch, U, S, V, dS, dU, dV, dG, tau, stream);
+  return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
+}
+
+int ksvd2_batch_backward(int dtype, int64_t batch, const void *cu, const void *su,
+                         const void *cv, const void *sv, const int32_t *info, const void *s1,
+                         const void *s2, const void *ds1, const void *ds2, const void *dU,
+                         const void *dV, void *dg11, void *dg21, void *dg12, void *dg22,
+                         double tau, void *stream) {
+  if (dtype == 1)
+    return bwd_soa<double>(batch, cu, su, cv, sv, info, s1, s2, ds1, ds2, dU, dV, dg11, dg21,
+                           dg12, dg22, tau, stream);
+  if (dtype == 0)
+    return bwd_soa<float>(batch, cu, su, cv, sv, info, s1, s2, ds1, ds2, dU, dV, dg11, dg21,
+                          dg12, dg22, tau, stream);
   return fail(KSVD2_EDTYPE, "dtype must be 0 (f32) or 1 (f64), got %d", dtype);
 }
 

@@ -55,8 +55,17 @@ def test_invalid_arguments_rejected(L):
     assert rc == -1 and b"aligned" in L.ksvd2_last_error()
     assert L.ksvd2_batch_f64(0, *([None] * 15), None) == 0          # empty batch: no-op
     assert L.ksvd2_svd2x2(7, 4, p, p, p, p, None, None) == -2
-    assert L.ksvd2_batch_backward(1, 4, p, p, p, None, None, None, p, -1.0, None) == -1
-    assert L.ksvd2_batch_backward(5, 4, p, p, p, None, None, None, p, 0.0, None) == -2
+    assert L.ksvd2_svd2x2_backward(1, 4, p, p, p, None, None, None, p, -1.0, None) == -1
+    assert L.ksvd2_svd2x2_backward(5, 4, p, p, p, None, None, None, p, 0.0, None) == -2
+    planes = [p] * 7 + [None] * 4 + [p] * 4          # cu..s2, ds1 ds2 dU dV, dg planes
+    assert L.ksvd2_batch_backward(1, 4, *planes, -1.0, None) == -1
+    assert b"tau" in L.ksvd2_last_error()
+    assert L.ksvd2_batch_backward(5, 4, *planes, 0.0, None) == -2
+    bad = list(planes)
+    bad[4] = None                                   # info is required (determinant signs)
+    assert L.ksvd2_batch_backward(1, 4, *bad, 0.0, None) == -1
+    assert b"info" in L.ksvd2_last_error()
+    assert L.ksvd2_batch_backward(1, 0, *([None] * 15), 0.0, None) == 0
     assert L.ksvd2_hypot_batch(1, -3, p, p, p, None) == -1
 
 
@@ -88,7 +97,7 @@ def test_sweep_arguments_rejected(L):
     assert need >= 8 * (4 * 4 + 6 * 6)                                # holds a second G
     assert L.kog_sweep_batch(*args(n2, 2, need)) == -1                # graph mode, null stream
     assert L.kog_sweep_batch(*args(n2, 7, need)) == -1                # bad mode
-    assert L.kog_sweep_batch(*args(n2, 1, need, 2)) == -1             # bad ordering
+    assert L.kog_sweep_batch(*args(n2, 1, need, 3)) == -1             # bad ordering
     assert b"ordering" in L.ksvd2_last_error()
     assert L.kog_sweep_tune(1, 9, 256) == -1 and L.kog_sweep_tune(1, 0, 300) == -1
 

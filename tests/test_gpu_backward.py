@@ -253,3 +253,98 @@ def test_full_batch_fwd_bwd(orc, dtype):
     want = orc.svd2_backward(Un[idx], Sn[idx], Vn[idx], dS[idx], dU[idx], dV[idx])
     err = np.abs(dGn[idx].astype(np.float64) - want).reshape(len(idx), -1).max(1)
     assert np.all(err <= _bound(Un[idx], Sn[idx], Vn[idx], dS[idx], dU[idx], dV[idx], dtype))
+
+
+def _planes4(M):
+    """[B,2,2] -> [4,B] planes of the entries (1,1), (2,1), (1,2), (2,2)."""
+    return np.ascontiguousarray(np.stack([M[:, 0, 0], M[:, 1, 0], M[:, 0, 1], M[:, 1, 1]]))
+
+
+def _full_from_planes(c, s, info, bit):
+    """U = [c -d s; s d c] with d = -1 where the info bit is set."""
+    d = np.where(info & bit, -1.0, 1.0).astype(c.dtype)
+    return np.stack([np.stack([c, -d * s], -1), np.stack([s, d * c], -1)], 1)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_backward_planes_vs_oracle_and_full_layout(orc, dtype):
+    """ksvd2_batch_backward on the SoA forward's own planes (ragged batch): within the
+    derived bound of the oracle adjoint, and bit for bit the [B,2,2] adjoint on the
+    expanded U, V; null upstream gradients equal zero ones, bit for bit."""
+    import torch
+
+    from paper_2407_13116_amd import api
+
+    B = (1 << 16) + 37
+    G, dS, dU, dV, lab = inputs.diff_batch(dtype, B=B)
+    fwd = api.ksvd2_batch(*to_dev(*inputs.soa_from_mats(G)), plain=True)
+    h = {k: v.cpu().numpy() for k, v in fwd.items()}
+    U = _full_from_planes(h["cu"], h["su"], h["info"], 1 << 8)
+    V = _full_from_planes(h["cv"], h["sv"], h["info"], 1 << 9)
+    S = np.stack([h["s1"], h["s2"]], 1)
+    o = orc.ksvd2(*inputs.soa_from_mats(G))
+    Uo, Vo = orc.full_uv(o)
+    assert np.array_equal(U.astype(np.float64), Uo) and np.array_equal(V.astype(np.float64), Vo)
+    ds1, ds2, pU, pV = to_dev(dS[:, 0], dS[:, 1], _planes4(dU), _planes4(dV))
+    dGp = api.ksvd2_backward_soa(fwd, ds1, ds2, pU, pV)
+    torch.cuda.synchronize()
+    g = dGp.cpu().numpy()
+    dG = np.stack([np.stack([g[0], g[2]], -1), np.stack([g[1], g[3]], -1)], 1)
+    want = orc.svd2_backward(U, S, V, dS, dU, dV)
+    err = np.abs(dG.astype(np.float64) - want).reshape(B, -1).max(1)
+    bound = _bound(U, S, V, dS, dU, dV, dtype)
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, (bad[:5], err[bad[:5]], bound[bad[:5]], lab[bad[:5]])
+    # the [B,2,2] kernel on the expanded matrices: the same bits
+    t = to_dev(U, S, V, dS, dU, dV)
+    dGf = api.svd2x2_backward(*t).cpu().numpy()
+    assert np.array_equal(dGf.view(np.uint8), np.ascontiguousarray(dG).view(np.uint8))
+    # null upstream gradients
+    for args, full in (((None, None, pU, pV), (t[0], t[1], t[2], None, t[4], t[5])),
+                       ((ds1, ds2, None, None), (t[0], t[1], t[2], t[3], None, None)),
+                       ((None, None, None, pV), (t[0], t[1], t[2], None, None, t[5]))):
+        g = api.ksvd2_backward_soa(fwd, *args).cpu().numpy()
+        a = np.stack([np.stack([g[0], g[2]], -1), np.stack([g[1], g[3]], -1)], 1)
+        b = api.svd2x2_backward(*full).cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), np.ascontiguousarray(b).view(np.uint8))
+
+
+def test_backward_planes_past_one_launch(orc):
+    """2^28 + 4,099 FP32 matrices (more than one launch of 2^28): outputs around the
+    launch boundary and at both ends within the bound of the oracle adjoint."""
+    import torch
+
+    from paper_2407_13116_amd import api
+
+    B = (1 << 28) + 4099
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    ang = torch.rand(2, B, device="cuda", generator=gen, dtype=torch.float32) * 6.2831855
+    info = (torch.randint(0, 4, (B,), device="cuda", generator=gen, dtype=torch.int32) << 8)
+    sv = torch.rand(2, B, device="cuda", generator=gen, dtype=torch.float32) + 0.5
+    fwd = {"cu": torch.cos(ang[0]), "su": torch.sin(ang[0]), "cv": torch.cos(ang[1]),
+           "sv": torch.sin(ang[1]), "info": info,
+           "s1": torch.maximum(sv[0], sv[1]).contiguous(), "s2": torch.minimum(sv[0], sv[1]).contiguous()}
+    del ang, sv
+    ds = torch.randn(2, B, device="cuda", generator=gen, dtype=torch.float32)
+    pU = torch.randn(4, B, device="cuda", generator=gen, dtype=torch.float32)
+    pV = torch.randn(4, B, device="cuda", generator=gen, dtype=torch.float32)
+    out = api.ksvd2_backward_soa(fwd, ds[0], ds[1], pU, pV)
+    torch.cuda.synchronize()
+    L = 1 << 28
+    idx = np.concatenate([np.arange(0, 64), np.arange(L - 300, L + 300), np.arange(B - 64, B)])
+    it = torch.from_numpy(idx).cuda()
+    h = {k: v[it].cpu().numpy() for k, v in fwd.items()}
+    U = _full_from_planes(h["cu"], h["su"], h["info"], 1 << 8)
+    V = _full_from_planes(h["cv"], h["sv"], h["info"], 1 << 9)
+    S = np.stack([h["s1"], h["s2"]], 1)
+    dSn = ds[:, it].cpu().numpy().T.copy()
+    p, q = pU[:, it].cpu().numpy(), pV[:, it].cpu().numpy()
+    dUn = np.stack([np.stack([p[0], p[2]], -1), np.stack([p[1], p[3]], -1)], 1)
+    dVn = np.stack([np.stack([q[0], q[2]], -1), np.stack([q[1], q[3]], -1)], 1)
+    g = out[:, it].cpu().numpy()
+    dG = np.stack([np.stack([g[0], g[2]], -1), np.stack([g[1], g[3]], -1)], 1)
+    want = orc.svd2_backward(U, S, V, dSn, dUn, dVn)
+    err = np.abs(dG.astype(np.float64) - want).reshape(len(idx), -1).max(1)
+    assert np.all(err <= _bound(U, S, V, dSn, dUn, dVn, np.float32)), err.max()
+    del fwd, ds, pU, pV, out
+    torch.cuda.empty_cache()
