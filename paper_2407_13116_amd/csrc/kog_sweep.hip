@@ -72,44 +72,145 @@ struct SweepDesc {
   const int64_t *aoff;   // offset of matrix m in galt
   void *galt;            // a second buffer of G's size (the two-step G updates)
   int chunk;             // steps per U/V update, a power of two in [2, kChunk]
+  int16_t *pairs;        // pair table of the chunk's steps (mode 0, dynamic ordering)
 };
 
-// Slot s of step k in the round-robin (circle) ordering: slot 0 is fixed,
-// slots 1..n-1 rotate by one position per step; slots s and n-1-s meet.
-// For 0 <= k <= n-2 and 1 <= s <= n-1, s - 1 + k < 2(n-1), so one conditional
-// subtraction is the remainder.
-__device__ inline int rr_player(int n, int k, int s) {
-  if (s == 0) return 0;
-  int x = s - 1 + k;
-  return 1 + (x >= n - 1 ? x - (n - 1) : x);
-}
-
-// Slot q of step k in the modified modulus ordering (the parallel strategy
-// Sect. 4 names for the order-n iteration): with m = n - 1 odd, step k pairs the
+// Pivot orderings.  Modified modulus (ord = 1; the parallel strategy Sect. 4
+// names for the order-n iteration): with m = n - 1 odd, step k pairs the
 // indices below m whose sum is k modulo m, and the one index c with 2c = k
 // (mod m), which the modulus strategy for odd orders leaves idle, with m.  Slot
-// 0 holds (c, m), slot q >= 1 the pair c -+ q (mod m).  Every pair meets once in
-// the m steps of a sweep.
-__device__ inline void mm_pair(int n, int k, int q, int &i, int &j) {
-  const int m = n - 1;
-  const int c = (k & 1) ? (k + m) >> 1 : k >> 1;  // 2c = k (mod m)
-  int a = c - q, b = c + q;
-  a = a < 0 ? a + m : a;
-  b = b >= m ? b - m : b;
-  b = q == 0 ? m : b;
-  i = a < b ? a : b;
-  j = a < b ? b : a;
+// 0 holds (c, m), slot q >= 1 the pair A_q = c + q, B_q = c - q (mod m).  Every
+// pair meets once in the m steps of a sweep.
+//
+// Round-robin (ord = 0; the circle method: index 0 fixed, 1..n-1 rotating by
+// one position per step, positions s and n-1-s meeting) is the same
+// 1-factorization under a fixed relabeling: with x the modulus label, the
+// round-robin index is lambda(x) = 1 + (2x mod m) for x < m and lambda(m) = 0,
+// and round-robin step k is modulus step k - 1 (mod m).  (Player 1 + ((s - 1 +
+// k) mod m) at position s meets 1 + ((m - 1 - s + k) mod m); halving the
+// labels minus one turns their sum 2k - 2 into k - 1.)  So both orderings run
+// through the same slot structure, and the two-step passes below serve both:
+// only the indices are mapped.  The slots of a step may be numbered in any
+// order without changing a bit (disjoint pivots).
+__device__ inline int ord_index(int ord, int m, int x) {
+  if (ord == 1) return x;
+  const int y = 2 * x;
+  return x == m ? 0 : 1 + (y >= m ? y - m : y);
 }
 
-// the pivot pair of slot q in step k of the ordering `ord`, i < j
+// the centre c of step k (2c = k' mod m, k' the modulus step)
+__device__ inline int mm_center(int n, int k, int ord) {
+  const int m = n - 1;
+  const int kk = ord == 1 ? k : (k == 0 ? m - 1 : k - 1);
+  return (kk & 1) ? (kk + m) >> 1 : kk >> 1;
+}
+
+// the indices A and B of slot q of the step with centre c
+__device__ inline void mm_ab(int m, int c, int q, int &A, int &B, int ord) {
+  int a = c + q, b = c - q;
+  a = a >= m ? a - m : a;
+  b = b < 0 ? b + m : b;
+  A = ord_index(ord, m, q == 0 ? m : a);
+  B = ord_index(ord, m, q == 0 ? c : b);
+}
+
+// the pivot pair of slot q in step k of the ordering `ord` (0 or 1), i < j
 __device__ inline void piv_pair(int ord, int n, int k, int q, int &i, int &j) {
-  if (ord == 1) {
-    mm_pair(n, k, q, i, j);
-  } else {
-    int a = rr_player(n, k, q), b = rr_player(n, k, n - 1 - q);
-    i = a < b ? a : b;
-    j = a < b ? b : a;
+  int A, B;
+  mm_ab(n - 1, mm_center(n, k, ord), q, A, B, ord);
+  i = A < B ? A : B;
+  j = A < B ? B : A;
+}
+
+// Dynamic ordering (ord = 2): the pivots of a step are a greedy matching on the
+// weights w = fma(x_ij, x_ij, x_ji * x_ji) (binary64, x = G 2^-t with t the norm
+// exponent), taken by decreasing weight, equal weights by the smaller index and
+// then the larger.  With that strict total order on the pairs, the greedy
+// matching is found in rounds of locally dominant pairs: each free index v
+// points to the first pair (v, u) among free u; pairs whose two ends point to
+// each other are the first at both ends, are taken by the greedy matching, and
+// leave the greedy matching of what remains; every round takes at least the
+// first remaining pair.  A pointer stays valid while its target is free (the
+// candidates only shrink), so only indices whose target was taken scan again.
+template <class R>
+__device__ inline double dyn_weight(const R *G, int n, int a, int b, double sc) {
+  double x = (double)G[a + (int64_t)b * n] * sc, y = (double)G[b + (int64_t)a * n] * sc;
+  return fma(x, x, y * y);
+}
+
+// pair (w1; a1 < b1) before pair (w2; a2 < b2) in the order of the matching
+__device__ inline bool dyn_before(double w1, int a1, int b1, double w2, int a2, int b2) {
+  if (w1 != w2) return w1 > w2;
+  if (a1 != a2) return a1 < a2;
+  return b1 < b2;
+}
+
+// The matching of the current G by the whole workgroup; mate and best are n
+// entries of LDS each, flag one int of LDS.  The pairs go to spair (i < j) in
+// increasing order of i.  Every thread of the block calls it.
+template <class R>
+__device__ void dyn_match(const R *G, int n, double sc, int16_t *mate, int16_t *best, int *flag,
+                          int16_t *spair) {
+  for (int v = threadIdx.x; v < n; v += blockDim.x) {
+    mate[v] = -1;
+    best[v] = -1;
   }
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (;;) {
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (mate[v] >= 0) continue;
+      int b = best[v];
+      if (b >= 0 && mate[b] < 0) continue;
+      double bw = 0.0;
+      int bu = -1, ba = 0, bb = 0;
+      for (int u = 0; u < n; ++u) {
+        if (u == v || mate[u] >= 0) continue;
+        int a = min(u, v), c = max(u, v);
+        double w = dyn_weight(G, n, a, c, sc);
+        if (bu < 0 || dyn_before(w, a, c, bw, ba, bb)) {
+          bw = w;
+          bu = u;
+          ba = a;
+          bb = c;
+        }
+      }
+      best[v] = (int16_t)bu;
+    }
+    __syncthreads();
+    // each index writes only its own entry: a mutual pair is taken by both ends
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (mate[v] >= 0) continue;
+      int u = best[v];
+      if (best[u] == v)
+        mate[v] = (int16_t)u;
+      else
+        *flag = 1;
+    }
+    __syncthreads();
+    int more = *flag;
+    __syncthreads();
+    if (!more) break;
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+  }
+  // the pairs in increasing order of their smaller index (wave 0)
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int base = 0;
+    for (int v0 = 0; v0 < n; v0 += 64) {
+      int v = v0 + lane;
+      bool lead = v < n && v < mate[v];
+      uint64_t bal = __ballot(lead);
+      int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+      if (lead) {
+        spair[2 * pos] = (int16_t)v;
+        spair[2 * pos + 1] = mate[v];
+      }
+      base += __popcll(bal);
+    }
+  }
+  __syncthreads();
 }
 
 template <class R> struct Piv {
@@ -273,20 +374,6 @@ __device__ void g_step_block(const R *Gin, R *G, int n, const R *S, const int16_
 // same order (the same bits).  The pivots of step k + 1 are formed first, by
 // the same element formulas.
 
-// A and B indices of slot q of step k (c = c_k)
-__device__ inline void mm_ab(int m, int c, int q, int &A, int &B) {
-  int a = c + q, b = c - q;
-  a = a >= m ? a - m : a;
-  b = b < 0 ? b + m : b;
-  A = q == 0 ? m : a;
-  B = q == 0 ? c : b;
-}
-
-__device__ inline int mm_center(int n, int k) {
-  const int m = n - 1;
-  return (k & 1) ? (k + m) >> 1 : k >> 1;
-}
-
 // a 2x2 block given by A/B row and A/B column (xAB = element (A row, B column))
 // to its i/j form (a = (i, i), b = (j, i), c = (i, j), d = (j, j)); rai: the A
 // row is the smaller index of its pair, cai likewise for the columns
@@ -335,13 +422,14 @@ __device__ inline Wab<R> blk_after(const R *S, int np, int p, int q, bool aip, b
 // and of B_(d-1) (slot d - 1), and its off-diagonal elements in the step-k
 // blocks (d, d-1) and (d-1, d).  Parameters to S2 (LDS) and slot2 (table).
 template <class R, int BS>
-__device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R *slot2) {
-  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+__device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R *slot2,
+                              int ord) {
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   for (int dd = threadIdx.x; dd < np; dd += BS) {
     const int dm = dd == 0 ? np - 1 : dd - 1;
     int Ad, Bd, Am, Bm;
-    mm_ab(m, c, dd, Ad, Bd);
-    mm_ab(m, c, dm, Am, Bm);
+    mm_ab(m, c, dd, Ad, Bd, ord);
+    mm_ab(m, c, dm, Am, Bm, ord);
     const bool aid = Ad < Bd, aim = Am < Bm;
     const R gAA = aid ? S1[C_S1 * np + dd] : S1[C_S2 * np + dd];
     const R gBB = aim ? S1[C_S2 * np + dm] : S1[C_S1 * np + dm];
@@ -419,10 +507,11 @@ __device__ inline double lane_up(double x) {
 // selection, inactive lanes load and store nothing through the buffer's
 // range check.
 template <class R, int BS, int kAhead>
-__device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, const R *S2) {
+__device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, const R *S2,
+                             int ord) {
   constexpr int NW = BS / 64;
   constexpr int W = (int)sizeof(R);
-  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   // the wave index is the same for all lanes of a wave: saying so keeps the
   // column offsets in scalar registers
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -440,8 +529,8 @@ __device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, cons
     int p = d0 + lane - 1;
     p = act ? (p < 0 ? p + np : p) : 0;
     int Ap, Bp, Aq, Bq;
-    mm_ab(m, c, p, Ap, Bp);
-    mm_ab(m, c, p == 0 ? np - 1 : p - 1, Aq, Bq);
+    mm_ab(m, c, p, Ap, Bp, ord);
+    mm_ab(m, c, p == 0 ? np - 1 : p - 1, Aq, Bq, ord);
     const bool aip = Ap < Bp;
     const int rA = Ap, rB = Bq;  // output row pair p of step k + 1
     const bool rai = rA < rB;
@@ -463,7 +552,7 @@ __device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, cons
     };
     auto load = [&](int t, R *x) {
       int Ae, Be;
-      mm_ab(m, c, slot_of(t), Ae, Be);
+      mm_ab(m, c, slot_of(t), Ae, Be, ord);
       const int si = min(Ae, Be) * cb, sj = max(Ae, Be) * cb;
       x[0] = in.ld(vip, si);
       x[1] = in.ld(vjp, si);
@@ -483,7 +572,7 @@ __device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, cons
         load(t + kAhead, f[z]);
         const int e = slot_of(t);
         int Ae, Be;
-        mm_ab(m, c, e, Ae, Be);
+        mm_ab(m, c, e, Ae, Be, ord);
         const bool aie = Ae < Be;
         // step-k block (p, e) after step k, by A/B row and column
         Blk<R> o = blk_rot(u11, u21, u12, u22, S1[C_V11 * np + e], S1[C_V21 * np + e],
@@ -544,24 +633,24 @@ __device__ inline FusedGeo fused_geo(int n, int nw, int snap_elems) {
 
 // columns A and B of each boundary slot (the pre-step slot of each segment)
 template <class R, int BS>
-__device__ void g_fused_snapshot(const R *G, int n, int k, FusedGeo g, R *snap) {
-  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+__device__ void g_fused_snapshot(const R *G, int n, int k, FusedGeo g, R *snap, int ord) {
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   for (int x = threadIdx.x; x < g.cs * 2 * n; x += BS) {
     const int sg = x / (2 * n), r = x - sg * 2 * n, side = r / n, row = r - side * n;
     int b = sg * g.ls - 1;
     b = b < 0 ? b + np : b;
     int A, B;
-    mm_ab(m, c, b, A, B);
+    mm_ab(m, c, b, A, B, ord);
     snap[x] = G[row + (int64_t)(side ? B : A) * n];
   }
 }
 
 template <class R, int BS, int S>
 __device__ void g_fused_inplace(R *G, int n, int k, const R *S1, const R *S2, FusedGeo g,
-                                const R *snap) {
+                                const R *snap, int ord) {
   constexpr int W = (int)sizeof(R);
   constexpr int kAhead = 4 / S;
-  const int np = n >> 1, m = n - 1, c = mm_center(n, k);
+  const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   const int lane = threadIdx.x & 63, sg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (sg >= g.cs) return;  // this wave has no segment (the same for all its lanes)
   const int L = (np + S - 1) / S;  // lanes holding slots
@@ -579,8 +668,8 @@ __device__ void g_fused_inplace(R *G, int n, int k, const R *S1, const R *S2, Fu
     val[s] = lane < L && p < np;
     pp[s] = val[s] ? p : 0;
     int Ap, Bp, Aq, Bq;
-    mm_ab(m, c, pp[s], Ap, Bp);
-    mm_ab(m, c, pp[s] == 0 ? np - 1 : pp[s] - 1, Aq, Bq);
+    mm_ab(m, c, pp[s], Ap, Bp, ord);
+    mm_ab(m, c, pp[s] == 0 ? np - 1 : pp[s] - 1, Aq, Bq, ord);
     aip[s] = Ap < Bp;
     rai[s] = Ap < Bq;  // output pair p: rows A_p and B_(p-1)
     sip[s] = min(Ap, Bp);
@@ -599,7 +688,7 @@ __device__ void g_fused_inplace(R *G, int n, int k, const R *S1, const R *S2, Fu
   // the blocks of column slot t (nothing is read for the boundary slots)
   auto load = [&](int t, R (*x)[4]) {
     int Ae, Be;
-    mm_ab(m, c, slot_of(t), Ae, Be);
+    mm_ab(m, c, slot_of(t), Ae, Be, ord);
     const bool edge = t == 0 || t >= cnt - 1;
     const int si = min(Ae, Be) * cb, sj = max(Ae, Be) * cb;
 #pragma unroll
@@ -630,7 +719,7 @@ __device__ void g_fused_inplace(R *G, int n, int k, const R *S1, const R *S2, Fu
       load(t + kAhead, f[z]);
       const int e = slot_of(t);
       int Ae, Be;
-      mm_ab(m, c, e, Ae, Be);
+      mm_ab(m, c, e, Ae, Be, ord);
       const bool aie = Ae < Be;
       if (t == 0 || t == cnt - 1) {  // a boundary slot: from the copy
         const R *sa = snap + (size_t)(t == 0 ? sg : sgn) * 2 * n, *sb = sa + n;
@@ -763,7 +852,7 @@ template <class R, int D = 8> __device__ void tile_store(const R *T, R *M, int n
 // the loop body has no branches
 template <class R, int NG>
 __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv,
-                               int ord, int cm) {
+                               int ord, int cm, const int16_t *ptab) {
   const int ldt = n + 1;
   const int np = n >> 1;
   const int lane = threadIdx.x & 63;
@@ -779,7 +868,13 @@ __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab
         bool ok = q < np;
         int qs = ok ? q : 0;
         int i, j;
-        piv_pair(ord, n, k, qs, i, j);
+        if (ord == 2) {
+          const int16_t *pp = ptab + 2 * ((size_t)(k & cm) * np + qs);
+          i = pp[0];
+          j = pp[1];
+        } else {
+          piv_pair(ord, n, k, qs, i, j);
+        }
         ii[u] = ok ? i : n;
         jj[u] = ok ? j : n;
         e1[u] = S[qs];           // u11 or v11
@@ -836,8 +931,9 @@ __device__ inline double lane_read(double x, int l) {
 // is read and written once per two steps.  Slots past np use the padding
 // column n, which is never copied back.
 template <class R, int S>
-__device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool isv, int cm) {
-  const int ldt = n + 1, np = n >> 1, m = n - 1, c = mm_center(n, k);
+__device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool isv, int cm,
+                                 int ord) {
+  const int ldt = n + 1, np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int comp = isv ? C_V11 : C_U11;
   const R *S1 = tab + (size_t)(k & cm) * kPivComp * np + comp * np;
@@ -852,8 +948,8 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
     const bool ok = p < np;
     const int ps = ok ? p : 0;
     int A, B, Aq, Bq;
-    mm_ab(m, c, ps, A, B);
-    mm_ab(m, c, ps == 0 ? np - 1 : ps - 1, Aq, Bq);
+    mm_ab(m, c, ps, A, B, ord);
+    mm_ab(m, c, ps == 0 ? np - 1 : ps - 1, Aq, Bq, ord);
     aip[s] = A < B;
     rai[s] = A < Bq;
     ia[s] = ok ? min(A, B) : n;  // the step-k pair (i, j) of slot p
@@ -908,34 +1004,34 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
 // (orders up to 256; the register budget of workgroups of up to 512 lanes)
 template <class R, bool kPairs = true>
 __device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv, int ord,
-                            int cm) {
+                            int cm, const int16_t *ptab) {
   if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
   const int np = n >> 1;
-  if (kPairs && ord == 1 && n >= 4 && np <= 128) {
+  if (kPairs && ord != 2 && n >= 4 && np <= 128) {
     // consecutive steps in pairs (the rows of a wave are its own: a wave
     // barrier orders one pass after the previous)
     int k = k0;
     for (; k + 1 <= k1; k += 2) {
       if (np <= 64)
-        tile_rotate_pair<R, 1>(T, n, nr, k, tab, isv, cm);
+        tile_rotate_pair<R, 1>(T, n, nr, k, tab, isv, cm, ord);
       else
-        tile_rotate_pair<R, 2>(T, n, nr, k, tab, isv, cm);
+        tile_rotate_pair<R, 2>(T, n, nr, k, tab, isv, cm, ord);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (k <= k1) {
       if (np <= 64)
-        tile_rotate_ng<R, 1>(T, n, nr, k, k, tab, isv, ord, cm);
+        tile_rotate_ng<R, 1>(T, n, nr, k, k, tab, isv, ord, cm, ptab);
       else
-        tile_rotate_ng<R, 2>(T, n, nr, k, k, tab, isv, ord, cm);
+        tile_rotate_ng<R, 2>(T, n, nr, k, k, tab, isv, ord, cm, ptab);
     }
     return;
   }
   if (np <= 64)
-    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord, cm);
+    tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord, cm, ptab);
   else
-    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv, ord, cm);
+    tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv, ord, cm, ptab);
 }
 
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
@@ -1067,6 +1163,22 @@ __global__ __launch_bounds__(kRed) void k_sw_init(SweepDesc d, R *G, R *U, R *V,
   }
 }
 
+// the dynamic ordering's pairs of step k (one workgroup per matrix) into the
+// pair table; LDS: the matching's two index arrays of the largest order
+template <class R>
+__global__ __launch_bounds__(kRed) void k_sw_match(SweepDesc d, const R *G, int16_t *pairs,
+                                                   int k) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int flag;
+  int m = blockIdx.x;
+  int n = d.n[m];
+  if (k >= n - 1 || d.done[m]) return;  // uniform over the block
+  int np = n >> 1;
+  int16_t *mate = reinterpret_cast<int16_t *>(smem), *best = mate + n;
+  int64_t slot = d.chunk * d.poff[m] + (int64_t)(k & (d.chunk - 1)) * np;
+  dyn_match(G + d.off[m], n, ldexp(1.0, -d.nexp[m]), mate, best, &flag, pairs + 2 * slot);
+}
+
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, R *par,
                                                       int16_t *pairs, int k) {
@@ -1076,10 +1188,15 @@ __global__ __launch_bounds__(kBlock) void k_sw_pivots(SweepDesc d, const R *G, R
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= np || k >= n - 1 || d.done[m]) return;
   int i, j;
-  piv_pair(d.ord, n, k, q, i, j);
   int64_t slot = d.chunk * d.poff[m] + (int64_t)(k & (d.chunk - 1)) * np;
-  pairs[2 * (slot + q)] = (int16_t)i;
-  pairs[2 * (slot + q) + 1] = (int16_t)j;
+  if (d.ord == 2) {  // written by k_sw_match
+    i = pairs[2 * (slot + q)];
+    j = pairs[2 * (slot + q) + 1];
+  } else {
+    piv_pair(d.ord, n, k, q, i, j);
+    pairs[2 * (slot + q)] = (int16_t)i;
+    pairs[2 * (slot + q) + 1] = (int16_t)j;
+  }
   piv_store(par + slot * kPivComp, np, q, pivot_svd(G + d.off[m], n, i, j));
 }
 
@@ -1130,7 +1247,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   tile_load(T, M, n, r0, nr);
   __syncthreads();
   tile_rotate<R, false>(T, n, nr, k0, k1, par + d.chunk * d.poff[m] * kPivComp, blockIdx.y != 0,
-                        d.ord, d.chunk - 1);
+                        d.ord, d.chunk - 1, d.pairs + 2 * d.chunk * d.poff[m]);
   __syncthreads();
   tile_store(T, M, n, r0, nr);
 }
@@ -1207,7 +1324,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   __syncthreads();
   // under the modified modulus ordering steps go in pairs through G and a
   // second buffer; the sweep's last step (n - 1 steps, an odd count) lands in G
-  const bool pairs2 = d.ord == 1 && n >= 4 && two;
+  const bool pairs2 = d.ord != 2 && n >= 4 && two;
   R *Ga = pairs2 ? reinterpret_cast<R *>(d.galt) + d.aoff[m] : Gm;
   // orders up to 256 update G in place when the boundary columns fit the tile
   // (in workgroups of up to 512 lanes, whose registers hold that path)
@@ -1215,15 +1332,31 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   const bool inplace = inplace_ok && uses_inplace(BS, n, tile_elems) && pairs2;
   int sw = 0;
   bool conv = false;
+  // dynamic ordering: the chunk's pairs go to the pair table (for the U/V
+  // update); the matching's index arrays use the U/V tile, its flag the
+  // reduction buffer (both idle during a step's pivots)
+  int16_t *ptab = d.ord == 2 ? d.pairs + 2 * d.chunk * d.poff[m] : nullptr;
   for (; sw < max_sweeps && !conv; ++sw) {
     const R *cur = Gm;
     for (int k = 0; k < n - 1;) {
       R *slot = tab + (size_t)(k & cm) * kPivComp * np;
+      if (d.ord == 2) {
+        int16_t *mate = reinterpret_cast<int16_t *>(T);
+        dyn_match(cur, n, nsc, mate, mate + n, reinterpret_cast<int *>(red), spair);
+      }
       for (int q = threadIdx.x; q < np; q += BS) {
         int i, j;
-        piv_pair(d.ord, n, k, q, i, j);
-        spair[2 * q] = (int16_t)i;
-        spair[2 * q + 1] = (int16_t)j;
+        if (d.ord == 2) {
+          i = spair[2 * q];
+          j = spair[2 * q + 1];
+          int16_t *pp = ptab + 2 * ((size_t)(k & cm) * np + q);
+          pp[0] = (int16_t)i;
+          pp[1] = (int16_t)j;
+        } else {
+          piv_pair(d.ord, n, k, q, i, j);
+          spair[2 * q] = (int16_t)i;
+          spair[2 * q + 1] = (int16_t)j;
+        }
         Piv<R> P = pivot_svd(cur, n, i, j);
         piv_store(spar, np, q, P);
         piv_store(slot, np, q, P);
@@ -1231,19 +1364,19 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
       __syncthreads();
       if (pairs2 && k + 2 <= n - 2) {
         R *slot2 = tab + (size_t)((k + 1) & cm) * kPivComp * np;
-        g_pivots_next<R, BS>(cur, n, k, spar, spar2, slot2);
-        if (inplace) g_fused_snapshot<R, BS>(Gm, n, k, geo, T);
+        g_pivots_next<R, BS>(cur, n, k, spar, spar2, slot2, d.ord);
+        if (inplace) g_fused_snapshot<R, BS>(Gm, n, k, geo, T, d.ord);
         __syncthreads();
         if (inplace) {
           if constexpr (BS <= 512) {
             if (np <= 64)
-              g_fused_inplace<R, BS, 1>(Gm, n, k, spar, spar2, geo, T);
+              g_fused_inplace<R, BS, 1>(Gm, n, k, spar, spar2, geo, T, d.ord);
             else
-              g_fused_inplace<R, BS, 2>(Gm, n, k, spar, spar2, geo, T);
+              g_fused_inplace<R, BS, 2>(Gm, n, k, spar, spar2, geo, T, d.ord);
           }
         } else {
           R *nxt = cur == Gm ? Ga : Gm;
-          g_fused_pair<R, BS, sizeof(R) == 8 ? 4 : 6>(cur, nxt, n, k, spar, spar2);
+          g_fused_pair<R, BS, sizeof(R) == 8 ? 4 : 6>(cur, nxt, n, k, spar, spar2, d.ord);
           cur = nxt;
         }
         k += 2;
@@ -1264,7 +1397,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
             int nr = min(rows, n - r0);
             tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
-            tile_rotate<R, (BS <= 512)>(T, n, nr, k0, kl, tab, side != 0, d.ord, cm);
+            tile_rotate<R, (BS <= 512)>(T, n, nr, k0, kl, tab, side != 0, d.ord, cm, ptab);
             __syncthreads();
             tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
             __syncthreads();
@@ -1660,7 +1793,7 @@ static int make_plan(int64_t nmat, const int32_t *n_host, const int64_t *off_hos
       // the matrices whose two-step passes go through the second buffer
       for (int x = s.begin; x < s.begin + s.count; ++x) {
         const int m = P.order[x], n = n_host[m];
-        const bool pairs2 = ordering == 1 && n >= 4 && two;
+        const bool pairs2 = ordering != 2 && n >= 4 && two;
         const bool inplace = s.inplace_ok && uses_inplace(s.block, n, te) && pairs2;
         if (pairs2 && !inplace) {
           P.aoff[m] = P.galt;
@@ -1669,7 +1802,7 @@ static int make_plan(int64_t nmat, const int32_t *n_host, const int64_t *off_hos
       }
     }
   }
-  P.L = ws_layout(nmat, P.npiv, chunk, mode == 0, P.galt, w);
+  P.L = ws_layout(nmat, P.npiv, chunk, mode == 0 || ordering == 2, P.galt, w);
   return KSVD2_OK;
 }
 
@@ -1758,8 +1891,9 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   if (!n_host || !off_host) return fail(KSVD2_EINVAL, "n_host and off_host are required");
   if (max_sweeps < 0) return fail(KSVD2_EINVAL, "max_sweeps < 0");
   if (mode < 0 || mode > 2) return fail(KSVD2_EINVAL, "mode must be 0, 1 or 2");
-  if (ordering != 0 && ordering != 1)
-    return fail(KSVD2_EINVAL, "ordering must be 0 (round-robin) or 1 (modified modulus)");
+  if (ordering < 0 || ordering > 2)
+    return fail(KSVD2_EINVAL,
+                "ordering must be 0 (round-robin), 1 (modified modulus) or 2 (dynamic)");
   if (nmat > 65535) return fail(KSVD2_EINVAL, "at most 65535 matrices per call");
   if (mode == 2 && st == nullptr)
     return fail(KSVD2_EINVAL, "mode 2 (hipGraph) needs a non-null stream");
@@ -1812,6 +1946,7 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
   d.aoff = reinterpret_cast<const int64_t *>(wsb + L.aoff);
   d.galt = wsb + L.galt;
   d.chunk = P.chunk;
+  d.pairs = reinterpret_cast<int16_t *>(wsb + L.pairs);
   const int32_t *order_dev = reinterpret_cast<const int32_t *>(wsb + L.order);
 
   R *par = reinterpret_cast<R *>(wsb + L.par);
@@ -1843,6 +1978,9 @@ static int sweep_impl(int dtype, int64_t nmat, const int32_t *n_host, const int6
     std::vector<int32_t> done(nmat);
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int k = 0; k < maxn - 1; ++k) {
+        if (ordering == 2)
+          hipLaunchKernelGGL(k_sw_match<R>, dim3((unsigned)nmat), dim3(kRed),
+                             (size_t)4 * maxn, st, d, G, pairs, k);
         hipLaunchKernelGGL(k_sw_pivots<R>, dim3(grid_for(maxnp), (unsigned)nmat), dim3(kBlock), 0,
                            st, d, G, par, pairs, k);
         hipLaunchKernelGGL(k_sw_update<R>, dim3(grid_for(maxblocks), (unsigned)nmat),

@@ -16,7 +16,7 @@ from . import _lib
 
 _DT = {torch.float32: 0, torch.float64: 1}
 MODES = {"plain": 0, "persistent": 1, "graph": 2}
-ORDERINGS = {"round-robin": 0, "modulus": 1}
+ORDERINGS = {"round-robin": 0, "modulus": 1, "dynamic": 2}
 
 
 class Packed:

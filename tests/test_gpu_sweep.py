@@ -124,6 +124,43 @@ def test_converged_modes_identical_and_accurate(orc, dtype):
             assert st == 0 and abs(swp - int(r["sweeps"][k])) <= 1
 
 
+def _off_ratio(G, G0, eps):
+    """||offdiag(G)||_F^2 / (n eps ||G0||_F)^2, each sum correctly rounded (math.fsum of
+    the binary64 squares: relative error a few 2^-53)."""
+    import math
+
+    n = G.shape[0]
+    Gd = np.asarray(G, np.float64)
+    off = Gd[~np.eye(n, dtype=bool)]
+    num = math.fsum((off * off).tolist())
+    g0 = np.asarray(G0, np.float64).ravel()
+    den = math.fsum((g0 * g0).tolist()) * (n * eps) ** 2
+    return num / den
+
+
+def _check_stop(orc, G0, s_gpu, eps):
+    """The stopping decision (Sect. 1: stop once ||offdiag(G)||_F <= n eps ||G_0||_F after
+    a sweep) of the device, taken after s_gpu sweeps, against the exact test on the
+    oracle's iterates, and against the oracle's own count with its test on.  Any
+    binary64 sum of N terms is within (N - 1) 2^-53 (relatively) of the exact one, so a
+    decision may differ between the two reductions only when the exact ratio lies
+    within delta = (n^2 + 8) 2^-52 of 1; elsewhere both counts must be the same."""
+    n = G0.shape[0]
+    delta = (n * n + 8) * 2.0 ** -52
+    Gp, Up, Vp, _, _ = orc.kog_sweep(G0, max_sweeps=s_gpu - 1, tol_factor=-1.0)
+    Gs, _, _, _, _ = orc.kog_sweep(Gp, max_sweeps=1, tol_factor=-1.0, U=Up, V=Vp)
+    r_prev = _off_ratio(Gp, G0, eps) if s_gpu > 1 else np.inf
+    r_last = _off_ratio(Gs, G0, eps)
+    assert r_last <= 1 + delta, (n, s_gpu, r_last)
+    assert r_prev > 1 - delta, (n, s_gpu, r_prev)
+    _, _, _, st, s_orc = orc.kog_sweep(G0, max_sweeps=s_gpu + 2, tol_factor=1.0)
+    assert st == 0
+    if s_orc != s_gpu:
+        assert abs(s_orc - s_gpu) == 1, (n, s_orc, s_gpu)
+        r_dec = r_prev if s_orc > s_gpu else r_last
+        assert abs(r_dec - 1) <= delta, (n, s_orc, s_gpu, r_dec)
+
+
 def test_uniform_workload_full_size_sampled(orc):
     """256 matrices of order 256 (FP64), persistent mode as benchmarked."""
     import torch
@@ -145,6 +182,7 @@ def test_uniform_workload_full_size_sampled(orc):
         n = mats[k].shape[0]
         # LAPACK's singular values are accurate to n eps sigma_max (absolute) only
         assert np.max(np.abs(sig - ref)) <= 10 * n * 2.0 ** -53 * ref[0]
+        _check_stop(orc, mats[k], int(sweeps[k]), 2.0 ** -53)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -169,6 +207,7 @@ def test_uneven_workload_full_size_sampled(orc, dtype):
     for k in picks:
         G, U, V, st, swp = orc.kog_sweep(mats[k], max_sweeps=int(sweeps[k]), tol_factor=-1.0)
         assert _same(Gs[k], G) and _same(Us[k], U) and _same(Vs[k], V), (k, ns[k])
+        _check_stop(orc, mats[k], int(sweeps[k]), 2.0 ** (-53 if dtype == np.float64 else -24))
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -446,6 +485,93 @@ def test_two_step_passes_every_block_size(orc, dtype):
     finally:
         for bucket, block in enumerate((256, 512, 512, 1024, 1024)):
             sw.set_tuning(tdt, bucket, block)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_every_tuning_knob_bitwise(orc, dtype):
+    """The schedule knobs the autotuner searches (steps per U/V update, two steps of G
+    per pass, the in-place pass, a cap on U/V tile rows, with every workgroup size)
+    change no bit: one and a half sweeps of orders across the buckets against the
+    oracle, under each setting, both orderings."""
+    import torch
+
+    from paper_2407_13116_amd import sweep as sw
+
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    ns = [6, 64, 66, 130, 256, 258, 300]
+    mats = _mats(np.random.default_rng(45), ns, dtype)
+    settings = [dict(chunk=2), dict(chunk=16, rows=8), dict(two=0), dict(inplace=0, block=512),
+                dict(chunk=32, two=0, rows=1, block=1024), dict(inplace=0, chunk=64, rows=24),
+                dict(block=256, chunk=8)]
+    try:
+        for ordering in ("modulus", "round-robin"):
+            ref = [orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0,
+                                 ordering=1 if ordering == "modulus" else 0) for G0 in mats]
+            for st in settings:
+                sw.reset_tuning()
+                sw.set_tuning(tdt, -1, **st)
+                p, got = _run(mats, dtype, "persistent", max_sweeps=2, tolf=-1.0,
+                              ordering=ordering)
+                for k in range(len(ns)):
+                    G, U, V, _, _ = ref[k]
+                    for key, want in (("G", G), ("U", U), ("V", V)):
+                        assert _same(got[key][k], want), (ordering, st, ns[k], key)
+    finally:
+        sw.reset_tuning()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_dynamic_ordering_bitwise_vs_oracle(orc, dtype, mode):
+    """The dynamic ordering (a greedy matching of every step's weights): two sweeps
+    bit for bit against the oracle in every mode, on orders 2 .. 258 and on sparse and
+    integer matrices whose weights tie (zeros, repeated magnitudes), where the index
+    order of equal weights decides; then converged runs with the oracle's sweep count."""
+    rng = np.random.default_rng(91)
+    ns = [2, 4, 6, 10, 16, 34, 64, 66, 130]
+    mats = _mats(rng, ns, dtype)
+    for n in (8, 40, 258):
+        A = rng.choice([0.0, 1.0, -1.0, 2.0], (n, n)) * (rng.random((n, n)) < 0.3)
+        mats.append(np.asfortranarray(A.astype(dtype)))
+    ns = [m.shape[0] for m in mats]
+    p, got = _run(mats, dtype, mode, max_sweeps=2, tolf=-1.0, ordering="dynamic")
+    for k, G0 in enumerate(mats):
+        G, U, V, _, _ = orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0, ordering=2)
+        assert _same(got["G"][k], G), (mode, ns[k], "G")
+        assert _same(got["U"][k], U), (mode, ns[k], "U")
+        assert _same(got["V"][k], V), (mode, ns[k], "V")
+    small = mats[:7]
+    p, got = _run(small, dtype, mode, max_sweeps=30, tolf=1.0, ordering="dynamic")
+    for k, G0 in enumerate(small):
+        G, U, V, st, swp = orc.kog_sweep(G0, max_sweeps=30, tol_factor=1.0, ordering=2)
+        assert st == 0 and int(got["sweeps"][k]) == swp, (mode, ns[k])
+        assert _same(got["G"][k], G) and _same(got["U"][k], U), (mode, ns[k])
+
+
+def test_autotuner_installs_a_valid_schedule(tmp_path, monkeypatch):
+    """The autotuner's coordinate search on a small uneven batch: one setting per bucket
+    present, each within the knobs' ranges and installed in the library's table; a
+    second call reuses the cache without timing."""
+    import torch
+
+    from paper_2407_13116_amd import autotune
+    from paper_2407_13116_amd import sweep as sw
+
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    mats = _mats(np.random.default_rng(46), [20, 40, 100, 130, 200, 300], np.float64)
+    try:
+        chosen = autotune.tune(mats, torch.float64, sample=4, force=True)
+        assert sorted(chosen) == [0, 1, 2, 3]
+        for b, st in chosen.items():
+            assert st["block"] in (256, 512, 1024) and st["two"] in (0, 1)
+            assert st["inplace"] in (0, 1) and st["chunk"] in (16, 32, 64, 128)
+            assert st["rows"] in (0, 16, 32, 64)
+            assert sw.get_tuning(torch.float64, b) == st
+        sw.reset_tuning()
+        again = autotune.tune(mats, torch.float64, sample=4)
+        assert again == chosen
+    finally:
+        sw.reset_tuning()
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
