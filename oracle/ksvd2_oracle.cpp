@@ -1538,6 +1538,20 @@ template <class R>
 static void qrcp_one(int m, int n, R *A, R *tau, int32_t *perm, R *Rsq) {
   auto a = [&](int i, int j) -> R & { return A[i + (int64_t)j * m]; };
   for (int j = 0; j < n; ++j) perm[j] = j;
+  /* Scaling (a reading: the paper takes the QR preprocessing from LAPACK, whose
+     norms avoid overflow): when the squared column norms could leave the normal
+     range (2 |e_max| + ceil(lg m) + 2 >= e_nu, e_max the largest exponent of an
+     entry), the matrix is multiplied by 2^-e_max first and R by 2^e_max at the
+     end; the reflectors and tau are scale-free. */
+  int emax = INT_MIN;
+  for (int64_t x = 0; x < (int64_t)m * n; ++x)
+    if (A[x] != 0) emax = std::max(emax, std::ilogb(A[x]));
+  int lgm = 0;
+  while ((1 << lgm) < m) ++lgm;
+  int sc = 0;
+  if (emax != INT_MIN && 2 * std::abs(emax) + lgm + 2 >= Fmt<R>::e_nu) sc = -emax;
+  if (sc != 0)
+    for (int64_t x = 0; x < (int64_t)m * n; ++x) A[x] = std::scalbn(A[x], sc);
   for (int k = 0; k < n; ++k) {
     /* pivot: the largest squared norm of the trailing columns (rows k..m-1) */
     int p = k;
@@ -1576,6 +1590,9 @@ static void qrcp_one(int m, int n, R *A, R *tau, int32_t *perm, R *Rsq) {
       for (int i = k + 1; i < m; ++i) a(i, j) -= tw * a(i, k);
     }
   }
+  if (sc != 0)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i <= j && i < m; ++i) a(i, j) = std::scalbn(a(i, j), -sc);
   /* the n x n triangular factor, zeros below the diagonal */
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i) Rsq[i + (int64_t)j * n] = (i <= j) ? a(i, j) : (R)0;

@@ -15,6 +15,7 @@
 // (columns are independent, so no workgroup barrier is needed there).
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -39,11 +40,34 @@ template <class R> __device__ inline R wave_sum(R v) {
   return v;
 }
 
+template <class R> struct RectLim;
+template <> struct RectLim<double> {
+  static constexpr int e_nu = 1023;
+};
+template <> struct RectLim<float> {
+  static constexpr int e_nu = 127;
+};
+
+// The power of two s by which the factorization scales the matrix first: the
+// squared column norms (m terms up to 2^(2 e_max + 2)) stay in the normal range
+// when 2 |e_max| + ceil(lg m) + 2 < e_nu; otherwise s = -e_max puts the largest
+// entry into [1, 2).  The reflectors and tau do not depend on such a scaling, R
+// scales by 2^s, so R is scaled back at the end; the pivots compare norms all
+// scaled alike.  (Exact, except for entries that scaling down moves below the
+// normal range.)
+__host__ __device__ inline int qrcp_scale(int emax, int m, int e_nu) {
+  if (emax == INT_MIN) return 0;
+  int lgm = 0;
+  while ((1 << lgm) < m) ++lgm;
+  const int ae = emax < 0 ? -emax : emax;
+  return (2 * ae + lgm + 2 < e_nu) ? 0 : -emax;
+}
+
 template <class R>
 __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, int32_t *perm,
                                                      R *Rsq) {
   __shared__ R s_nrm[kRectMaxN];
-  __shared__ int s_piv;
+  __shared__ int s_piv, s_emax;
   __shared__ R s_tau, s_beta, s_scal;
   const int mat = blockIdx.x;
   const int m = d.m[mat], n = d.n[mat];
@@ -52,6 +76,21 @@ __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, i
   int32_t *pm = perm + d.toff[mat];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int j = threadIdx.x; j < n; j += blockDim.x) pm[j] = j;
+  const int64_t tot = (int64_t)m * n;
+  if (threadIdx.x == 0) s_emax = INT_MIN;
+  __syncthreads();
+  {
+    int e = INT_MIN;
+    for (int64_t x = threadIdx.x; x < tot; x += blockDim.x)
+      if (a[x] != (R)0) e = max(e, ilogb(a[x]));
+    atomicMax(&s_emax, e);  // LDS
+  }
+  __syncthreads();
+  const int sc = qrcp_scale(s_emax, m, RectLim<R>::e_nu);
+  if (sc != 0) {
+    for (int64_t x = threadIdx.x; x < tot; x += blockDim.x) a[x] = ldexp(a[x], sc);
+    __syncthreads();
+  }
   // squared column norms over all rows; later steps take them from the update
   // pass of the step before (the same rows, summed by the same lanes in the same
   // order as a separate pass would)
@@ -155,6 +194,14 @@ __global__ __launch_bounds__(kQrcpBlock) void k_qrcp(RectDesc d, R *A, R *tau, i
         s = wave_sum(s);
         if (lane == 0) s_nrm[j] = s;
       }
+    }
+    __syncthreads();
+  }
+  // R scaled back (the reflectors below the diagonal are scale-free)
+  if (sc != 0) {
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
+      int j = (int)(idx / n), i = (int)(idx - (int64_t)j * n);
+      if (i <= j) a[i + (int64_t)j * m] = ldexp(a[i + (int64_t)j * m], -sc);
     }
     __syncthreads();
   }

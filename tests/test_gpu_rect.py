@@ -204,3 +204,133 @@ def test_rect_rank_deficient_and_zero_columns(dt):
         assert np.abs(sd - ref).max() <= 40 * m * e * ref[0]
         R = U.astype(np.float64) @ np.diag(sd) @ V.astype(np.float64).T
         assert np.abs(R - Gd).max() <= 40 * m * e * np.linalg.norm(Gd)
+
+
+def _qapply_gpu(mats, dt, seed=8):
+    """kog_qrcp_batch, then kog_qrcp_apply with random n x n factors U_R, V_R; returns
+    per matrix the device's reflectors, tau and pivots, the U_R, V_R used, and the
+    device's U and V."""
+    import ctypes
+
+    import torch
+
+    from paper_2407_13116_amd import _lib
+    from paper_2407_13116_amd import sweep as sw
+
+    L = _lib.lib()
+    rng = np.random.default_rng(seed)
+    pr = sw.PackedRect(mats, dtype=dt)
+    ntot = int(pr.n.sum())
+    tau = torch.empty(ntot, dtype=pr.A.dtype, device="cuda")
+    perm = torch.empty(ntot, dtype=torch.int32, device="cuda")
+    wsz = int(L.kog_rect_workspace_size(len(pr.m)))
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    m, n, aoff, roff = (np.ascontiguousarray(x) for x in (pr.m, pr.n, pr.aoff, pr.roff))
+    d = 1 if dt == np.float64 else 0
+    assert L.kog_qrcp_batch(d, len(m), ptr(m), ptr(n), ptr(aoff), ptr(roff), pr.A.data_ptr(),
+                            tau.data_ptr(), perm.data_ptr(), pr.R.G.data_ptr(), ws.data_ptr(),
+                            wsz, None) == 0
+    URs = [rng.standard_normal((k, k)).astype(dt) for k in n]
+    VRs = [rng.standard_normal((k, k)).astype(dt) for k in n]
+    UR = sw.Packed(URs, dtype=dt)
+    VR = sw.Packed(VRs, dtype=dt)
+    U = torch.empty_like(pr.A)
+    V = torch.empty_like(pr.R.G)
+    assert L.kog_qrcp_apply(d, len(m), ptr(m), ptr(n), ptr(aoff), ptr(roff), pr.A.data_ptr(),
+                            tau.data_ptr(), perm.data_ptr(), UR.G.data_ptr(), VR.G.data_ptr(),
+                            U.data_ptr(), V.data_ptr(), ws.data_ptr(), wsz, None) == 0
+    torch.cuda.synchronize()
+    Ah, th, ph, Uh = pr.A.cpu().numpy(), tau.cpu().numpy(), perm.cpu().numpy(), U.cpu().numpy()
+    Vs = pr.R.unpack(V)
+    out, t0 = [], 0
+    for k in range(len(mats)):
+        mm, nn = int(m[k]), int(n[k])
+        sl = slice(aoff[k], aoff[k] + mm * nn)
+        out.append((Ah[sl].reshape((mm, nn), order="F"), th[t0:t0 + nn], ph[t0:t0 + nn],
+                    URs[k], VRs[k], Uh[sl].reshape((mm, nn), order="F"), Vs[k]))
+        t0 += nn
+    return out
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shapes", [SHAPES, TALL], ids=["mixed", "tall"])
+def test_qapply_vs_oracle(orc, dt, shapes):
+    """U = H_0 ... H_{n-1} [U_R; 0] and V = P V_R from the same reflectors, tau and pivots
+    (the device's own QRCP output) and the same U_R, V_R, device against the oracle.
+    V is a permutation of rows: bit for bit.  U differs only through the order of the
+    sums v^T u: each reflector changes a column by at most (4m + 3) eps ||u|| beyond the
+    other evaluation (tau ||v||^2 = 2), and orthogonal steps do not amplify earlier
+    differences, so |U - U_oracle| <= n (4m + 3) eps ||U_R[:, j]|| column by column."""
+    mats = _batch(dt, seed=6, shapes=shapes)
+    e = _eps(dt)
+    for k, (A, tau, perm, UR, VR, U, V) in enumerate(_qapply_gpu(mats, dt)):
+        mm, nn = A.shape
+        Uo, Vo = orc.qapply(A, tau, perm, UR, VR)
+        assert np.array_equal(np.ascontiguousarray(V).view(np.uint8),
+                              np.ascontiguousarray(Vo).view(np.uint8)), k
+        cn = np.linalg.norm(UR.astype(np.float64), axis=0)
+        err = np.abs(U.astype(np.float64) - Uo.astype(np.float64)).max(0)
+        bound = nn * (4 * mm + 3) * e * cn
+        assert np.all(err <= bound), (k, float((err / bound).max()))
+        # the same reflectors applied in the opposite order, or with the sign of tau
+        # flipped, would miss by O(||U_R||): the bound is far below that
+        assert float(bound.max()) < 0.05 * float(cn.min()) or mm * nn < 16
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_rect_svd_vs_oracle_same_sweeps(orc, dt):
+    """The whole rectangular path against oracle.svd_rect run for the device's number
+    of sweeps: sorted singular values within 40 m eps sigma_1, and each singular pair
+    (u_j, v_j) within 40 m eps ||G|| / gap_j of the oracle's (up to the sign of the
+    pair), gap_j the distance of sigma_j to the nearest other singular value."""
+    from paper_2407_13116_amd import sweep as sw
+
+    rng = np.random.default_rng(17)
+    shapes = [(40, 10), (64, 64), (100, 64), (129, 128), (300, 256)]
+    mats = [(rng.standard_normal(s) * np.exp2(-np.arange(s[1]) / 8.0)).astype(dt)
+            for s in shapes]
+    res, sweeps = sw.svd_rect(mats, mode="persistent")
+    assert np.all(sweeps > 0)
+    e = _eps(dt)
+    for k, (G, (U, s, V)) in enumerate(zip(mats, res)):
+        mm, nn = G.shape
+        Uo, so, Vo, swo = orc.svd_rect(G, max_sweeps=int(sweeps[k]), tol_factor=-1.0)
+        order = np.argsort(-so, kind="stable")
+        Uo, so, Vo = Uo[:, order], so[order], Vo[:, order]
+        gn = float(np.linalg.norm(G.astype(np.float64)))
+        assert np.abs(s.astype(np.float64) - so).max() <= 40 * mm * e * so[0], k
+        sd = so.astype(np.float64)
+        gap = np.array([np.min(np.abs(np.delete(sd, j) - sd[j])) for j in range(nn)])
+        sgn = np.sign(np.sum(U.astype(np.float64) * Uo, 0))
+        sgn[sgn == 0] = 1
+        tol = 40 * mm * e * gn / gap
+        du = np.abs(U.astype(np.float64) * sgn - Uo).max(0)
+        dv = np.abs(V.astype(np.float64) * sgn - Vo).max(0)
+        ok = tol < 0.5                     # pairs the perturbation theory resolves
+        assert ok.sum() >= min(8, nn), k    # the leading pairs at least
+        assert np.all(du[ok] <= tol[ok]) and np.all(dv[ok] <= tol[ok]), (k, float((du / tol).max()))
+
+
+@pytest.mark.parametrize("dt,shift", [(np.float64, 600), (np.float64, -600), (np.float32, 80),
+                                      (np.float32, -80)])
+def test_rect_entries_beyond_the_squares_range(orc, dt, shift):
+    """Entries whose squares overflow or underflow: the factorization scales the matrix by
+    a power of two first (oracle and device alike), so the pivots, R and the whole SVD are
+    those of the unscaled matrix scaled back."""
+    from paper_2407_13116_amd import sweep as sw
+
+    mats = [np.ldexp(x, shift).astype(dt) for x in _batch(dt, seed=7, shapes=SHAPES[:6])]
+    for k, (G, (Ag, tg, pg, Rg)) in enumerate(zip(mats, _qrcp_gpu(mats, dt))):
+        mm, nn = G.shape
+        Ao, to, po, Ro = orc.qrcp(G)
+        assert np.all(np.isfinite(Rg)) and np.array_equal(pg, po), k
+        tol = 16 * mm * _eps(dt) * float(np.linalg.norm(np.ldexp(G.astype(np.float64), -shift)))
+        assert np.abs(np.ldexp(Rg.astype(np.float64) - Ro, -shift)).max() <= tol, k
+    res, sweeps = sw.svd_rect(mats)
+    assert np.all(sweeps > 0)
+    for G, (U, s, V) in zip(mats, res):
+        Gd = np.ldexp(G.astype(np.float64), -shift)
+        ref = np.linalg.svd(Gd, compute_uv=False)
+        sd = np.ldexp(s.astype(np.float64), -shift)
+        assert np.abs(sd - ref).max() <= 40 * G.shape[0] * _eps(dt) * ref[0]

@@ -72,3 +72,26 @@ def test_qrcp_ties_pick_the_first_column(orc, dt):
     assert perm[0] == P2[0]
     assert perm[0] == 1
 
+
+
+@pytest.mark.parametrize("dtype,shift", [(np.float64, 700), (np.float64, -700),
+                                         (np.float32, 90), (np.float32, -90)])
+def test_qrcp_scaled_inputs(orc, dtype, shift):
+    """Entries whose squares leave the normal range: the factorization of G 2^shift has
+    the pivots of G's, R = 2^shift R(G) bit for bit (the scaling is exact), the same
+    reflectors and tau, and agrees with LAPACK."""
+    rng = np.random.default_rng(31)
+    G = (rng.standard_normal((40, 12)) * np.exp2(rng.integers(-3, 4, 12))).astype(dtype)
+    Gs = np.ldexp(G, shift).astype(dtype)
+    A0, t0, p0, R0 = orc.qrcp(G)
+    A1, t1, p1, R1 = orc.qrcp(Gs)
+    assert np.all(np.isfinite(R1)) and np.array_equal(p0, p1)
+    assert np.array_equal(R1, np.ldexp(R0, shift).astype(dtype))
+    assert np.array_equal(np.tril(A1, -1), np.tril(A0, -1)) and np.array_equal(t1, t0)
+    if dtype == np.float64:
+        import scipy.linalg as sla
+
+        Rl, P = sla.qr(Gs, mode="r", pivoting=True)
+        assert np.array_equal(P, p1)
+        scale = np.abs(Rl).max()
+        assert np.abs(np.abs(np.diag(R1[:12, :12])) - np.abs(np.diag(Rl[:12, :12]))).max() <= 1e-13 * scale
