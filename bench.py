@@ -44,6 +44,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_13116_amd", "csrc", f)
                   for f in ("ksvd2_device.hpp", "ksvd2_kernels.hip", "abi_common.hpp")]
 BYTES_FWD = {np.float64: 92, np.float32: 52}      # algorithmic bytes per matrix (in + out)
 BYTES_FWDBWD = {np.float64: 112 + 192, np.float32: 56 + 96}
+BYTES_BWD = {np.float64: 192, np.float32: 96}     # backward alone ([B,2,2] layout)
 
 
 def parse():
@@ -84,42 +85,47 @@ def settle(fn, seconds=SETTLE_S):
     return calls
 
 
-def timed_loop(fn, steps, warmup):
+def timed_loop(fn, steps, warmup, per_launch=None):
     """Settle the clock, do `warmup` untimed calls, then time exactly `steps` calls: wall
     clock between two synchronisations, and HIP events recorded on the launch stream
-    around the same region."""
+    around the same region.  With a list as `per_launch`, an event is also recorded
+    between consecutive calls and the durations of the timed calls (ms) are appended."""
     import torch
 
     settle(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(steps):
+    evs[0].record()
+    for i in range(steps):
         fn()
-    ev1.record()
+        if per_launch is not None or i == steps - 1:
+            evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall / steps * 1e3, ev0.elapsed_time(ev1) / steps
+    if per_launch is not None:
+        per_launch.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    return wall / steps * 1e3, evs[0].elapsed_time(evs[steps]) / steps
 
 
-def fwd_case(dtype, steps, warmup, fast=False):
+def fwd_case(dtype, steps, warmup, fast=False, per_launch=None):
     import torch
 
     from paper_2407_13116_amd import api, inputs
 
-    g = inputs.forward_sweep(dtype)
+    g, lab = inputs.forward_sweep(dtype, with_labels=True)
     d = [torch.from_numpy(x).cuda() for x in g]
     out = api.ksvd2_batch(*d, plain=False, fast=fast)
     torch.cuda.synchronize()
     ms_wall, ms_ev = timed_loop(lambda: api.ksvd2_batch(*d, plain=False, out=out, fast=fast),
-                                steps, warmup)
+                                steps, warmup, per_launch)
     B = g[0].size
     res = {"B": B, "ms_wall": ms_wall, "ms_kernel": ms_ev, "rate": B / (ms_wall * 1e-3)}
     res["GBs"] = B * BYTES_FWD[dtype] / (ms_ev * 1e-3) / 1e9
     host = {k: v.cpu().numpy() for k, v in out.items()}
+    host["labels"] = lab
     del d, out
     torch.cuda.empty_cache()
     return res, g, host
@@ -171,16 +177,20 @@ def rect_case(dtype):
 
 
 def fwdbwd_case(dtype, steps, warmup):
+    """Forward and backward of the differentiable workload through the
+    torch.autograd.Function (api.svd2x2): G [B,2,2] -> (U, S, V), then torch.autograd.grad
+    with the upstream gradients (dU, dS, dV), i.e. the adjoint kernel."""
     import torch
 
     from paper_2407_13116_amd import api, inputs
 
     G, dS, dU, dV, _ = inputs.diff_batch(dtype)
     t = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (G, dS, dU, dV)]
+    t[0].requires_grad_(True)
 
     def step():
-        U, S, V = api.svd2x2_raw(t[0])
-        return api.svd2x2_backward(U, S, V, t[1], t[2], t[3])
+        U, S, V = api.svd2x2(t[0])
+        return torch.autograd.grad((U, S, V), t[0], (t[2], t[1], t[3]))[0]
 
     ms_wall, ms_ev = timed_loop(step, max(steps // 2, 5), warmup)
     B = G.shape[0]
@@ -191,48 +201,173 @@ def fwdbwd_case(dtype, steps, warmup):
     return out
 
 
-def sigma2_error_sample(g, host, dtype, n=1500):
-    """max relative error of sigma_2 (units of eps) on a sample, by input class, against
-    a high-precision closed form (exact rationals + mpmath)."""
-    from fractions import Fraction
+# ---------------------------------------------------------------------------
+# sigma reference for the whole batch: double-word (about 104-bit) arithmetic,
+# vectorised over numpy arrays, with exponents kept apart so that no product
+# over- or underflows.  sigma_1 = (h1 + h2) / 2 with h1 = hypot(g11 + g22, g21 -
+# g12) and h2 = hypot(g11 - g22, g12 + g21) (h1^2 = F + 2 det, h2^2 = F - 2 det
+# with F = ||G||_F^2, so h1 + h2 = 2 sigma_1 for either sign of det, a sum of
+# non-negative terms), sigma_2 = |det| / sigma_1 with det from exact products.
+# Validated against exact rationals and mpmath in the CPU tests.
 
-    import mpmath
+def _dw_two_sum(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
 
+
+def _dw_split(a):
+    c = 134217729.0 * a          # 2^27 + 1 (operands are at most a few units here)
+    hi = c - (c - a)
+    return hi, a - hi
+
+
+def _dw_two_prod(a, b):
+    p = a * b
+    ah, al = _dw_split(a)
+    bh, bl = _dw_split(b)
+    return p, ((ah * bh - p) + ah * bl + al * bh) + al * bl
+
+
+def _dw_add(xh, xl, yh, yl):
+    """AccurateDWPlusDW (Joldes, Muller, Popescu 2017, Algorithm 6): relative error
+    below 3 2^-106 of the exact sum, also under cancellation."""
+    sh, sl = _dw_two_sum(xh, yh)
+    th, tl = _dw_two_sum(xl, yl)
+    c = sl + th
+    vh, vl = _dw_two_sum(sh, c)       # |sh| >= |c| may fail under cancellation: TwoSum
+    w = tl + vl
+    return _dw_two_sum(vh, w)
+
+
+def _dw_mul(xh, xl, yh, yl):
+    ph, pl = _dw_two_prod(xh, yh)
+    pl = pl + (xh * yl + xl * yh)
+    return _dw_two_sum(ph, pl)
+
+
+def _dw_div(xh, xl, yh, yl):
+    q = xh / yh
+    ph, pl = _dw_two_prod(q, yh)
+    r = ((xh - ph) - pl + xl - q * yl) / yh
+    return _dw_two_sum(q, r)
+
+
+def _dw_sqrt(xh, xl):
+    with np.errstate(invalid="ignore", divide="ignore"):
+        y = np.sqrt(xh)
+        ph, pl = _dw_two_prod(y, y)
+        r = ((xh - ph) - pl + xl) / (2.0 * y)
+        r = np.where(y > 0, r, 0.0)
+    return _dw_two_sum(y, r)
+
+
+def sigma_ref(g11, g21, g12, g22):
+    """Singular values of the 2x2 matrices [g11 g12; g21 g22] (float64 or float32
+    planes) to about 2^-100 relative: (m1h, m1l, E1, m2h, m2l, E2) with sigma_i =
+    (mih + mil) 2^Ei, or mih = mil = 0 for sigma_i = 0."""
+    a, c, b, d = (np.asarray(x, np.float64) for x in (g11, g21, g12, g22))
+    ax = np.maximum(np.maximum(np.abs(a), np.abs(b)), np.maximum(np.abs(c), np.abs(d)))
+    _, emax = np.frexp(ax)
+    sa, sb, sc, sd = (np.ldexp(x, -emax) for x in (a, b, c, d))   # exact but for tiny parts
+    zero = np.zeros_like(sa)
+
+    def hyp(xh, xl, yh, yl):
+        x2 = _dw_mul(xh, xl, xh, xl)
+        y2 = _dw_mul(yh, yl, yh, yl)
+        return _dw_sqrt(*_dw_add(*x2, *y2))
+
+    h1 = hyp(*_dw_two_sum(sa, sd), *_dw_two_sum(sc, -sb))
+    h2 = hyp(*_dw_two_sum(sa, -sd), *_dw_two_sum(sb, sc))
+    s1h, s1l = _dw_add(*h1, *h2)
+    s1h, s1l = s1h * 0.5, s1l * 0.5
+    # det = g11 g22 - g12 g21 from the exact products of the mantissas
+    ma, ea = np.frexp(a)
+    mb, eb = np.frexp(b)
+    mc, ec = np.frexp(c)
+    md, ed = np.frexp(d)
+    p1h, p1l = _dw_two_prod(ma, md)
+    p2h, p2l = _dw_two_prod(mb, mc)
+    E1 = np.where(p1h != 0, ea + ed, -(1 << 30))
+    E2 = np.where(p2h != 0, eb + ec, -(1 << 30))
+    E = np.maximum(E1, E2)
+    sh1, sh2 = np.maximum(E1 - E, -1100), np.maximum(E2 - E, -1100)
+    dh, dl = _dw_add(np.ldexp(p1h, sh1), np.ldexp(p1l, sh1),
+                     -np.ldexp(p2h, sh2), -np.ldexp(p2l, sh2))
+    neg = dh < 0
+    dh, dl = np.where(neg, -dh, dh), np.where(neg, -dl, dl)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        qh, ql = _dw_div(dh, dl, s1h, s1l)
+    ok = (s1h > 0) & (dh > 0)
+    qh, ql = np.where(ok, qh, 0.0), np.where(ok, ql, 0.0)
+    # normalise: sigma_1 = s1 2^emax, sigma_2 = q 2^(E - emax)
+    _, f1 = np.frexp(s1h)
+    _, f2 = np.frexp(qh)
+    m1h, m1l = np.ldexp(s1h, -f1), np.ldexp(s1l, -f1)
+    m2h, m2l = np.ldexp(qh, -f2), np.ldexp(ql, -f2)
+    return (m1h, m1l, np.where(s1h > 0, emax + f1, 0), m2h, m2l,
+            np.where(ok, E - emax + f2, 0))
+
+
+def rel_err_ulps(f, e, mh, ml, me, eps):
+    """|f 2^e - sigma| / sigma / eps for sigma = (mh + ml) 2^me (0/0 -> 0, x/0 -> inf)."""
+    with np.errstate(invalid="ignore", over="ignore", divide="ignore"):
+        t = np.ldexp(np.asarray(f, np.float64), np.clip(e - me, -1100, 1100))
+        r = np.abs((t - mh) - ml) / mh / eps
+    r = np.where(mh == 0, np.where(np.asarray(f) == 0, 0.0, np.inf), r)
+    return r
+
+
+ERR_EDGES = (1.0, 2.0, 4.0, 8.0, 16.0, 2.0 ** 10, 2.0 ** 26)
+
+
+def sigma_error_histogram(g, host, labels, dtype, chunk=1 << 21):
+    """Relative errors of sigma_1 and sigma_2 of the whole batch against sigma_ref, in
+    units of eps, by family (general, upper triangular, near-singular): maximum and
+    counts per bucket (<= 1, 2, 4, 8, 16, 2^10, 2^26 eps, more)."""
     eps = 2.0 ** (-53 if dtype == np.float64 else -24)
+    names = ("general", "upper_triangular", "near_singular")
+    buckets = [f"<={x:g}" for x in ERR_EDGES] + [f">{ERR_EDGES[-1]:g}"]
+    out = {s: {n: {"max": 0.0, "hist": dict.fromkeys(buckets, 0)} for n in names}
+           for s in ("sigma1", "sigma2")}
     B = g[0].size
-    idx = np.random.default_rng(5).choice(B, n, replace=False)
-    worst = {"triangular": 0.0, "general": 0.0}
-    # general inputs over the full exponent range lose sigma_2 on some matrices (the
-    # paper's Sect. 4 / Fig. 4): report how many stay within 8 eps, 2^10 eps, 2^26 eps
-    edges = (8.0, 2.0 ** 10, 2.0 ** 26)
-    hist = {"<=8": 0, "<=2^10": 0, "<=2^26": 0, ">2^26": 0}
-    with mpmath.workprec(320):
-        for i in idx:
-            a, b, c, d = (Fraction(float(p[i])) for p in g)
-            F = a * a + b * b + c * c + d * d
-            D = a * d - c * b
-            if F == 0:
-                continue
-            disc = F * F - 4 * D * D
-            s1 = mpmath.sqrt((mpmath.mpf(F.numerator) / F.denominator
-                              + mpmath.sqrt(mpmath.mpf(disc.numerator) / disc.denominator)) / 2)
-            s2 = abs(mpmath.mpf(D.numerator) / D.denominator) / s1
-            got = mpmath.ldexp(mpmath.mpf(float(host["f2"][i])), int(host["e2"][i]))
-            re = 0.0 if s2 == 0 and got == 0 else float(abs(got - s2) / s2 / eps) if s2 else float("inf")
-            key = "triangular" if b == 0 else "general"
-            worst[key] = max(worst[key], re)
-            if key == "general":
-                k = next((j for j, e in enumerate(edges) if re <= e), len(edges))
-                hist[list(hist)[k]] += 1
-    worst["general_histogram"] = hist
-    return worst
+
+    def errs(o):
+        sl = slice(o, min(B, o + chunk))
+        m1h, m1l, E1, m2h, m2l, E2 = sigma_ref(*(p[sl] for p in g))
+        return (sl, rel_err_ulps(host["f1"][sl], host["e1"][sl], m1h, m1l, E1, eps),
+                rel_err_ulps(host["f2"][sl], host["e2"][sl], m2h, m2l, E2, eps))
+
+    # numpy releases the interpreter lock in its array operations: chunks in threads
+    from concurrent.futures import ThreadPoolExecutor
+
+    workers = max(1, min(8, (os.cpu_count() or 1) // 2))
+    with ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(errs, range(0, B, chunk)))
+    for sl, r1, r2 in parts:
+        lab = labels[sl]
+        for key, r in (("sigma1", r1), ("sigma2", r2)):
+            idx = np.searchsorted(np.asarray(ERR_EDGES), r, side="left")
+            for li, n in enumerate(names):
+                sel = lab == li
+                if not np.any(sel):
+                    continue
+                ent = out[key][n]
+                ent["max"] = max(ent["max"], float(r[sel].max()))
+                cnt = np.bincount(idx[sel], minlength=len(buckets))
+                for bi, bname in enumerate(buckets):
+                    ent["hist"][bname] += int(cnt[bi])
+    return out
 
 
-def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=60, tune=True):
+def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=60, tune=True,
+               traffic_profile=None):
     """Time one converged solve of a batch of square matrices per execution mode, with the
-    modified modulus ordering, and once with the round-robin ordering (the
-    matrices are re-uploaded untimed before every run).  Effective bytes: every step reads
-    and writes G, U and V once, 6 n^2 w per matrix per step."""
+    modified modulus ordering, then once (persistent mode) with the round-robin and once
+    with the dynamic ordering (the matrices are re-uploaded untimed before every run).
+    ms_per_sweep is the solve's time over its largest sweep count (the batch finishes with
+    its slowest matrix); with a committed counter summary of one sweep of this batch
+    (traffic_profile), the HBM rate that sweep moves at this speed."""
     import torch
 
     from paper_2407_13116_amd import autotune
@@ -242,64 +377,81 @@ def sweep_case(mats, dtype, modes=("plain", "persistent", "graph"), max_sweeps=6
     chosen = autotune.tune(mats, tdt) if tune else {}
     p = sw.Packed(mats, dtype=dtype)
     G0 = p.G.clone()
-    w = np.dtype(dtype).itemsize
-    res = {"tuned_blocks": {str(k): v for k, v in chosen.items()}}
+    # the schedule the autotuner picked per order bucket (0: n <= 64, 1: <= 128, 2: <= 256,
+    # 3: <= 512): workgroup size, two steps per G pass, in-place pass, U/V chunk, tile rows
+    res = {"tuned_knobs": {str(k): v for k, v in chosen.items()}}
     ws = None
-    for mode in modes:
-        times = []
-        for rep in range(2 if mode == "graph" else 1):   # graph: capture, then replay
-            p.G.copy_(G0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode=mode,
-                                     workspace=ws, sort=True)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            ws = out["workspace"]
-        sweeps = np.abs(out["sweeps"].cpu().numpy()).astype(np.int64)
-        n = p.n.astype(np.int64)
-        bytes_ = float(np.sum(sweeps * (n - 1) * 6 * n * n * w))
-        res[mode] = {"seconds": times[-1], "sweeps_mean": float(sweeps.mean()),
-                     "sweeps_max": int(sweeps.max()),
-                     "converged": bool(np.all(out["sweeps"].cpu().numpy() > 0)),
-                     "eff_GBs": bytes_ / times[-1] / 1e9,
-                     "matrices_per_s": len(mats) / times[-1]}
-        log(f"[bench] sweep {mode}: {res[mode]}")
-    if "persistent" in modes:
-        # the same solve with the round-robin ordering (persistent mode)
+
+    def solve(mode, ordering="modulus"):
+        nonlocal ws
         p.G.copy_(G0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        o2 = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode="persistent",
-                                workspace=ws, sort=True, ordering="round-robin")
+        out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode=mode,
+                                 workspace=ws, sort=True, ordering=ordering)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        s2 = np.abs(o2["sweeps"].cpu().numpy()).astype(np.int64)
-        res["persistent_round_robin_ordering"] = {
-            "seconds": t, "sweeps_mean": float(s2.mean()), "sweeps_max": int(s2.max()),
-            "converged": bool(np.all(o2["sweeps"].cpu().numpy() > 0))}
-        log(f"[bench] sweep persistent, round-robin: {res['persistent_round_robin_ordering']}")
-        p.G.copy_(G0)
-        out = sw.kog_sweep_batch(p, max_sweeps=max_sweeps, tol_factor=1.0, mode="persistent",
-                                 workspace=ws, sort=True)
+        ws = out["workspace"]
+        s = out["sweeps"].cpu().numpy()
+        sa = np.abs(s)
+        return out, {"seconds": t, "sweeps_mean": float(sa.mean()), "sweeps_max": int(sa.max()),
+                     "converged": bool(np.all(s > 0)), "matrices_per_s": len(mats) / t,
+                     "ms_per_sweep": t / max(int(sa.max()), 1) * 1e3}
+
+    for mode in modes:
+        if mode == "graph":
+            solve(mode)                       # capture, then the timed replay
+        out, res[mode] = solve(mode)
+        log(f"[bench] sweep {mode}: {res[mode]}")
+    if traffic_profile and "persistent" in modes:
+        tb = measured_sweep_traffic(traffic_profile)
+        if tb is not None:
+            r = res["persistent"]
+            gbs = tb / (r["ms_per_sweep"] * 1e-3) / 1e9
+            r["hbm"] = {"measured_bytes_per_sweep": tb, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                        "source": os.path.relpath(traffic_profile, ROOT)}
+    if "persistent" in modes:
+        for name, ordering in (("persistent_round_robin_ordering", "round-robin"),
+                               ("persistent_dynamic_ordering", "dynamic")):
+            _, res[name] = solve("persistent", ordering)
+            log(f"[bench] sweep persistent, {ordering}: {res[name]}")
+        out, _ = solve("persistent")
     # the sigma gradient dG = U diag(dsigma) V^T of the last solve: 2 n^3 flops per matrix
     ds = torch.from_numpy(np.random.default_rng(17).standard_normal(int(p.n.sum())).astype(dtype)).cuda()
     fl = float(np.sum(2.0 * p.n.astype(np.float64) ** 3))
     ms_w, ms_ev = timed_loop(lambda: sw.sigma_grad(p, out["U"], out["V"], ds, workspace=ws), 10, 2)
+    peak = FP64_VECTOR_TFLOPS if dtype == np.float64 else 157.3
     res["sigma_grad"] = {"ms": ms_ev, "TFLOPs": fl / (ms_ev * 1e-3) / 1e12,
-                         "frac_fp64_vector_peak": fl / (ms_ev * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS
-                         if dtype == np.float64 else None}
+                         "frac_mfma_peak": fl / (ms_ev * 1e-3) / 1e12 / peak,
+                         "peak_TFLOPs": peak}
     log(f"[bench] sigma_grad: {res['sigma_grad']}")
     del p, G0
     torch.cuda.empty_cache()
     return res
 
 
-def kernel_source_hash():
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2407_13116_amd", "csrc", f)
+                 for f in ("kog_sweep.hip", "ksvd2_device.hpp", "abi_common.hpp")]
+SWEEP_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pmc_traffic_k_sw_persistent_f64_256x256.md")
+
+
+def measured_sweep_traffic(path):
+    """HBM bytes of one persistent sweep from a committed counter summary taken on the
+    same kernel sources (else None)."""
+    kv = _profile_values(path)
+    try:
+        if kv["kernel_source_sha256"] != kernel_source_hash(SWEEP_SOURCES):
+            return None
+        return float(kv["bytes_per_sweep"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_source_hash(files=None):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -509,7 +661,7 @@ def profile_workload(w, reps):
                  *(np.ascontiguousarray(dU[:, i, j]) for j in range(2) for i in range(2)),
                  *(np.ascontiguousarray(dV[:, i, j]) for j in range(2) for i in range(2)))
         for _ in range(reps + 1):
-            api.ksvd2_backward_soa(out, up[0], up[1], up[2:6], up[6:10])
+            api.ksvd2_backward_soa(out, up[0], up[1], torch.stack(up[2:6]), torch.stack(up[6:10]))
     elif w in ("cplx128", "cplx64"):
         G = torch.from_numpy(inputs.complex_batch(np.complex128 if w == "cplx128"
                                                   else np.complex64)).cuda()
@@ -555,7 +707,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     log("[bench] FP64 forward, 2^24 matrices")
-    f64, g64, h64 = fwd_case(np.float64, args.steps, args.warmup)
+    launches = []
+    f64, g64, h64 = fwd_case(np.float64, args.steps, args.warmup, per_launch=launches)
     log(f"[bench] f64: {f64}")
     res = {
         "metric": METRIC,
@@ -576,6 +729,8 @@ def main():
                    "batch": f64["B"]},
         "roofline": roofline(f64),
     }
+    # HIP-event duration of each timed launch of the headline kernel (ms, launch order)
+    res["roofline"]["timed_launch_ms"] = [round(x, 5) for x in launches]
     extra = {}
     if not args.no_extra:
         log("[bench] FP32 forward, 2^24 matrices")
@@ -590,7 +745,7 @@ def main():
             ff, gf, hf = fwd_case(dt, args.steps, args.warmup, fast=True)
             extra[name] = {"rate": ff["rate"], "ms_per_launch": ff["ms_kernel"],
                            "GBs": ff["GBs"], "hbm_frac": ff["GBs"] / HBM_PEAK_GBS}
-            fast_err[name] = sigma2_error_sample(gf, hf, dt)
+            fast_err[name] = sigma_error_histogram(gf, hf, hf["labels"], dt)
             del gf, hf
         if not args.no_cpu:
             extra["fwd_fast_f64"]["cpu_baseline"] = oracle_beside("fast")
@@ -602,12 +757,20 @@ def main():
         for dt, name in ((np.float64, "fwdbwd_f64"), (np.float32, "fwdbwd_f32")):
             log(f"[bench] {name}, 2^22 matrices")
             fb = fwdbwd_case(dt, args.steps, args.warmup)
+            # binding bound of the pair: the forward at its algorithmic VALU work, the
+            # backward at its algorithmic HBM bytes (it is bound by streaming)
+            t_fwd = ALG_VALU_SLOTS[dt] * fb["B"] / (VALU_LANE_PEAK_T * 1e12)
+            t_bwd = BYTES_BWD[dt] * fb["B"] / (HBM_PEAK_GBS * 1e9)
             extra[name] = {"rate": fb["rate"], "ms_per_step": fb["ms_kernel"], "GBs": fb["GBs"],
-                           "hbm_frac": fb["GBs"] / HBM_PEAK_GBS}
+                           "hbm_frac": fb["GBs"] / HBM_PEAK_GBS,
+                           "bound_ms": (t_fwd + t_bwd) * 1e3,
+                           "frac_of_bound": (t_fwd + t_bwd) * 1e3 / fb["ms_kernel"],
+                           "path": "torch.autograd.Function (api.svd2x2) + torch.autograd.grad"}
         from paper_2407_13116_amd import inputs as _inp
 
         log("[bench] sweep: 256 x (n=256) FP64")
-        extra["sweep_uniform_f64"] = sweep_case(_inp.sweep_uniform(), np.float64)
+        extra["sweep_uniform_f64"] = sweep_case(_inp.sweep_uniform(), np.float64,
+                                                traffic_profile=SWEEP_TRAFFIC_PROFILE)
         for dt, name in ((np.float64, "sweep_uneven_f64"), (np.float32, "sweep_uneven_f32")):
             log(f"[bench] sweep: 1,000 uneven orders, {name}")
             extra[name] = sweep_case(_inp.sweep_uneven(dtype=dt), dt)
@@ -616,13 +779,15 @@ def main():
         if not args.no_cpu:
             extra["rect_f64"]["cpu_baseline"] = oracle_beside("rect", seconds=5.0)
         log(f"[bench] rect: {extra['rect_f64']}")
-        log("[bench] sigma_2 accuracy sample")
-        extra["max_rel_err_sigma2_ulp"] = {"f64": sigma2_error_sample(g64, h64, np.float64),
-                                           "f32": sigma2_error_sample(g32, h32, np.float32),
-                                           "unit": "eps (2^-53 / 2^-24)",
-                                           "sample": "1,500 matrices per precision"}
-        extra["max_rel_err_sigma2_ulp_fast"] = dict(fast_err, unit="eps (2^-53 / 2^-24)",
-                                                    sample="1,500 matrices per precision")
+        log("[bench] sigma accuracy: the whole 2^24 batches against the double-word reference")
+        ref = ("every matrix of the 2^24 batch against a double-word (about 2^-100) "
+               "reference of sigma_1, sigma_2 (bench.sigma_ref)")
+        extra["max_rel_err_sigma_ulp"] = {
+            "f64": sigma_error_histogram(g64, h64, h64["labels"], np.float64),
+            "f32": sigma_error_histogram(g32, h32, h32["labels"], np.float32),
+            "unit": "eps (2^-53 / 2^-24)", "sample": ref}
+        extra["max_rel_err_sigma_ulp_fast"] = dict(fast_err, unit="eps (2^-53 / 2^-24)",
+                                                   sample=ref)
     res["extra"] = extra
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")

@@ -91,9 +91,11 @@ def forward_small(seed: int = 1, B: int = 65536):
     return soa_from_mats(G)
 
 
-def forward_sweep(dtype=np.float64, seed=None, B: int = 1 << 24):
+def forward_sweep(dtype=np.float64, seed=None, B: int = 1 << 24, with_labels: bool = False):
     """Config: accuracy/throughput sweep.  float64: e in [-1000,1000] (seed 2);
-    float32: e in [-120,120] (seed 3).  10% upper triangular, 1% near-singular."""
+    float32: e in [-120,120] (seed 3).  10% upper triangular, 1% near-singular.
+    with_labels: also return the family of each matrix (0 general, 1 upper
+    triangular, 2 near-singular)."""
     f64 = np.dtype(dtype) == np.float64
     if seed is None:
         seed = 2 if f64 else 3
@@ -111,6 +113,11 @@ def forward_sweep(dtype=np.float64, seed=None, B: int = 1 << 24):
         r1 = G[ni, 0, j]
         # RN(g (1 + delta)): g*delta is exact (a power-of-two scaling), one rounding in the sum
         G[ni, 1, j] = r1 + r1 * delta
+    if with_labels:
+        lab = np.zeros(B, np.int8)
+        lab[tri] = 1
+        lab[near] = 2
+        return soa_from_mats(G), lab
     return soa_from_mats(G)
 
 
