@@ -208,22 +208,36 @@ __device__ __attribute__((always_inline)) inline double hypot_cr(double x, doubl
 
 // hypot(t, 1) for 0 <= t <= 1 (the secants of angles up to pi/4): the larger
 // argument is exactly 1, so no scaling is needed; below 2^-30 the result is 1.
+// S = 1 + t^2 lies in [1, 2], so the root lies in [1, sqrt 2]: sqrt_dw_cr's
+// tests for roots of 2 and above are dropped (the same candidate, acceptance
+// test and fallback for this range).
 __device__ __attribute__((always_inline)) inline double hypot1_le1(double t) {
   if (t < 0x1p-30) return 1.0;
   double q, qe;
   two_prod(t, t, q, qe);
   double sh = 1.0 + q;
   double sl = (q - (sh - 1.0)) + qe;
-  return sqrt_dw_cr(sh, sl, 1.0, 0.0, q, qe);
+  double s = sh + sl;
+  double r0 = __builtin_amdgcn_rsq(s);
+  double g = s * r0, h = 0.5 * r0;
+  double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, sh) + sl;
+  double y = fma(d, h, g);
+  double rho = fma(-y, y, sh) + sl;
+  constexpr double c1 = 0x1p-52 * (1.0 - 0x1p-40);
+  if (fabs(rho) < y * c1) return y;
+  return hypot_resolve(1.0, 0.0, q, qe, y, 0x1p-52, y == 1.0 ? 0x1p-53 : 0x1p-52);
 }
 
 // ---------------------------------------------------------------------------
-// Correctly rounded hypot, binary32: evaluate in binary64 (squares exact), round
-// to binary32, and settle the one float midpoint that can separate the binary64
+// Correctly rounded hypot, binary32, the general route: evaluate in binary64
+// (squares exact), round to binary32, and settle the one float midpoint that can separate the binary64
 // value from the exact one by an exact sign test of S - m^2 (hi^2 - m^2 is
 // exact in binary64, so only the addition of lo^2 rounds, which keeps the sign).
 // ---------------------------------------------------------------------------
-__device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y) {
+__device__ __attribute__((noinline)) float hypot_cr32_slow(float x, float y) {
   double a = fabs((double)x), b = fabs((double)y);
   double hi = fmax(a, b), lo = fmin(a, b);
   if (isinf(hi)) return (float)hi;
@@ -282,8 +296,59 @@ __device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y
   return f;
 }
 
+
+// ---------------------------------------------------------------------------
+// Correctly rounded hypot, binary32, in binary32 arithmetic.  With hi >= lo > 0
+// and hi = A 2^e (A in [1, 2)), an exponent gap above 13 leaves hi (lo^2 <
+// 2^-26 hi^2 moves the root by less than a quarter ulp); otherwise S = A^2 + B^2
+// (B = lo 2^-e, exact) is formed as a double-float sh + sl from exact squares
+// (error below 2^-46 S), a reciprocal square root estimate (about 2^-23) and one
+// Newton step on sh + sl give the candidate y, and y is the correctly rounded root when
+// its residual rho = S - y^2 (one fma, exact by Sterbenz, plus sl) satisfies
+// |rho| < y ulp(y) (1 - 2^-16): then |sqrt(S) - y| = |rho| / (sqrt(S) + y) stays
+// below ulp(y)/2 with a margin of 2^-40 y^2 over every rounding error above.
+// Below y = 2 the gap to the next smaller float is half as wide, so a negative
+// residual there is left to the general route, as are uncertified lanes (about
+// 2^-16 of them), results that could be subnormal (hi below 2^-126) and the
+// overflow edge (handled by the final scaling, see below).
+// ---------------------------------------------------------------------------
+__device__ __attribute__((always_inline)) inline float hypot_cr(float x, float y) {
+  const float a = fabsf(x), b = fabsf(y);
+  const float hi = fmaxf(a, b), lo = fminf(a, b);
+  if (lo == 0.0f || isinf(hi)) return hi;
+  const int eh = ilog2(hi), el = ilog2(lo);
+  if (eh - el > 13) return hi;
+  if (eh < -126) return hypot_cr32_slow(x, y);
+  const float A = ldexpf(hi, -eh), B = ldexpf(lo, -eh);  // exact
+  const float p = A * A, pe = fmaf(A, A, -p), q = B * B, qe = fmaf(B, B, -q);
+  const float sh = p + q;                                  // p >= q: Fast2Sum
+  const float sl = (q - (sh - p)) + (pe + qe);
+  const float r0 = __builtin_amdgcn_rsqf(sh);
+  const float g = sh * r0, h = 0.5f * r0;
+  const float d = fmaf(-g, g, sh) + sl;
+  const float yv = fmaf(d, h, g);
+  const float rho = fmaf(-yv, yv, sh) + sl;
+  constexpr float c1 = 0x1p-23f * (1.0f - 0x1p-16f), c2 = 0x1p-22f * (1.0f - 0x1p-16f);
+  const float thr = yv * (yv >= 2.0f ? c2 : c1);
+  if (fabsf(rho) < thr && !(yv == 2.0f && rho < 0.0f))
+    return ldexpf(yv, eh);  // y 2^e: exact, or +inf when the root rounds to 2^128
+  return hypot_cr32_slow(x, y);
+}
+
+// hypot(t, 1) for 0 <= t <= 1: A = 1, no scaling; below 2^-13 the result is 1
 __device__ __attribute__((always_inline)) inline float hypot1_le1(float t) {
-  return hypot_cr(t, 1.0f);
+  if (t < 0x1p-13f) return 1.0f;
+  const float q = t * t, qe = fmaf(t, t, -q);
+  const float sh = 1.0f + q;
+  const float sl = (q - (sh - 1.0f)) + qe;
+  const float r0 = __builtin_amdgcn_rsqf(sh);
+  const float g = sh * r0, h = 0.5f * r0;
+  const float d = fmaf(-g, g, sh) + sl;
+  const float yv = fmaf(d, h, g);
+  const float rho = fmaf(-yv, yv, sh) + sl;
+  constexpr float c1 = 0x1p-23f * (1.0f - 0x1p-16f);
+  if (fabsf(rho) < yv * c1) return yv;  // y in [1, sqrt 2]
+  return hypot_cr32_slow(t, 1.0f);
 }
 
 // ---------------------------------------------------------------------------

@@ -177,3 +177,46 @@ def test_batch_past_one_launch(orc, dtype):
     del planes, out
     torch.cuda.empty_cache()
     assert_bitwise(got, orc.ksvd2(*g), label=f"2^28+4099 {dtype.__name__}")
+
+
+def test_device_hypot_binary32_dense(orc):
+    """The binary32 hypot (binary32 arithmetic with a certified candidate, the binary64
+    route for the rest) bit for bit against the oracle on 2^24 random pairs across
+    exponent gaps 0..20 (the gap exit is at 13), on 2^20 pairs built next to rounding
+    midpoints (x random, y = RN(sqrt(m^2 - x^2)) and its neighbours for a midpoint m),
+    next to the overflow threshold, around roots of 2 after scaling, and with
+    subnormal larger arguments."""
+    import torch
+
+    from paper_2407_13116_amd import api
+
+    rng = np.random.default_rng(23)
+    f = np.finfo(np.float32)
+    n = 1 << 24
+    e1 = rng.integers(-125, 127, n)
+    x = np.ldexp(1 + rng.random(n), e1).astype(np.float32)
+    y = np.ldexp(1 + rng.random(n), e1 - rng.integers(0, 21, n)).astype(np.float32)
+    # next to midpoints: m = float + half an ulp (in binary64, exact), x below m
+    k = 1 << 18
+    mant = (1 + rng.integers(0, 1 << 23, k) * 2.0 ** -23)
+    m = (mant + 2.0 ** -24) * np.ldexp(1.0, rng.integers(-100, 100, k))
+    xm = (m * rng.random(k)).astype(np.float32).astype(np.float64)
+    ym = np.sqrt(np.maximum(m * m - xm * xm, 0)).astype(np.float32)
+    ymm = [ym, np.nextafter(ym, np.float32(np.inf)), np.nextafter(ym, np.float32(0))]
+    xs = np.concatenate([xm.astype(np.float32)] * 3)
+    ys = np.concatenate(ymm)
+    # overflow edge and roots of 2 after scaling (A^2 + B^2 near 4)
+    big = np.array([f.max, np.nextafter(f.max, 0), 2.0 ** 127, 1.9 * 2.0 ** 127], np.float32)
+    xo = np.repeat(big, 256)
+    yo = (np.ldexp(rng.random(xo.size), 127 - rng.integers(0, 16, xo.size))).astype(np.float32)
+    t = (2 - rng.random(1 << 16) * 2.0 ** -10).astype(np.float32)          # A just below 2
+    xr = t
+    yr = (rng.random(t.size) * 2.0 ** -6).astype(np.float32)
+    sub = (rng.integers(1, 1 << 23, (2, 1 << 14)) * np.float64(f.smallest_subnormal)).astype(np.float32)
+    X = np.concatenate([x, xs, xo, xr, sub[0], -x[:4096]])
+    Y = np.concatenate([y, ys, yo, yr, sub[1], y[:4096]])
+    xd, yd = to_dev(X, Y)
+    got = api.hypot(xd, yd).cpu().numpy()
+    torch.cuda.synchronize()
+    want = orc.hypot(X, Y)
+    assert_bitwise({"h": got}, {"h": want}, label="binary32 hypot vs oracle")
