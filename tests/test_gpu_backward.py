@@ -9,6 +9,12 @@
   gauge-invariant loss for FP32 vs FP64 differences to 1e-3), near-degenerate matrices
   (the polar-factor loss, differences through a 300-bit SVD; FP32 uses tau = 2^-12),
   rank-deficient matrices (first singular triple);
+* not checked by finite differences: general upstream dU and dV on the near-degenerate
+  subset in FP32, and sigma_1 and sigma_2 weighted differently there.  With sigma1/sigma2 -
+  1 < 1e-6 the singular vectors, and any loss that tells the two triples apart, change by
+  eps/(sigma1 - sigma2) ~ 6% under binary32 rounding, so no finite difference resolves
+  them to 1e-3; the adjoint's arithmetic on those matrices is still checked against the
+  oracle adjoint within the derived bound (test_backward_kernel_vs_oracle);
 * the full 2^22 batch in both precisions: finite, and sampled outputs vs the oracle;
 * the kernels' 16-byte vector paths and their element-wise paths give the same bits.
 """
