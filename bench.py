@@ -622,6 +622,8 @@ PROFILE_WORKLOADS = """
                     and WRITE_SIZE should each read 1 GiB)
   sweep4            one persistent sweep of the 256 x (n=256) FP64 workload
   sweep4rr          the same with the round-robin ordering
+  sgrad64 / sgrad32 the sigma-gradient U diag(dsigma) V^T of the 256 x (n=256) sweep
+                    batch (FP64) or of the 1,000 uneven orders (FP32), after one sweep
 """
 
 
@@ -686,6 +688,17 @@ def profile_workload(w, reps):
         for _ in range(reps):
             sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="persistent",
                                ordering="round-robin" if w == "sweep4rr" else "modulus")
+    elif w in ("sgrad64", "sgrad32"):
+        from paper_2407_13116_amd import sweep as sw
+
+        dt = np.float64 if w == "sgrad64" else np.float32
+        p = sw.Packed(inputs.sweep_uniform() if w == "sgrad64" else inputs.sweep_uneven(dtype=dt),
+                      dtype=dt)
+        out = sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="persistent")
+        ds = torch.from_numpy(np.random.default_rng(17).standard_normal(int(p.n.sum()))
+                              .astype(dt)).cuda()
+        for _ in range(reps + 1):
+            sw.sigma_grad(p, out["U"], out["V"], ds, workspace=out["workspace"])
     else:
         print(f"unknown workload {w}; one of:{PROFILE_WORKLOADS}", file=sys.stderr)
         return 2

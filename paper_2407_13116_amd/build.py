@@ -3,7 +3,10 @@
 Floating-point flags matter for the method's bit-exactness: no contraction
 (every fused multiply-add is an explicit fma), correctly rounded binary32
 division and square root, binary32 denormals kept (gradual underflow), no
-fast-math, and no packed-FP32 instruction selection.
+fast-math, and no packed-FP32 instruction selection.  Matrix-core instructions
+take their accumulators in ordinary vector registers (the compiler otherwise
+copies them between the accumulator and vector register files on every trip
+of the sigma-gradient's loop); only the kernels that use them change.
 """
 from __future__ import annotations
 
@@ -23,6 +26,7 @@ FLAGS = [
     "-ffp-contract=off", "-fno-fast-math", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function",
 ]
 

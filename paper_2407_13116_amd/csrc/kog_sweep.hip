@@ -1417,15 +1417,17 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
 //
 // dG = U diag(dsigma) V^T per matrix (d sigma_i / dG = u_i v_i^T, summed with
 // weights dsigma_i): a dense contraction over k, run on the matrix cores.  A
-// 64 x 64 output tile per 256-lane workgroup, 32 x 32 per wave as 2 x 2 MFMA
+// 64 x 128 output tile per 256-lane workgroup, 32 x 64 per wave as 2 x 4 MFMA
 // blocks of 16 x 16 x 4: per step of four k, each lane supplies one element
-// of A = U diag(dsigma) (row l mod 16, column k0 + l / 16) and of B = V^T (row
-// k0 + l / 16, column l mod 16) per block, i.e. 16 consecutive rows of a
-// column of U or V per quarter wave.  Out-of-range rows, columns and k read a
-// clamped element and contribute zero.  Result element (i, j) of a block sits
-// in lane j + 16 (i mod 4), register i / 4 for binary64 and in lane
-// j + 16 (i / 4), register i mod 4 for binary32 (as the instructions lay
-// them out on gfx950).
+// of A = U diag(dsigma) (row l mod 16, column k0 + l / 16) per row block and
+// one of B = V^T (row k0 + l / 16, column l mod 16) per column block, i.e. 16
+// consecutive rows of a column of U or V per quarter wave; the eight products
+// of a step share those six operands (the diagonal scaling goes to the side
+// with fewer blocks).  Rows and columns past the matrix read row or column
+// n - 1 and feed only outputs that are not stored; k past the matrix
+// contributes zero.  Result element (i, j) of a block sits in lane
+// j + 16 (i mod 4), register i / 4 for binary64 and in lane j + 16 (i / 4),
+// register i mod 4 for binary32 (as the instructions lay them out on gfx950).
 
 template <class R> struct Mfma;
 template <> struct Mfma<double> {
@@ -1443,32 +1445,15 @@ template <> struct Mfma<float> {
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-// the operands of one step of four k: A = U diag(dsigma) at rows ra, rb and
-// B = V^T at columns ca, cb, zero outside the matrix
-template <class R> struct SgOps {
-  R a0, a1, b0, b1;
-};
-template <class R>
-__device__ inline SgOps<R> sg_load(const R *Um, const R *Vm, const R *dsm, int n, int k,
-                                   int ra, int rb, int ca, int cb, bool ia, bool ib, bool ja,
-                                   bool jb) {
-  bool kin = k < n;
-  int ks = kin ? k : n - 1;
-  const R *uk = Um + (int64_t)ks * n, *vk = Vm + (int64_t)ks * n;
-  R s = dsm[ks];
-  R u0 = uk[ra], u1 = uk[rb], v0 = vk[ca], v1 = vk[cb];
-  SgOps<R> o;
-  o.a0 = (kin && ia) ? u0 * s : (R)0;
-  o.a1 = (kin && ib) ? u1 * s : (R)0;
-  o.b0 = (kin && ja) ? v0 : (R)0;
-  o.b1 = (kin && jb) ? v1 : (R)0;
-  return o;
-}
+constexpr int kSgWR = 2, kSgWC = 4;                   // 16 x 16 blocks per wave
+constexpr int kSgTR = 32 * kSgWR, kSgTC = 32 * kSgWC;  // workgroup tile (2 x 2 waves)
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so the
 // 1-D grid is read as b = x + 8 j (x = b mod 8 the XCD): XCD x takes matrices
 // x, x + 8, ..., tile after tile, and the tiles of one matrix, which share
 // its U and V panels, meet in one L2.  tpm = tiles per matrix of the largest.
+// Every output element accumulates its k in ascending order, four per
+// instruction, whatever the tile shape.
 template <class R>
 __global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, int64_t nmat, int tpm,
                                                     const R *U, const R *V, const R *ds, R *dG) {
@@ -1478,42 +1463,83 @@ __global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, int64_t nmat, i
   if (m >= nmat) return;
   int t = (int)(j % tpm);
   int n = d.n[m];
-  int tiles = (n + 63) / 64;
-  if (t >= tiles * tiles) return;
+  int tr = (n + kSgTR - 1) / kSgTR, tc = (n + kSgTC - 1) / kSgTC;
+  if (t >= tr * tc) return;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int r0 = (t % tiles) * 64 + (w & 1) * 32, c0 = (t / tiles) * 64 + (w >> 1) * 32;
+  int r0 = (t % tr) * kSgTR + (w & 1) * 16 * kSgWR, c0 = (t / tr) * kSgTC + (w >> 1) * 16 * kSgWC;
   if (r0 >= n || c0 >= n) return;  // the whole wave is outside the matrix
   int64_t o = d.off[m];
   const R *Um = U + o, *Vm = V + o, *dsm = ds + d.soff[m];
   const int li = lane & 15, lk = lane >> 4;
-  int ra = r0 + li, rb = r0 + 16 + li, ca = c0 + li, cb = c0 + 16 + li;
-  bool ia = ra < n, ib = rb < n, ja = ca < n, jb = cb < n;
-  ra = ia ? ra : n - 1;
-  rb = ib ? rb : n - 1;
-  ca = ja ? ca : n - 1;
-  cb = jb ? cb : n - 1;
-  v4 acc00 = v4{0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-  // software pipeline: the operands of step k0 + 4 are loaded before the
-  // matrix instructions of step k0 are issued
-  SgOps<R> cur = sg_load(Um, Vm, dsm, n, lk, ra, rb, ca, cb, ia, ib, ja, jb);
-  for (int k0 = 0; k0 < n; k0 += 4) {
-    SgOps<R> nxt = sg_load(Um, Vm, dsm, n, k0 + 4 + lk, ra, rb, ca, cb, ia, ib, ja, jb);
-    acc00 = Mfma<R>::mma(cur.a0, cur.b0, acc00);
-    acc01 = Mfma<R>::mma(cur.a0, cur.b1, acc01);
-    acc10 = Mfma<R>::mma(cur.a1, cur.b0, acc10);
-    acc11 = Mfma<R>::mma(cur.a1, cur.b1, acc11);
-    cur = nxt;
+  // element indices within the matrix (at most 2^26 of them, so byte offsets
+  // fit 32 bits and every load is a scalar base plus one 32-bit offset)
+  uint32_t ra[kSgWR], cb[kSgWC];
+#pragma unroll
+  for (int x = 0; x < kSgWR; ++x) ra[x] = (uint32_t)min(r0 + 16 * x + li, n - 1);
+#pragma unroll
+  for (int y = 0; y < kSgWC; ++y) cb[y] = (uint32_t)min(c0 + 16 * y + li, n - 1);
+  const uint32_t col = (uint32_t)n;
+  auto at = [](const R *base, uint32_t idx) {
+    return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) +
+                                        (size_t)(idx * (uint32_t)sizeof(R)));
+  };
+  v4 acc[kSgWR][kSgWC];
+#pragma unroll
+  for (int x = 0; x < kSgWR; ++x)
+#pragma unroll
+    for (int y = 0; y < kSgWC; ++y) acc[x][y] = v4{0, 0, 0, 0};
+  // the operands of the four k of one step; `masked` for the steps that may
+  // reach past the matrix
+  auto load = [&](int k, bool masked, R *a, R *bv) {
+    const bool kin = !masked || k < n;
+    const uint32_t ks = (uint32_t)(kin ? k : n - 1), kc = ks * col;
+    const R s = at(dsm, ks);
+#pragma unroll
+    for (int x = 0; x < kSgWR; ++x) {
+      const R u = at(Um, kc + ra[x]);
+      a[x] = kin ? u * s : (R)0;
+    }
+#pragma unroll
+    for (int y = 0; y < kSgWC; ++y) {
+      const R v = at(Vm, kc + cb[y]);
+      bv[y] = kin ? v : (R)0;
+    }
+  };
+  R a[kSgWR], bv[kSgWC];
+  // one step: issue the matrix instructions of the operands in hand, then take
+  // the next step's operands, which were loaded before them
+  auto step = [&](const R *na, const R *nb) {
+#pragma unroll
+    for (int x = 0; x < kSgWR; ++x)
+#pragma unroll
+      for (int y = 0; y < kSgWC; ++y) acc[x][y] = Mfma<R>::mma(a[x], bv[y], acc[x][y]);
+#pragma unroll
+    for (int x = 0; x < kSgWR; ++x) a[x] = na[x];
+#pragma unroll
+    for (int y = 0; y < kSgWC; ++y) bv[y] = nb[y];
+  };
+  load(lk, true, a, bv);
+  int k0 = 0;
+  // every k of step k0 + 4 lies inside the matrix while k0 + 8 <= n
+  for (; k0 + 8 <= n; k0 += 4) {
+    R na[kSgWR], nb[kSgWC];
+    load(k0 + 4 + lk, false, na, nb);
+    step(na, nb);
+  }
+  for (; k0 < n; k0 += 4) {
+    R na[kSgWR], nb[kSgWC];
+    load(k0 + 4 + lk, true, na, nb);
+    step(na, nb);
   }
   R *out = dG + o;
-  const v4 *accs[2][2] = {{&acc00, &acc01}, {&acc10, &acc11}};
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < kSgWR; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < kSgWC; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int r = r0 + 16 * x + Mfma<R>::row(lane, v), c = c0 + 16 * y + li;
-        if (r < n && c < n) out[r + (int64_t)c * n] = (*accs[x][y])[v];
+        if (r < n && c < n) out[r + (int64_t)c * n] = acc[x][y][v];
       }
 }
 
@@ -2105,6 +2131,12 @@ static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *o
     stot += n;
     maxn = std::max(maxn, n);
   }
+  const int tpm = ((maxn + kSgTR - 1) / kSgTR) * ((maxn + kSgTC - 1) / kSgTC);
+  const int64_t groups = (nmat + 7) / 8;
+  // one workgroup per tile and matrix slot; the grid's lanes must count in 32 bits
+  if (8 * groups * tpm > (int64_t)(UINT32_MAX / 256))
+    return fail(KSVD2_EINVAL, "%lld matrices of order up to %d are too many tiles for one call",
+                (long long)nmat, maxn);
   size_t need = align256(nmat * 4) + align256(nmat * 8) * 2;
   if (ws_bytes < need) return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   std::vector<unsigned char> host(need, 0);
@@ -2119,10 +2151,8 @@ static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *o
   d.n = reinterpret_cast<const int32_t *>(wsb + o_n);
   d.off = reinterpret_cast<const int64_t *>(wsb + o_off);
   d.soff = reinterpret_cast<const int64_t *>(wsb + o_soff);
-  int t = (maxn + 63) / 64;
-  int64_t groups = (nmat + 7) / 8;
-  hipLaunchKernelGGL(k_sigma_grad<R>, dim3((unsigned)(8 * groups * t * t)), dim3(256), 0, st, d,
-                     nmat, t * t, U, V, ds, dG);
+  hipLaunchKernelGGL(k_sigma_grad<R>, dim3((unsigned)(8 * groups * tpm)), dim3(256), 0, st, d,
+                     nmat, tpm, U, V, ds, dG);
   return launch_status("kog_sigma_grad launch");
 }
 
