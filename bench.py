@@ -622,6 +622,7 @@ PROFILE_WORKLOADS = """
                     and WRITE_SIZE should each read 1 GiB)
   sweep4            one persistent sweep of the 256 x (n=256) FP64 workload
   sweep4rr          the same with the round-robin ordering
+  sweep5 / sweep5f32  one persistent sweep of the 1,000 uneven orders 16-512 (FP64 / FP32)
   sgrad64 / sgrad32 the sigma-gradient U diag(dsigma) V^T of the 256 x (n=256) sweep
                     batch (FP64) or of the 1,000 uneven orders (FP32), after one sweep
 """
@@ -688,6 +689,13 @@ def profile_workload(w, reps):
         for _ in range(reps):
             sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="persistent",
                                ordering="round-robin" if w == "sweep4rr" else "modulus")
+    elif w in ("sweep5", "sweep5f32"):
+        from paper_2407_13116_amd import sweep as sw
+
+        dt = np.float64 if w == "sweep5" else np.float32
+        p = sw.Packed(inputs.sweep_uneven(dtype=dt), dtype=dt)
+        for _ in range(reps):
+            sw.kog_sweep_batch(p, max_sweeps=1, tol_factor=-1.0, mode="persistent")
     elif w in ("sgrad64", "sgrad32"):
         from paper_2407_13116_amd import sweep as sw
 

@@ -1417,17 +1417,17 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
 //
 // dG = U diag(dsigma) V^T per matrix (d sigma_i / dG = u_i v_i^T, summed with
 // weights dsigma_i): a dense contraction over k, run on the matrix cores.  A
-// 64 x 128 output tile per 256-lane workgroup, 32 x 64 per wave as 2 x 4 MFMA
+// 128 x 128 output tile per 256-lane workgroup, 64 x 64 per wave as 4 x 4 MFMA
 // blocks of 16 x 16 x 4: per step of four k, each lane supplies one element
 // of A = U diag(dsigma) (row l mod 16, column k0 + l / 16) per row block and
 // one of B = V^T (row k0 + l / 16, column l mod 16) per column block, i.e. 16
-// consecutive rows of a column of U or V per quarter wave; the eight products
-// of a step share those six operands (the diagonal scaling goes to the side
-// with fewer blocks).  Rows and columns past the matrix read row or column
-// n - 1 and feed only outputs that are not stored; k past the matrix
-// contributes zero.  Result element (i, j) of a block sits in lane
-// j + 16 (i mod 4), register i / 4 for binary64 and in lane j + 16 (i / 4),
-// register i mod 4 for binary32 (as the instructions lay them out on gfx950).
+// consecutive rows of a column of U or V per quarter wave; the sixteen
+// products of a step share those eight operands.  Rows and columns past the
+// matrix read row or column n - 1 and feed only outputs that are not stored;
+// k past the matrix contributes zero.  Result element (i, j) of a block sits
+// in lane j + 16 (i mod 4), register i / 4 for binary64 and in lane
+// j + 16 (i / 4), register i mod 4 for binary32 (as the instructions lay them
+// out on gfx950).
 
 template <class R> struct Mfma;
 template <> struct Mfma<double> {
@@ -1445,26 +1445,26 @@ template <> struct Mfma<float> {
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-constexpr int kSgWR = 2, kSgWC = 4;                   // 16 x 16 blocks per wave
+constexpr int kSgWR = 4, kSgWC = 4;                   // 16 x 16 blocks per wave
 constexpr int kSgTR = 32 * kSgWR, kSgTC = 32 * kSgWC;  // workgroup tile (2 x 2 waves)
 
-// Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so the
-// 1-D grid is read as b = x + 8 j (x = b mod 8 the XCD): XCD x takes matrices
-// x, x + 8, ..., tile after tile, and the tiles of one matrix, which share
-// its U and V panels, meet in one L2.  tpm = tiles per matrix of the largest.
-// Every output element accumulates its k in ascending order, four per
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so
+// workgroup b runs on XCD b mod 8.  The host deals the matrices to the XCDs,
+// largest first, each to the XCD with the least work so far, and lists each
+// XCD's tiles matrix by matrix, largest matrices first: sched[b] = (matrix,
+// tile) of workgroup b, or matrix -1 where an XCD's list is shorter than the
+// longest.  The tiles of one matrix, which share its U and V panels, meet in
+// one L2.  Every output element accumulates its k in ascending order, four per
 // instruction, whatever the tile shape.
 template <class R>
-__global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, int64_t nmat, int tpm,
+__global__ __launch_bounds__(256) void k_sigma_grad(SweepDesc d, const int2 *sched,
                                                     const R *U, const R *V, const R *ds, R *dG) {
   typedef typename Mfma<R>::v4 v4;
-  int64_t b = blockIdx.x, j = b >> 3;
-  int64_t m = (b & 7) + 8 * (j / tpm);
-  if (m >= nmat) return;
-  int t = (int)(j % tpm);
+  const int2 e = sched[blockIdx.x];
+  if (e.x < 0) return;  // padding of a shorter XCD list
+  const int m = e.x, t = e.y;
   int n = d.n[m];
-  int tr = (n + kSgTR - 1) / kSgTR, tc = (n + kSgTC - 1) / kSgTC;
-  if (t >= tr * tc) return;
+  int tr = (n + kSgTR - 1) / kSgTR;
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int r0 = (t % tr) * kSgTR + (w & 1) * 16 * kSgWR, c0 = (t / tr) * kSgTC + (w >> 1) * 16 * kSgWC;
   if (r0 >= n || c0 >= n) return;  // the whole wave is outside the matrix
@@ -2131,19 +2131,37 @@ static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *o
     stot += n;
     maxn = std::max(maxn, n);
   }
-  const int tpm = ((maxn + kSgTR - 1) / kSgTR) * ((maxn + kSgTC - 1) / kSgTC);
-  const int64_t groups = (nmat + 7) / 8;
-  // one workgroup per tile and matrix slot; the grid's lanes must count in 32 bits
-  if (8 * groups * tpm > (int64_t)(UINT32_MAX / 256))
+  // the workgroup schedule: matrices by decreasing order, each dealt to the
+  // XCD with the least work so far (work of a tile ~ n)
+  std::vector<int> ord(nmat);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return n_host[x] > n_host[y]; });
+  std::vector<std::vector<int2>> bins(8);
+  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int m : ord) {
+    const int n = n_host[m];
+    const int tl = ((n + kSgTR - 1) / kSgTR) * ((n + kSgTC - 1) / kSgTC);
+    const int x = (int)(std::min_element(load, load + 8) - load);
+    for (int t = 0; t < tl; ++t) bins[x].push_back(make_int2(m, t));
+    load[x] += (double)tl * n;
+  }
+  size_t longest = 0;
+  for (auto &v : bins) longest = std::max(longest, v.size());
+  const size_t nwg = 8 * longest;
+  if (nwg > (size_t)(UINT32_MAX / 256))
     return fail(KSVD2_EINVAL, "%lld matrices of order up to %d are too many tiles for one call",
                 (long long)nmat, maxn);
-  size_t need = align256(nmat * 4) + align256(nmat * 8) * 2;
+  size_t o_n = 0, o_off = align256(nmat * 4), o_soff = o_off + align256(nmat * 8);
+  size_t o_sched = o_soff + align256(nmat * 8);
+  size_t need = o_sched + align256(nwg * sizeof(int2));
   if (ws_bytes < need) return fail(KSVD2_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   std::vector<unsigned char> host(need, 0);
-  size_t o_n = 0, o_off = align256(nmat * 4), o_soff = o_off + align256(nmat * 8);
   std::memcpy(host.data() + o_n, n_host, nmat * 4);
   std::memcpy(host.data() + o_off, off_host, nmat * 8);
   std::memcpy(host.data() + o_soff, soff.data(), nmat * 8);
+  int2 *sc = reinterpret_cast<int2 *>(host.data() + o_sched);
+  for (size_t j = 0; j < longest; ++j)
+    for (int x = 0; x < 8; ++x) sc[8 * j + x] = j < bins[x].size() ? bins[x][j] : make_int2(-1, 0);
   unsigned char *wsb = static_cast<unsigned char *>(ws);
   hipError_t e = hipMemcpyAsync(wsb, host.data(), need, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(KSVD2_EHIP, "descriptor upload: %s", hipGetErrorString(e));
@@ -2151,8 +2169,8 @@ static int sigma_grad_impl(int64_t nmat, const int32_t *n_host, const int64_t *o
   d.n = reinterpret_cast<const int32_t *>(wsb + o_n);
   d.off = reinterpret_cast<const int64_t *>(wsb + o_off);
   d.soff = reinterpret_cast<const int64_t *>(wsb + o_soff);
-  hipLaunchKernelGGL(k_sigma_grad<R>, dim3((unsigned)(8 * groups * tpm)), dim3(256), 0, st, d,
-                     nmat, tpm, U, V, ds, dG);
+  hipLaunchKernelGGL(k_sigma_grad<R>, dim3((unsigned)nwg), dim3(256), 0, st, d,
+                     reinterpret_cast<const int2 *>(wsb + o_sched), U, V, ds, dG);
   return launch_status("kog_sigma_grad launch");
 }
 
@@ -2215,16 +2233,19 @@ extern "C" {
 
 size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host) {
   if (nmat <= 0 || !n_host || (dtype != 0 && dtype != 1)) return 0;
-  int64_t npiv = 0, nsq = 0;
+  int64_t npiv = 0, nsq = 0, tiles = 0;
   for (int64_t m = 0; m < nmat; ++m) {
     int64_t nm = std::max(n_host[m], 0);
     npiv += nm / 2;
     nsq += nm * nm;
+    tiles += ((nm + kSgTR - 1) / kSgTR) * ((nm + kSgTC - 1) / kSgTC);
   }
   // every mode, ordering and tuning: the longest chunk, the pair table and a
   // second buffer for every matrix
   size_t a = ws_layout(nmat, npiv, kChunk, true, nsq, dtype ? 8 : 4).total;
-  size_t b = align256(nmat * 4) + align256(nmat * 8) * 2;
+  // kog_sigma_grad: the descriptors and its workgroup schedule (at most eight
+  // lists as long as all the tiles together)
+  size_t b = align256(nmat * 4) + align256(nmat * 8) * 2 + align256((size_t)tiles * 8 * 8);
   return std::max(a, b);
 }
 
