@@ -10,8 +10,10 @@
   one (1,000 orders 16..512, FP64 and FP32) in the launch configuration the benchmark
   times; sampled matrices recomputed by the oracle with the same number of sweeps, bit for
   bit.
-* The sigma gradient dG = U diag(dsigma) V^T: against float64 numpy, and against central
-  differences of sorted sigma through the GPU sweep.
+* The sigma gradient dG = U diag(dsigma) V^T: against float64 numpy, against central
+  differences of sorted sigma through the GPU sweep, and the contraction alone on general
+  U and V of orders 1..300 (ragged tiles, several matrices per XCD) within its rounding
+  bound.
 * Resuming (accumulate): 1 + 1 sweeps equal 2 sweeps bitwise; edge cases (order 2,
   diagonal and zero matrices).
 * Orderings: every case above runs the default modified modulus ordering; the
@@ -230,6 +232,36 @@ def test_sigma_gradient(dtype):
     for k, n in enumerate(ns):
         want = Us[k].astype(np.float64) @ np.diag(dsn[k].astype(np.float64)) @ Vs[k].astype(np.float64).T
         assert np.max(np.abs(dGs[k] - want)) <= 4 * n * eps * np.max(np.abs(dsn[k])) * 4
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_sigma_gradient_tiles_and_schedule(dtype):
+    """The contraction U diag(dsigma) V^T itself, on general (not orthogonal) U and V:
+    orders from 1 to 300 (odd ones too, ragged 128 x 128 workgroup tiles and 64 x 64 wave
+    tiles, k not a multiple of 4), more matrices than XCDs and in no order of size, so the
+    host's largest-first schedule deals several matrices to one XCD.  Every element
+    against float64 numpy within the dot product's rounding bound: n + 1 roundings
+    (the products u_ik dsigma_k, then the sum) of the absolute terms."""
+    import torch
+
+    from paper_2407_13116_amd import sweep as sw
+
+    rng = np.random.default_rng(31)
+    ns = [1, 3, 5, 17, 64, 127, 128, 129, 200, 257, 300, 2, 66, 131, 4, 255, 96, 33]
+    Um = [np.asfortranarray(rng.standard_normal((n, n)).astype(dtype)) for n in ns]
+    Vm = [np.asfortranarray(rng.standard_normal((n, n)).astype(dtype)) for n in ns]
+    pu, pv = sw.Packed(Um, dtype=dtype), sw.Packed(Vm, dtype=dtype)
+    ds_h = rng.standard_normal(int(pu.n.sum())).astype(dtype)
+    dG = sw.sigma_grad(pu, pu.G, pv.G, torch.from_numpy(ds_h).cuda())
+    torch.cuda.synchronize()
+    got = pu.unpack(dG)
+    dsn = pu.unpack_sigma(torch.from_numpy(ds_h))
+    eps = 2.0 ** (-53 if dtype == np.float64 else -24)
+    for k, n in enumerate(ns):
+        U64, V64, d64 = Um[k].astype(np.float64), Vm[k].astype(np.float64), dsn[k].astype(np.float64)
+        want = (U64 * d64) @ V64.T
+        bound = (n + 1) * eps * (np.abs(U64 * d64) @ np.abs(V64).T) * 1.01 + 1e-300
+        assert np.all(np.abs(got[k].astype(np.float64) - want) <= bound), n
 
 
 def test_sigma_gradient_fd():
