@@ -126,3 +126,26 @@ def test_sweep_tuning_table(L):
     finally:
         L.kog_sweep_reset_tuning()
 
+
+
+def test_sigma_grad_arguments_rejected(L):
+    """kog_sigma_grad: argument errors before any device work (no GPU needed), and the
+    workspace size function covers its descriptor and workgroup schedule."""
+    import numpy as np
+
+    n = np.array([4, 0], dtype=np.int32)
+    off = np.array([0, 16], dtype=np.int64)
+    p = ctypes.c_void_p(256)
+    args = lambda nn, ws_bytes, dtype=1, nmat=2: (dtype, nmat, nn.ctypes.data_as(ctypes.c_void_p),
+                                                  off.ctypes.data_as(ctypes.c_void_p), p, p, p, p,
+                                                  p, ws_bytes, None)
+    assert L.kog_sigma_grad(*args(n, 1 << 20)) == -1                  # order 0
+    assert b"order" in L.ksvd2_last_error()
+    assert L.kog_sigma_grad(*args(n, 1 << 20, nmat=-1)) == -1
+    assert L.kog_sigma_grad(*args(n, 1 << 20, nmat=0)) == 0           # empty: no-op
+    assert L.kog_sigma_grad(*args(n, 1 << 20, dtype=3)) == -2
+    n2 = np.array([4, 300], dtype=np.int32)
+    assert L.kog_sigma_grad(*args(n2, 64)) == -4                      # workspace too small
+    need = L.kog_sweep_workspace_size(1, 2, n2.ctypes.data_as(ctypes.c_void_p))
+    # descriptor (n, off, soff) and the schedule: at most 8 lists of all 1 + 9 tiles
+    assert need >= 256 * 3 + 8 * 8 * 10
