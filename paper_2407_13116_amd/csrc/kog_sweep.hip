@@ -905,13 +905,14 @@ __device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab
 }
 
 // wave rotation by one lane (lane l receives lane l - 1's value, lane 0 lane
-// 63's) and a read of one lane's value; every lane active
+// 63's) and a read of one lane's value; every lane active (every lane has a
+// source, so no previous value of the destination is kept)
 __device__ inline float lane_ror(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x13c, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x13c, 0xf, 0xf, true));
 }
 __device__ inline double lane_ror(double x) {
-  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x13c, 0xf, 0xf, false);
-  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x13c, 0xf, 0xf, false);
+  int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x13c, 0xf, 0xf, true);
+  int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x13c, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 __device__ inline float lane_read(float x, int l) {
@@ -940,8 +941,8 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
   const R *S2 = tab + (size_t)((k + 1) & cm) * kPivComp * np + comp * np;
   const int wl = (np - 1) & 63, ws = (np - 1) >> 6;  // lane and slot of slot np - 1
   int ia[S], ib[S], i2[S], j2[S];
-  bool aip[S], rai[S];
-  R a11[S], a21[S], a12[S], a22[S], b11[S], b21[S], b12[S], b22[S];
+  bool rai[S];
+  R pA1[S], pA2[S], pB1[S], pB2[S], b11[S], b21[S], b12[S], b22[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int p = lane + 64 * s;
@@ -950,17 +951,21 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
     int A, B, Aq, Bq;
     mm_ab(m, c, ps, A, B, ord);
     mm_ab(m, c, ps == 0 ? np - 1 : ps - 1, Aq, Bq, ord);
-    aip[s] = A < B;
+    const bool aip = A < B;
     rai[s] = A < Bq;
     ia[s] = ok ? min(A, B) : n;  // the step-k pair (i, j) of slot p
     ib[s] = ok ? max(A, B) : n;
     i2[s] = ok ? min(A, Bq) : n;
     j2[s] = ok ? max(A, Bq) : n;
     const int q2 = ps == 0 ? 0 : np - ps;
-    a11[s] = S1[ps];
-    a21[s] = S1[np + ps];
-    a12[s] = S1[2 * np + ps];
-    a22[s] = S1[3 * np + ps];
+    // step k: row A of the pair takes the rotation's first output when A < B,
+    // else its second (choosing the coefficients once per pass is the same
+    // operation, on the same operands, as choosing between the two outputs)
+    const R a11 = S1[ps], a21 = S1[np + ps], a12 = S1[2 * np + ps], a22 = S1[3 * np + ps];
+    pA1[s] = aip ? a11 : a12;
+    pA2[s] = aip ? a21 : a22;
+    pB1[s] = aip ? a12 : a11;
+    pB2[s] = aip ? a22 : a21;
     b11[s] = S2[q2];
     b21[s] = S2[np + q2];
     b12[s] = S2[2 * np + q2];
@@ -977,10 +982,8 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
     R nA[S], nB[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const R xi = xa[s], xj = xb[s];
-      const R ni = lin(a11[s], xi, a21[s], xj), nj = lin(a12[s], xi, a22[s], xj);
-      nA[s] = aip[s] ? ni : nj;
-      nB[s] = aip[s] ? nj : ni;
+      nA[s] = lin(pA1[s], xa[s], pA2[s], xb[s]);
+      nB[s] = lin(pB1[s], xa[s], pB2[s], xb[s]);
     }
     // the B element of slot np - 1 (lane wl, slot ws) for lane 0's first pair
     R wsel = nB[0];
