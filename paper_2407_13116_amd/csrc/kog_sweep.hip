@@ -453,16 +453,25 @@ __device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R 
 // wave-uniform (column) part; an offset at or past the end (kOff) reads zero
 // and stores nothing, without a memory access.  The descriptor's last word
 // (kBufWord3) selects 32-bit raw data access on this GPU family; the range is
-// the matrix's size in bytes, with no stride.
+// the matrix's size in bytes, with no stride.  The base and size are the same
+// in every lane; taking them from the first lane says so to the compiler,
+// which otherwise wraps every access in a loop over distinct descriptors when
+// it cannot prove that (the two G buffers of a pass swap roles every pass).
 constexpr int kOff = 0x40000000;
 constexpr int kBufWord3 = 0x00020000;
+template <class T> __device__ inline T *wave_uniform(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
 template <class R> struct Buf;
 template <> struct Buf<double> {
   typedef unsigned int V __attribute__((ext_vector_type(2)));
   __amdgpu_buffer_rsrc_t r;
   __device__ Buf(const double *p, int bytes)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, bytes,
-                                            kBufWord3)) {}
+      : r(__builtin_amdgcn_make_buffer_rsrc(wave_uniform(const_cast<double *>(p)), (short)0,
+                                            __builtin_amdgcn_readfirstlane(bytes), kBufWord3)) {}
   __device__ double ld(int vo, int so) const {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
@@ -473,8 +482,8 @@ template <> struct Buf<double> {
 template <> struct Buf<float> {
   __amdgpu_buffer_rsrc_t r;
   __device__ Buf(const float *p, int bytes)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, bytes,
-                                            kBufWord3)) {}
+      : r(__builtin_amdgcn_make_buffer_rsrc(wave_uniform(const_cast<float *>(p)), (short)0,
+                                            __builtin_amdgcn_readfirstlane(bytes), kBufWord3)) {}
   __device__ float ld(int vo, int so) const {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
