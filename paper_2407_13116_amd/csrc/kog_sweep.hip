@@ -860,8 +860,9 @@ template <class R, int D = 8> __device__ void tile_store(const R *T, R *M, int n
 // last pivot rotates the padding column n of the tile (never copied back), so
 // the loop body has no branches
 template <class R, int NG>
-__device__ void tile_rotate_ng(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv,
-                               int ord, int cm, const int16_t *ptab) {
+__device__ __attribute__((always_inline)) void tile_rotate_ng(R *T, int n, int nr, int k0, int k1,
+                                                               const R *tab, bool isv, int ord,
+                                                               int cm, const int16_t *ptab) {
   const int ldt = n + 1;
   const int np = n >> 1;
   const int lane = threadIdx.x & 63;
@@ -941,8 +942,9 @@ __device__ inline double lane_read(double x, int l) {
 // is read and written once per two steps.  Slots past np use the padding
 // column n, which is never copied back.
 template <class R, int S>
-__device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool isv, int cm,
-                                 int ord) {
+__device__ __attribute__((always_inline)) void tile_rotate_pair(R *T, int n, int nr, int k,
+                                                                 const R *tab, bool isv, int cm,
+                                                                 int ord) {
   const int ldt = n + 1, np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int comp = isv ? C_V11 : C_U11;
@@ -1013,10 +1015,13 @@ __device__ void tile_rotate_pair(R *T, int n, int nr, int k, const R *tab, bool 
 }
 
 // kPairs: take consecutive steps of the modified modulus ordering in pairs
-// (orders up to 256; the register budget of workgroups of up to 512 lanes)
+// (orders up to 256; the register budget of workgroups of up to 512 lanes).
+// The rotations are inlined into their kernels, whose compiler then knows the
+// tile is in LDS (an outlined copy would reach it through generic addresses).
 template <class R, bool kPairs = true>
-__device__ void tile_rotate(R *T, int n, int nr, int k0, int k1, const R *tab, bool isv, int ord,
-                            int cm, const int16_t *ptab) {
+__device__ __attribute__((always_inline)) void tile_rotate(R *T, int n, int nr, int k0, int k1,
+                                                            const R *tab, bool isv, int ord,
+                                                            int cm, const int16_t *ptab) {
   if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
   const int np = n >> 1;
   if (kPairs && ord != 2 && n >= 4 && np <= 128) {

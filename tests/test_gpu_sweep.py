@@ -495,13 +495,14 @@ def test_two_step_passes_every_block_size(orc, dtype):
     """The persistent kernel at every workgroup size (in place for orders up to 256
     in workgroups of up to 512 lanes, through the second buffer otherwise, paired U/V
     rotations or not): orders at the boundaries of the lane layouts (n/2 = 2, 3, 63,
-    64, 65, 128, 129), bit for bit against the oracle over a sweep and a half."""
+    64, 65, 128, 129, 192, 193, 256), bit for bit against the oracle over a sweep and
+    a half."""
     import torch
 
     from paper_2407_13116_amd import sweep as sw
 
     tdt = torch.float64 if dtype == np.float64 else torch.float32
-    ns = [4, 6, 126, 128, 130, 256, 258, 202]
+    ns = [4, 6, 126, 128, 130, 256, 258, 202, 384, 386, 512]
     mats = _mats(np.random.default_rng(44), ns, dtype)
     ref = [orc.kog_sweep(G0, max_sweeps=2, tol_factor=-1.0) for G0 in mats]
     try:
