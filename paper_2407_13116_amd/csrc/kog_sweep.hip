@@ -1045,10 +1045,15 @@ __device__ __attribute__((always_inline)) void tile_rotate(R *T, int n, int nr, 
     }
     return;
   }
+  // binary32 lanes take up to four pivots per pass when there are more than 128
+  // (one round of parameter loads per step instead of two); binary64 stays at two,
+  // whose registers the 1,024-lane kernels already need for their other phases
   if (np <= 64)
     tile_rotate_ng<R, 1>(T, n, nr, k0, k1, tab, isv, ord, cm, ptab);
-  else
+  else if (np <= 128 || sizeof(R) == 8)
     tile_rotate_ng<R, 2>(T, n, nr, k0, k1, tab, isv, ord, cm, ptab);
+  else
+    tile_rotate_ng<R, 4>(T, n, nr, k0, k1, tab, isv, ord, cm, ptab);
 }
 
 // Fixed-order sum of squares (in binary64) of G's entries (or of its off-
