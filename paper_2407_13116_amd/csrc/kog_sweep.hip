@@ -1299,7 +1299,8 @@ __global__ __launch_bounds__(kRed) void k_sw_finish(SweepDesc d, R *G, R *sigma,
 //
 // One workgroup per matrix (the launch covers the matrices listed in `mats`,
 // longest first).  LDS holds the reduction buffer, the pivot parameters of
-// one or two steps and the pair table, and the U/V row tile; G stays in
+// one or two steps and the pair table, and the U/V row tile (which during a
+// U/V update also spreads over the parameters and the pair table); G stays in
 // global memory (two steps at a time go from G to a second buffer in the
 // workspace and back); the chunk's rotation table is in the workspace.
 
@@ -1339,7 +1340,19 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
   R *Gm = G + o, *Um = U + o, *Vm = V + o;
   R *tab = par + d.chunk * d.poff[m] * kPivComp;
   const int cm = d.chunk - 1;
-  int rows = min(n, tile_elems / (n + 1));
+  // the U/V tiles also take the LDS of the step parameters and the pair list,
+  // which no phase reads across a U/V update (each step writes them afresh)
+  R *Tuv = reinterpret_cast<R *>(smem + kRed * sizeof(double));
+  const int uv_elems =
+      tile_elems +
+      (int)((persistent_fixed_lds<R>(maxn, two != 0) - kRed * sizeof(double)) / sizeof(R));
+  // U/V tiles of equal height, as few as fit, rounded up to a whole number of
+  // rows per wave when that still fits
+  const int rows_max = min(n, uv_elems / (n + 1));
+  const int ntl = (n + rows_max - 1) / rows_max;
+  int rows = (n + ntl - 1) / ntl;
+  if ((rows + BS / 64 - 1) / (BS / 64) * (BS / 64) <= rows_max)
+    rows = (rows + BS / 64 - 1) / (BS / 64) * (BS / 64);
   int sg, nt;
   double fro2 = init_matrix(Gm, Um, Vm, n, accumulate != 0, red, sg, nt);
   const double nsc = ldexp(1.0, -nt);
@@ -1417,11 +1430,11 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
           R *M = side ? Vm : Um;
           for (int r0 = 0; r0 < n; r0 += rows) {
             int nr = min(rows, n - r0);
-            tile_load<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
+            tile_load<R, (BS >= 1024 ? 4 : 8)>(Tuv, M, n, r0, nr);
             __syncthreads();
-            tile_rotate<R, (BS <= 512)>(T, n, nr, k0, kl, tab, side != 0, d.ord, cm, ptab);
+            tile_rotate<R, (BS <= 512)>(Tuv, n, nr, k0, kl, tab, side != 0, d.ord, cm, ptab);
             __syncthreads();
-            tile_store<R, (BS >= 1024 ? 4 : 8)>(T, M, n, r0, nr);
+            tile_store<R, (BS >= 1024 ? 4 : 8)>(Tuv, M, n, r0, nr);
             __syncthreads();
           }
         }
