@@ -378,9 +378,11 @@ size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);
  *   KOG_TUNE_INPLACE (3) 1 (default): that pass in place for orders up to 256
  *                        in workgroups of up to 512 lanes; 0: through the
  *                        second buffer
- *   KOG_TUNE_ROWS    (4) at most this many U/V tile rows in LDS (0, the
- *                        default: as many as fit), which leaves LDS for more
- *                        workgroups per compute unit
+ *   KOG_TUNE_ROWS    (4) size the U/V tile's own LDS for at most this many
+ *                        rows of the largest order (0, the default: as many as
+ *                        fit), which leaves LDS for more workgroups per compute
+ *                        unit; a U/V update also spreads over the LDS of the
+ *                        step parameters
  * kog_sweep_set_tuning sets `knob` of `bucket` (-1: of every bucket) and returns
  * KSVD2_EINVAL for a value out of range; kog_sweep_get_tuning returns the entry
  * (or a negative status); kog_sweep_reset_tuning restores the defaults;

@@ -5,7 +5,7 @@ that bucket's matrices and search the schedule knobs of the library's tuning tab
 one after the other (coordinate descent from the defaults): the workgroup size
 (waves per matrix), two steps of G per pass or one, the in-place form of that pass
 or the second buffer, the number of steps whose U/V rotations are applied together
-(the chunk) and a cap on the U/V tile rows held in LDS.  No setting changes a bit of
+(the chunk) and a cap on the LDS of the U/V tile.  No setting changes a bit of
 the results (every one performs the same operations in the same order), so the
 fastest is kept and installed (kog_sweep_set_tuning).  Results are cached in a JSON
 file keyed by device name, dtype and bucket, so a later process reuses them without

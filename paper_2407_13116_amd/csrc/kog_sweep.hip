@@ -1671,8 +1671,10 @@ static WsLayout ws_layout(int64_t nmat, int64_t npiv, int chunk, bool pairs, int
 //            entry of the bucket of its largest order
 //   two      two steps of G per pass under the modified modulus ordering
 //   inplace  the in-place form of that pass (orders up to 256, up to 512 lanes)
-//   rows     at most this many U/V tile rows in LDS (0: as many as fit); fewer
-//            rows leave LDS for a second workgroup on a compute unit
+//   rows     the U/V tile's own LDS for at most this many rows of the largest
+//            order (0: as many as fit); fewer rows leave LDS for a second
+//            workgroup on a compute unit (a U/V update also spreads over the
+//            step parameters' LDS)
 enum Knob { K_BLOCK = 0, K_CHUNK = 1, K_TWO = 2, K_INPLACE = 3, K_ROWS = 4, K_NKNOB = 5 };
 struct Tune {
   int v[2][5][K_NKNOB];
