@@ -368,7 +368,8 @@ size_t kog_sweep_workspace_size(int dtype, int64_t nmat, const int32_t *n_host);
  * Process-wide; set by the autotuner.  Results do not depend on it: every
  * setting performs the same arithmetic in the same order.  Knobs:
  *   KOG_TUNE_BLOCK   (0) lanes per workgroup (one workgroup per matrix): 256,
- *                        512 or 1024; defaults 256, 512, 512, 1024, 1024
+ *                        512 or 1024; defaults 256, 512, 512, 512, 1024
+ *                        (binary64) and 256, 512, 512, 1024, 1024 (binary32)
  *   KOG_TUNE_CHUNK   (1) steps whose U/V rotations are applied together, a
  *                        power of two in [2, 128] (default 128); a call uses
  *                        the entry of the bucket of its largest order; it sets

@@ -28,13 +28,15 @@ SEARCH = (("block", (256, 512, 1024)),
           ("inplace", (1, 0)),
           ("chunk", (128, 64, 32, 16)),
           ("rows", (0, 64, 32, 16)))
-DEFAULTS = {"block": (256, 512, 512, 1024, 1024), "chunk": 128, "two": 1, "inplace": 1,
+# the library's defaults (binary64 takes 512 lanes for orders 257-512, binary32 1,024)
+DEFAULTS = {"block": {"f64": (256, 512, 512, 512, 1024), "f32": (256, 512, 512, 1024, 1024)},
+            "chunk": 128, "two": 1, "inplace": 1,
             "rows": 0}
 CANDIDATES = SEARCH[0][1]
 CACHE = os.environ.get("KSVD2_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
 BUCKET_EDGES = (64, 128, 256, 512)
-_VERSION = 2   # cache entries of other versions are re-tuned
+_VERSION = 3   # cache entries of other versions are re-tuned
 
 
 def bucket_of(n: int) -> int:
@@ -59,9 +61,9 @@ def _save(tab):
     os.replace(tmp, CACHE)
 
 
-def _default(bucket):
+def _default(bucket, dtype):
     d = {k: v for k, v in DEFAULTS.items() if k != "block"}
-    d["block"] = DEFAULTS["block"][bucket]
+    d["block"] = DEFAULTS["block"]["f64" if dtype == torch.float64 else "f32"][bucket]
     return d
 
 
@@ -87,7 +89,7 @@ def _search(mats, dtype, bucket, ordering):
     """Coordinate descent over SEARCH from the defaults; returns (setting, times)."""
     p = sw.Packed(mats, dtype=np.float64 if dtype == torch.float64 else np.float32)
     G0 = p.G.clone()
-    cur = _default(bucket)
+    cur = _default(bucket, dtype)
     times = {}
     t_cur = _time_setting(p, G0, dtype, bucket, cur, ordering)
     times[json.dumps(cur, sort_keys=True)] = t_cur
@@ -125,7 +127,7 @@ def tune(mats, dtype=torch.float64, sample: int = 64, force: bool = False, verbo
             pick = [ms[i] for i in rng.choice(len(ms), min(sample, len(ms)), replace=False)]
             setting, t_best, times = _search(pick, dtype, b, ordering)
             tab[key] = {"version": _VERSION, "setting": setting, "ms": t_best,
-                        "ms_default": times[json.dumps(_default(b), sort_keys=True)],
+                        "ms_default": times[json.dumps(_default(b, dtype), sort_keys=True)],
                         "tried": len(times), "sample": len(pick)}
             if verbose:
                 print(f"[autotune] {key}: {setting} {t_best:.3f} ms "

@@ -318,7 +318,8 @@ __device__ inline void g_diag_store(R *G, int n, int i, int j, const R *S, int n
 // Gin and writes G (the same buffer, or another one of the same layout: every
 // element is written).
 template <class R, int BS, int D>
-__device__ void g_step_block(const R *Gin, R *G, int n, const R *S, const int16_t *pr) {
+__device__ __attribute__((always_inline)) void g_step_block(const R *Gin, R *G, int n, const R *S,
+                                                             const int16_t *pr) {
   const int np = n >> 1;
   const int dp = BS % np, dq = BS / np;
   // block w = p + q np, walked with stride BS by carries
@@ -422,8 +423,9 @@ __device__ inline Wab<R> blk_after(const R *S, int np, int p, int q, bool aip, b
 // and of B_(d-1) (slot d - 1), and its off-diagonal elements in the step-k
 // blocks (d, d-1) and (d-1, d).  Parameters to S2 (LDS) and slot2 (table).
 template <class R, int BS>
-__device__ void g_pivots_next(const R *Gin, int n, int k, const R *S1, R *S2, R *slot2,
-                              int ord) {
+__device__ __attribute__((always_inline)) void g_pivots_next(const R *Gin, int n, int k,
+                                                              const R *S1, R *S2, R *slot2,
+                                                              int ord) {
   const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   for (int dd = threadIdx.x; dd < np; dd += BS) {
     const int dm = dd == 0 ? np - 1 : dd - 1;
@@ -516,8 +518,8 @@ __device__ inline double lane_up(double x) {
 // selection, inactive lanes load and store nothing through the buffer's
 // range check.
 template <class R, int BS, int kAhead>
-__device__ void g_fused_pair(const R *Gin, R *G, int n, int k, const R *S1, const R *S2,
-                             int ord) {
+__device__ __attribute__((always_inline)) void g_fused_pair(const R *Gin, R *G, int n, int k,
+                                                             const R *S1, const R *S2, int ord) {
   constexpr int NW = BS / 64;
   constexpr int W = (int)sizeof(R);
   const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
@@ -642,7 +644,8 @@ __device__ inline FusedGeo fused_geo(int n, int nw, int snap_elems) {
 
 // columns A and B of each boundary slot (the pre-step slot of each segment)
 template <class R, int BS>
-__device__ void g_fused_snapshot(const R *G, int n, int k, FusedGeo g, R *snap, int ord) {
+__device__ __attribute__((always_inline)) void g_fused_snapshot(const R *G, int n, int k,
+                                                                 FusedGeo g, R *snap, int ord) {
   const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
   for (int x = threadIdx.x; x < g.cs * 2 * n; x += BS) {
     const int sg = x / (2 * n), r = x - sg * 2 * n, side = r / n, row = r - side * n;
@@ -655,8 +658,9 @@ __device__ void g_fused_snapshot(const R *G, int n, int k, FusedGeo g, R *snap, 
 }
 
 template <class R, int BS, int S>
-__device__ void g_fused_inplace(R *G, int n, int k, const R *S1, const R *S2, FusedGeo g,
-                                const R *snap, int ord) {
+__device__ __attribute__((always_inline)) void g_fused_inplace(R *G, int n, int k, const R *S1,
+                                                                const R *S2, FusedGeo g,
+                                                                const R *snap, int ord) {
   constexpr int W = (int)sizeof(R);
   constexpr int kAhead = 4 / S;
   const int np = n >> 1, m = n - 1, c = mm_center(n, k, ord);
@@ -1014,25 +1018,28 @@ __device__ __attribute__((always_inline)) void tile_rotate_pair(R *T, int n, int
   }
 }
 
-// kPairs: take consecutive steps of the modified modulus ordering in pairs
-// (orders up to 256; the register budget of workgroups of up to 512 lanes).
-// The rotations are inlined into their kernels, whose compiler then knows the
-// tile is in LDS (an outlined copy would reach it through generic addresses).
-template <class R, bool kPairs = true>
+// PS: take consecutive steps of the modified modulus ordering in pairs with up
+// to PS slots per lane (0: never; 2: orders up to 256; 4: up to 512), as the
+// register budget of the calling kernel allows.  The rotations are inlined
+// into their kernels, whose compiler then knows the tile is in LDS (an
+// outlined copy would reach it through generic addresses).
+template <class R, int PS>
 __device__ __attribute__((always_inline)) void tile_rotate(R *T, int n, int nr, int k0, int k1,
                                                             const R *tab, bool isv, int ord,
                                                             int cm, const int16_t *ptab) {
   if ((int)(threadIdx.x >> 6) >= nr) return;  // more waves than rows: this wave has none
   const int np = n >> 1;
-  if (kPairs && ord != 2 && n >= 4 && np <= 128) {
+  if (PS > 0 && ord != 2 && n >= 4 && np <= 64 * PS) {
     // consecutive steps in pairs (the rows of a wave are its own: a wave
     // barrier orders one pass after the previous)
     int k = k0;
     for (; k + 1 <= k1; k += 2) {
       if (np <= 64)
         tile_rotate_pair<R, 1>(T, n, nr, k, tab, isv, cm, ord);
-      else
+      else if (PS < 4 || np <= 128)
         tile_rotate_pair<R, 2>(T, n, nr, k, tab, isv, cm, ord);
+      else
+        tile_rotate_pair<R, (PS < 4 ? 2 : 4)>(T, n, nr, k, tab, isv, cm, ord);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1040,8 +1047,10 @@ __device__ __attribute__((always_inline)) void tile_rotate(R *T, int n, int nr, 
     if (k <= k1) {
       if (np <= 64)
         tile_rotate_ng<R, 1>(T, n, nr, k, k, tab, isv, ord, cm, ptab);
-      else
+      else if (PS < 4 || np <= 128 || sizeof(R) == 8)
         tile_rotate_ng<R, 2>(T, n, nr, k, k, tab, isv, ord, cm, ptab);
+      else
+        tile_rotate_ng<R, (PS < 4 ? 2 : 4)>(T, n, nr, k, k, tab, isv, ord, cm, ptab);
     }
     return;
   }
@@ -1268,7 +1277,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_sw_apply(SweepDesc d, R *U, R *
   R *M = (blockIdx.y ? V : U) + d.off[m];
   tile_load(T, M, n, r0, nr);
   __syncthreads();
-  tile_rotate<R, false>(T, n, nr, k0, k1, par + d.chunk * d.poff[m] * kPivComp, blockIdx.y != 0,
+  tile_rotate<R, 0>(T, n, nr, k0, k1, par + d.chunk * d.poff[m] * kPivComp, blockIdx.y != 0,
                         d.ord, d.chunk - 1, d.pairs + 2 * d.chunk * d.poff[m]);
   __syncthreads();
   tile_store(T, M, n, r0, nr);
@@ -1319,7 +1328,10 @@ template <class R> __host__ __device__ inline size_t persistent_fixed_lds(int ma
   return (b + 15) & ~(size_t)15;
 }
 
-template <class R, int BS>
+// PS: pair slots per lane of the U/V rotations (see tile_rotate); the host takes
+// 4 only for launches with orders above 256, so that the kernels of smaller
+// orders keep the register allocation of 2
+template <class R, int BS, int PS>
 __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t *mats, R *G,
                                                       R *U, R *V, R *par, R *sigma,
                                                       int32_t *sweeps_out, int max_sweeps,
@@ -1432,7 +1444,7 @@ __global__ __launch_bounds__(BS) void k_sw_persistent(SweepDesc d, const int32_t
             int nr = min(rows, n - r0);
             tile_load<R, (BS >= 1024 ? 4 : 8)>(Tuv, M, n, r0, nr);
             __syncthreads();
-            tile_rotate<R, (BS <= 512)>(Tuv, n, nr, k0, kl, tab, side != 0, d.ord, cm, ptab);
+            tile_rotate<R, PS>(Tuv, n, nr, k0, kl, tab, side != 0, d.ord, cm, ptab);
             __syncthreads();
             tile_store<R, (BS >= 1024 ? 4 : 8)>(Tuv, M, n, r0, nr);
             __syncthreads();
@@ -1681,10 +1693,12 @@ struct Tune {
 };
 static Tune default_tune() {
   Tune t;
-  const int blocks[5] = {256, 512, 512, 1024, 1024};
+  // binary64 orders 257-512 take 512 lanes (four pair slots per lane in the U/V
+  // rotations), binary32 ones 1,024 (measured on the uneven batch)
+  const int blocks[2][5] = {{256, 512, 512, 1024, 1024}, {256, 512, 512, 512, 1024}};
   for (int d = 0; d < 2; ++d)
     for (int b = 0; b < 5; ++b) {
-      t.v[d][b][K_BLOCK] = blocks[b];
+      t.v[d][b][K_BLOCK] = blocks[d][b];
       t.v[d][b][K_CHUNK] = kChunk;
       t.v[d][b][K_TWO] = 1;
       t.v[d][b][K_INPLACE] = 1;
@@ -1762,8 +1776,8 @@ template <class R> static size_t persistent_lds(int maxn, size_t limit, bool all
   return 0;
 }
 
-template <class R, int BS> static void set_lds_attr(size_t lds) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sw_persistent<R, BS>),
+template <class R, int BS, int PS> static void set_lds_attr(size_t lds) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sw_persistent<R, BS, PS>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -1876,20 +1890,28 @@ static int launch_persistent(const SweepDesc &d, const int32_t *mats_dev, const 
   const unsigned cnt = (unsigned)s.count;
   switch (s.block) {
     case 256:
-      set_lds_attr<R, 256>(s.lds);
-      hipLaunchKernelGGL((k_sw_persistent<R, 256>), dim3(cnt), dim3(256), s.lds, st, d,
+      set_lds_attr<R, 256, 2>(s.lds);
+      hipLaunchKernelGGL((k_sw_persistent<R, 256, 2>), dim3(cnt), dim3(256), s.lds, st, d,
                          mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
                          accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
       break;
     case 512:
-      set_lds_attr<R, 512>(s.lds);
-      hipLaunchKernelGGL((k_sw_persistent<R, 512>), dim3(cnt), dim3(512), s.lds, st, d,
-                         mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
-                         accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
+      // four pair slots per lane only where an order above 256 needs them
+      if (s.maxn > 256) {
+        set_lds_attr<R, 512, 4>(s.lds);
+        hipLaunchKernelGGL((k_sw_persistent<R, 512, 4>), dim3(cnt), dim3(512), s.lds, st, d,
+                           mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
+                           accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
+      } else {
+        set_lds_attr<R, 512, 2>(s.lds);
+        hipLaunchKernelGGL((k_sw_persistent<R, 512, 2>), dim3(cnt), dim3(512), s.lds, st, d,
+                           mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
+                           accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
+      }
       break;
     case 1024:
-      set_lds_attr<R, 1024>(s.lds);
-      hipLaunchKernelGGL((k_sw_persistent<R, 1024>), dim3(cnt), dim3(1024), s.lds, st, d,
+      set_lds_attr<R, 1024, 0>(s.lds);
+      hipLaunchKernelGGL((k_sw_persistent<R, 1024, 0>), dim3(cnt), dim3(1024), s.lds, st, d,
                          mats_dev, G, U, V, par, sigma, sweeps_out, max_sweeps, tolf,
                          accumulate, s.maxn, s.tile_elems, s.two, s.inplace_ok);
       break;

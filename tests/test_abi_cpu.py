@@ -106,7 +106,8 @@ def test_sweep_tuning_table(L):
     """The tuning knobs: defaults, per-bucket and all-bucket settings, range checks."""
     try:
         assert L.kog_sweep_reset_tuning() == 0
-        assert [L.kog_sweep_get_tuning(1, b, 0) for b in range(5)] == [256, 512, 512, 1024, 1024]
+        assert [L.kog_sweep_get_tuning(1, b, 0) for b in range(5)] == [256, 512, 512, 512, 1024]
+        assert [L.kog_sweep_get_tuning(0, b, 0) for b in range(5)] == [256, 512, 512, 1024, 1024]
         assert L.kog_sweep_get_tuning(0, 2, 1) == 128                  # chunk
         assert L.kog_sweep_get_tuning(0, 2, 2) == 1 and L.kog_sweep_get_tuning(0, 2, 3) == 1
         assert L.kog_sweep_get_tuning(0, 2, 4) == 0                    # rows: as many as fit

@@ -516,8 +516,7 @@ def test_two_step_passes_every_block_size(orc, dtype):
                 assert _same(got["U"][k], U), (block, ns[k], "U")
                 assert _same(got["V"][k], V), (block, ns[k], "V")
     finally:
-        for bucket, block in enumerate((256, 512, 512, 1024, 1024)):
-            sw.set_tuning(tdt, bucket, block)
+        sw.reset_tuning()
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
