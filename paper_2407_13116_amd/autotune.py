@@ -1,7 +1,9 @@
 """Autotuner of the persistent sweep kernels.
 
 For each (dtype, order bucket) present in a batch, time one sweep of a sample of
-that bucket's matrices and search the schedule knobs of the library's tuning table
+that bucket's matrices (up to 512: a workgroup per matrix, so a sample that keeps the
+256 compute units busy, as the whole batch does; smaller samples favoured wider
+workgroups) and search the schedule knobs of the library's tuning table
 one after the other (coordinate descent from the defaults): the workgroup size
 (waves per matrix), two steps of G per pass or one, the in-place form of that pass
 or the second buffer, the number of steps whose U/V rotations are applied together
@@ -36,7 +38,7 @@ CANDIDATES = SEARCH[0][1]
 CACHE = os.environ.get("KSVD2_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
 BUCKET_EDGES = (64, 128, 256, 512)
-_VERSION = 3   # cache entries of other versions are re-tuned
+_VERSION = 4   # cache entries of other versions are re-tuned
 
 
 def bucket_of(n: int) -> int:
@@ -107,7 +109,7 @@ def _search(mats, dtype, bucket, ordering):
     return cur, t_cur, times
 
 
-def tune(mats, dtype=torch.float64, sample: int = 64, force: bool = False, verbose=False,
+def tune(mats, dtype=torch.float64, sample: int = 512, force: bool = False, verbose=False,
          ordering="modulus"):
     """Tune every bucket present in `mats` (list of square numpy matrices); returns
     {bucket: setting} with the knobs installed."""
