@@ -129,6 +129,25 @@ def test_sweep_tuning_table(L):
 
 
 
+
+def test_autotuner_starts_from_the_library_defaults(L):
+    """The autotuner's starting point per dtype and order bucket is the library's own
+    default schedule (its search and its 'ms_default' figure assume so)."""
+    import torch
+
+    from paper_2407_13116_amd import autotune
+
+    knobs = {"block": 0, "chunk": 1, "two": 2, "inplace": 3, "rows": 4}
+    try:
+        assert L.kog_sweep_reset_tuning() == 0
+        for dt, tdt in ((1, torch.float64), (0, torch.float32)):
+            for b in range(5):
+                want = autotune._default(b, tdt)
+                got = {k: L.kog_sweep_get_tuning(dt, b, v) for k, v in knobs.items()}
+                assert got == want, (dt, b, got, want)
+    finally:
+        L.kog_sweep_reset_tuning()
+
 def test_sigma_grad_arguments_rejected(L):
     """kog_sigma_grad: argument errors before any device work (no GPU needed), and the
     workspace size function covers its descriptor and workgroup schedule."""
