@@ -128,8 +128,6 @@ def test_sweep_tuning_table(L):
         L.kog_sweep_reset_tuning()
 
 
-
-
 def test_autotuner_starts_from_the_library_defaults(L):
     """The autotuner's starting point per dtype and order bucket is the library's own
     default schedule (its search and its 'ms_default' figure assume so)."""
