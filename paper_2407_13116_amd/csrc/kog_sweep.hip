@@ -21,10 +21,12 @@
 // kChunk consecutive steps are kept in a table, and U and V are brought up to
 // date once per chunk, a tile of rows at a time in LDS.  Each row of U or V
 // receives exactly the same rotations in the same order as with per-step
-// updates; deferring changes the memory traffic, not a single bit.  Under the
-// modified modulus ordering the persistent modes also update G two steps per
-// pass (the pairs of consecutive steps interlock; see g_fused_pair), again with
-// the same operations on every element.
+// updates; deferring changes the memory traffic, not a single bit.  Under both
+// cyclic orderings (round-robin is the modified modulus ordering with its
+// indices relabeled) the persistent modes also update G two steps per pass
+// (the pairs of consecutive steps interlock; see g_fused_pair) and rotate the
+// U/V tiles two steps per LDS pass (tile_rotate_pair), again with the same
+// operations on every element.
 //
 // Executions of exactly the same arithmetic:
 //   mode 0  plain per-step launches: a pivot kernel and a G kernel per step,
